@@ -1,0 +1,121 @@
+// Host-side launchers of the HIP kernels (implemented in the .hip files).
+// Every launcher enqueues on ctx.stream and never synchronises.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "hm_common.hpp"
+
+namespace hm {
+
+// Per-right-hand-side GMRES(3) state kept on the device between the passes of
+// one smoothing step.
+struct GmState {
+    double beta;          // ||r0||
+    double s[4];          // 1 / ||z_j||: the stored Arnoldi vectors are unnormalised
+    double hr[4][3];      // Hessenberg matrix, real part
+    double hi[4][3];      // Hessenberg matrix, imaginary part
+    double yr[3], yi[3];  // least-squares solution times s_i (update weights)
+    int k;                // Arnoldi columns in use (0: r0 = 0, nothing to do)
+    int arnoldi_done;     // 1 after breakdown or the last column
+};
+
+// Per-right-hand-side norms read by the host.
+struct RhsNorms {
+    double f2;   // ||f_s||^2
+    double r2;   // latest ||f_s - A_s x||^2
+};
+
+// Shared launch parameters of one batched call.
+struct LaunchCtx {
+    hipStream_t stream;
+    int nrhs;              // batch size (grid z)
+    const int* active;     // [nrhs] device flags; 0 skips that right-hand side
+    double* partials;      // reduction scratch [nrhs][max_blocks][8]
+    unsigned* counters;    // [nrhs] zeroed completion counters
+    long long max_blocks;  // capacity of `partials` per right-hand side
+    int rpt;               // rows per thread of the level kernels
+};
+
+// The operator of one level: analytic on level 0 (from k^2), stored Galerkin
+// stencil planes of radius `radius` on coarser levels.
+template <typename T>
+struct LevelOp {
+    int level;
+    Grid g;
+    int radius;
+    const cplx<T>* coef;  // [(2r+1)^2][plane], levels >= 1
+    const T* k2;          // padded k^2 plane, level 0
+    double h;
+};
+
+// Vectors of one level in the padded layout: `count` consecutive planes.
+template <typename T>
+struct Vec {
+    cplx<T>* p;
+    long long plane;
+    __host__ __device__ cplx<T>* rhs(int b) const { return p + b * plane; }
+};
+
+template <typename T> void launch_apply(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> y);
+template <typename T> void launch_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> r);
+template <typename T>
+void launch_jacobi(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
+template <typename T>
+void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc);
+template <typename T>
+void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
+
+// GMRES(3) passes (one smoothing step = residual, 3 x (apply, orth), update).
+template <typename T>
+void launch_gm_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> v0, GmState* st);
+template <typename T>
+void launch_gm_apply(const LaunchCtx&, const LevelOp<T>&, int j, Vec<T> V, Vec<T> w, GmState* st);
+template <typename T>
+void launch_gm_orth(const LaunchCtx&, Grid g, int j, Vec<T> V, Vec<T> w, GmState* st, double breakdown);
+template <typename T> void launch_gm_update(const LaunchCtx&, Grid g, Vec<T> V, Vec<T> u, GmState* st);
+
+// ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
+template <typename T>
+void launch_resnorm(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, RhsNorms* norms);
+// ||f||^2 into norms[b].f2.
+template <typename T> void launch_norm(const LaunchCtx&, Grid g, Vec<T> f, RhsNorms* norms);
+
+// FP32-in-FP64 refinement: r = f - A_s x in FP64, stored as complex64, norm into norms[b].r2.
+void launch_refine_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x, Vec<double> f,
+                            Vec<float> r32, RhsNorms* norms);
+// x_out = x_in + e (e complex64), then r = f - A_s x_out as above.
+void launch_correct_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x_in, Vec<float> e,
+                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms);
+
+// Layout conversion between the caller's dense [b][n+1][n+1] arrays and the
+// padded planes. src_is_f32 / dst_is_f32 select complex64 on the caller side.
+// scale_w multiplies by W (rhs -> f_s); conj conjugates.
+template <typename T>
+void launch_copy_in(const LaunchCtx&, Grid g, const void* src, bool src_is_f32, Vec<T> dst, bool scale_w,
+                    bool conj);
+template <typename T>
+void launch_copy_out(const LaunchCtx&, Grid g, Vec<T> src, void* dst, bool dst_is_f32, bool scale_w, bool conj);
+template <typename T> void launch_zero(hipStream_t, cplx<T>* p, long long count);
+void launch_zero_real(hipStream_t, void* p, long long bytes);
+
+// Adjoint gradient: g_p = sum_b Re[mu_b,p W_p (1 + i s_p / (h k_p)) u_b,p], mu = conj(lambda).
+void launch_grad_k2(const LaunchCtx&, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,
+                    double* grad_k2_dense);
+
+// ---- setup ----
+// Padded k^2 planes from the caller's dense array (FP64 and optionally FP32).
+void launch_k2_in(hipStream_t, Grid g, const double* k2_dense, double* k2_64, float* k2_32);
+// Galerkin product of level l (fine) into level l+1 (coarse) in FP64.
+// Level 0 uses the shifted Laplacian built from k^2 (shift applied here only).
+void launch_galerkin(hipStream_t, int fine_level, Grid fine, int fine_radius, const cplx<double>* fine_coef,
+                     const double* k2_64, double h, double shift, int transfer, Grid coarse, int coarse_radius,
+                     cplx<double>* coarse_coef);
+void launch_cast_coef(hipStream_t, const cplx<double>* src, cplx<float>* dst, long long count);
+// Dense coarsest matrix [N][N] (N = (n_c+1)^2) from stencil planes, then LU with partial pivoting.
+void launch_dense_lu(hipStream_t, Grid g, int radius, const cplx<double>* coef, cplx<double>* dense, int* piv);
+// u = A^{-1} f on the coarsest grid with the stored LU (FP64 arithmetic).
+template <typename T>
+void launch_coarse_solve(const LaunchCtx&, Grid g, const cplx<double>* lu, const int* piv, Vec<T> f, Vec<T> u);
+// Stencil planes -> caller's dense [(2r+1)^2][n_l+1][n_l+1] complex128.
+void launch_stencil_out(hipStream_t, Grid g, int radius, const cplx<double>* coef, void* out);
+
+}  // namespace hm

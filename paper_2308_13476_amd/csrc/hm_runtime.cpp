@@ -1,0 +1,886 @@
+// Host runtime of the multigrid solver: workspace layout, hierarchy setup,
+// cycle scheduling and the C ABI declared in include/helmg.h.
+#include "helmg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hm_kernels.hpp"
+
+using namespace hm;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxCoarseNodes = 1089;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Grid make_grid(int n) {
+    Grid g;
+    g.n = n;
+    const int m = n + 1;
+    g.pitch = int(align_up(size_t(m + 2 * kGhost), 16));
+    g.plane = (long long)align_up(size_t(g.pitch) * size_t(m + 2 * kGhost), 64);
+    return g;
+}
+
+int next_radius(int r, int transfer) { return transfer == MG_TRANSFER_BEZIER ? (r + 4) / 2 : (r + 2) / 2; }
+
+int default_rpt(int n) {
+    if (const char* e = std::getenv("HELMG_RPT")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 64) return v;
+    }
+    return n >= 2048 ? 4 : n >= 512 ? 2 : 1;
+}
+
+long long blocks_per_rhs(const Grid& g, int rpt) {
+    const int r = (g.n + 1) < 256 ? 1 : rpt;
+    return (long long)((g.n + 1 + kBX - 1) / kBX) * ((g.n + 1 + kBY * r - 1) / (kBY * r));
+}
+
+struct LevelBuf {
+    Grid g;
+    int radius = 1;
+    cplx<double>* coef64 = nullptr;
+    cplx<float>* coef32 = nullptr;
+    // [max_batch] planes each; V holds 4 planes per right-hand side
+    cplx<double>* u64 = nullptr; cplx<double>* f64 = nullptr; cplx<double>* t64 = nullptr;
+    cplx<double>* w64 = nullptr; cplx<double>* V64 = nullptr;
+    cplx<float>* u32 = nullptr; cplx<float>* f32 = nullptr; cplx<float>* t32 = nullptr;
+    cplx<float>* w32 = nullptr; cplx<float>* V32 = nullptr;
+};
+
+// Sequential carve of the caller's workspace (base == nullptr only measures).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename P>
+    P* take(size_t bytes) {
+        off = align_up(off, kAlign);
+        P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+}  // namespace
+
+struct mg_ctx {
+    int n = 0, L = 0, transfer = 0, max_batch = 1, has32 = 0, coarsest_n = 4, rpt = 1;
+    double h = 0.0, shift = 0.0;
+    std::vector<LevelBuf> lv;
+    double* k2_64 = nullptr;
+    float* k2_32 = nullptr;
+    cplx<double>* dense = nullptr;
+    int* piv = nullptr;
+    GmState* gm = nullptr;
+    RhsNorms* norms = nullptr;
+    int* active = nullptr;
+    double* partials = nullptr;
+    unsigned* counters = nullptr;
+    long long max_blocks = 0;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    // host mirrors (pinned)
+    RhsNorms* h_norms = nullptr;
+    int* h_active = nullptr;
+    std::string err;
+    // kernel timing hook
+    int timing_class = 0;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_pending;
+    int t_launches = 0;
+    double t_ms = 0.0, t_nodes = 0.0;
+    // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
+    int cur_buf = 0;
+    std::vector<int> final_buf;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- layout plan
+bool levels_for(int n, int levels, int coarsest_n, int* L_out, std::string* why) {
+    if (n < 2) { *why = "n must be >= 2"; return false; }
+    int L = levels;
+    if (L <= 0) {
+        if (coarsest_n < 1) { *why = "coarsest_n must be >= 1"; return false; }
+        L = 1;
+        int m = n;
+        while (m > coarsest_n) {
+            if (m % 2) { *why = "n cannot be halved down to coarsest_n"; return false; }
+            m /= 2;
+            ++L;
+        }
+        if (m != coarsest_n) { *why = "n is not coarsest_n times a power of two"; return false; }
+    }
+    if (L < 2) { *why = "need at least two levels"; return false; }
+    if (L > 24 || n % (1 << (L - 1)) != 0) { *why = "n must be divisible by 2^(levels-1)"; return false; }
+    const int nc = n >> (L - 1);
+    if ((nc + 1) * (nc + 1) > kMaxCoarseNodes) { *why = "coarsest grid larger than 32 x 32 intervals"; return false; }
+    *L_out = L;
+    return true;
+}
+
+size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, int has32) {
+    Carver cv{base};
+    if (c) c->lv.assign(L, LevelBuf());
+    int r = 1;
+    long long max_blocks = 0;
+    const int rpt = default_rpt(n);
+    const size_t B = size_t(max_batch);
+    for (int l = 0; l < L; ++l) {
+        const Grid g = make_grid(n >> l);
+        LevelBuf tmp;
+        LevelBuf& lb = c ? c->lv[l] : tmp;
+        lb.g = g;
+        lb.radius = (l == 0) ? 1 : r;
+        const size_t pl = size_t(g.plane);
+        const size_t ncoef = size_t(2 * lb.radius + 1) * size_t(2 * lb.radius + 1);
+        if (l > 0) {
+            lb.coef64 = cv.take<cplx<double>>(ncoef * pl * 16);
+            if (has32) lb.coef32 = cv.take<cplx<float>>(ncoef * pl * 8);
+        }
+        lb.u64 = cv.take<cplx<double>>(B * pl * 16);
+        lb.f64 = cv.take<cplx<double>>(B * pl * 16);
+        lb.t64 = cv.take<cplx<double>>(B * pl * 16);
+        lb.w64 = cv.take<cplx<double>>(B * pl * 16);
+        lb.V64 = cv.take<cplx<double>>(4 * B * pl * 16);
+        if (has32) {
+            lb.u32 = cv.take<cplx<float>>(B * pl * 8);
+            lb.f32 = cv.take<cplx<float>>(B * pl * 8);
+            lb.t32 = cv.take<cplx<float>>(B * pl * 8);
+            lb.w32 = cv.take<cplx<float>>(B * pl * 8);
+            lb.V32 = cv.take<cplx<float>>(4 * B * pl * 8);
+        }
+        max_blocks = std::max(max_blocks, blocks_per_rhs(g, rpt));
+        r = next_radius(lb.radius, transfer);
+    }
+    const Grid g0 = make_grid(n);
+    double* k64 = cv.take<double>(size_t(g0.plane) * 8);
+    float* k32 = has32 ? cv.take<float>(size_t(g0.plane) * 4) : nullptr;
+    const int nc = n >> (L - 1);
+    const size_t Nc = size_t(nc + 1) * size_t(nc + 1);
+    cplx<double>* dense = cv.take<cplx<double>>(Nc * Nc * 16);
+    int* piv = cv.take<int>(Nc * 4);
+    GmState* gm = cv.take<GmState>(B * sizeof(GmState));
+    RhsNorms* norms = cv.take<RhsNorms>(B * sizeof(RhsNorms));
+    int* active = cv.take<int>(B * 4);
+    unsigned* counters = cv.take<unsigned>(B * 4);
+    double* partials = cv.take<double>(B * size_t(max_blocks) * 8 * 8);
+    if (c) {
+        c->k2_64 = k64;
+        c->k2_32 = k32;
+        c->dense = dense;
+        c->piv = piv;
+        c->gm = gm;
+        c->norms = norms;
+        c->active = active;
+        c->counters = counters;
+        c->partials = partials;
+        c->max_blocks = max_blocks;
+        c->rpt = rpt;
+    }
+    return align_up(cv.off, kAlign);
+}
+
+// ---------------------------------------------------------------- helpers
+#define HM_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            c->err = std::string(#call) + ": " + hipGetErrorString(e_);                 \
+            return MG_E_HIP;                                                             \
+        }                                                                                \
+    } while (0)
+
+mg_status check_launch(mg_ctx* c) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        c->err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return MG_E_HIP;
+    }
+    return MG_OK;
+}
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    static cplx<double>* u(LevelBuf& l) { return l.u64; }
+    static cplx<double>*& u_ref(LevelBuf& l) { return l.u64; }
+    static cplx<double>* f(LevelBuf& l) { return l.f64; }
+    static cplx<double>*& t_ref(LevelBuf& l) { return l.t64; }
+    static cplx<double>* w(LevelBuf& l) { return l.w64; }
+    static cplx<double>* V(LevelBuf& l) { return l.V64; }
+    static const cplx<double>* coef(const LevelBuf& l) { return l.coef64; }
+    static const double* k2(const mg_ctx* c) { return c->k2_64; }
+    static constexpr double breakdown = 1e-14;
+};
+template <> struct Prec<float> {
+    static cplx<float>* u(LevelBuf& l) { return l.u32; }
+    static cplx<float>*& u_ref(LevelBuf& l) { return l.u32; }
+    static cplx<float>* f(LevelBuf& l) { return l.f32; }
+    static cplx<float>*& t_ref(LevelBuf& l) { return l.t32; }
+    static cplx<float>* w(LevelBuf& l) { return l.w32; }
+    static cplx<float>* V(LevelBuf& l) { return l.V32; }
+    static const cplx<float>* coef(const LevelBuf& l) { return l.coef32; }
+    static const float* k2(const mg_ctx* c) { return c->k2_32; }
+    static constexpr double breakdown = 1e-6;
+};
+
+template <typename T>
+LevelOp<T> level_op(const mg_ctx* c, int l) {
+    const LevelBuf& lb = c->lv[l];
+    return LevelOp<T>{l, lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::k2(c), c->h};
+}
+
+template <typename T>
+Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
+
+LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
+    return LaunchCtx{s, nrhs, c->active, c->partials, c->counters, c->max_blocks, c->rpt};
+}
+
+// Timing hook: events around the launches of one kernel class.
+struct TimedScope {
+    mg_ctx* c;
+    hipStream_t s;
+    bool on;
+    int e0 = -1;
+    double nodes;
+    TimedScope(mg_ctx* c_, hipStream_t s_, int cls, double nodes_) : c(c_), s(s_), on(c_->timing_class == cls), nodes(nodes_) {
+        if (!on) return;
+        const size_t need = 2 * (c->ev_pending.size() + 1);
+        while (c->ev_pool.size() < need) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+            c->ev_pool.push_back(e);
+        }
+        e0 = int(2 * c->ev_pending.size());
+        (void)hipEventRecord(c->ev_pool[e0], s);
+    }
+    ~TimedScope() {
+        if (!on) return;
+        (void)hipEventRecord(c->ev_pool[e0 + 1], s);
+        c->ev_pending.push_back({e0, e0 + 1});
+        c->t_nodes += nodes;
+    }
+};
+
+void harvest_timing(mg_ctx* c) {
+    for (auto& pr : c->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]) == hipSuccess) {
+            c->t_ms += ms;
+            c->t_launches += 1;
+        }
+    }
+    c->ev_pending.clear();
+}
+
+// ---------------------------------------------------------------- cycle
+struct CycleParams {
+    int gamma, smoother, nu1, nu2;
+    double omega;
+};
+
+template <typename T>
+void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
+    LevelBuf& lb = c->lv[l];
+    const LevelOp<T> op = level_op<T>(c, l);
+    const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
+    if (cp.smoother == MG_JACOBI) {
+        {
+            TimedScope ts(c, lc.stream, l == 0 ? 2 : -1, nodes);
+            launch_jacobi<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
+                             vec<T>(Prec<T>::t_ref(lb), lb), 1.0 / cp.omega);
+        }
+        std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
+        if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
+        return;
+    }
+    Vec<T> V = vec<T>(Prec<T>::V(lb), lb);
+    Vec<T> W = vec<T>(Prec<T>::w(lb), lb);
+    launch_gm_residual<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), V, c->gm);
+    for (int j = 0; j < 3; ++j) {
+        {
+            TimedScope ts(c, lc.stream, l == 0 ? 1 : (l == 1 ? 4 : -1), nodes);
+            launch_gm_apply<T>(lc, op, j, V, W, c->gm);
+        }
+        launch_gm_orth<T>(lc, lb.g, j, V, W, c->gm, Prec<T>::breakdown);
+    }
+    launch_gm_update<T>(lc, lb.g, V, vec<T>(Prec<T>::u(lb), lb), c->gm);
+}
+
+template <typename T>
+void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
+    LevelBuf& lb = c->lv[l];
+    if (l == c->L - 1) {
+        launch_coarse_solve<T>(lc, lb.g, c->dense, c->piv, vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::u(lb), lb));
+        return;
+    }
+    LevelBuf& cb = c->lv[l + 1];
+    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp);
+    launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
+                       vec<T>(Prec<T>::w(lb), lb));
+    launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::f(cb), cb));
+    launch_zero<T>(lc.stream, Prec<T>::u(cb), cb.g.plane * lc.nrhs);
+    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp);
+    launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, vec<T>(Prec<T>::u(cb), cb), vec<T>(Prec<T>::u(lb), lb));
+    for (int s = 0; s < cp.nu2; ++s) smooth<T>(c, lc, l, cp);
+}
+
+// Zeroes every vector and coefficient plane (ghost frames must read zero).
+mg_status zero_workspace(mg_ctx* c, hipStream_t s) {
+    launch_zero_real(s, c->ws, (long long)(c->ws_bytes / 4 * 4));
+    return check_launch(c);
+}
+
+mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s) {
+    const Grid g0 = c->lv[0].g;
+    launch_k2_in(s, g0, k2, c->k2_64, c->k2_32);
+    for (int l = 0; l + 1 < c->L; ++l) {
+        const LevelBuf& f = c->lv[l];
+        LevelBuf& cc = c->lv[l + 1];
+        launch_galerkin(s, l, f.g, f.radius, f.coef64, c->k2_64, c->h, c->shift, c->transfer, cc.g, cc.radius,
+                        cc.coef64);
+        if (c->has32) {
+            const long long nc = (long long)(2 * cc.radius + 1) * (2 * cc.radius + 1) * cc.g.plane;
+            launch_cast_coef(s, cc.coef64, cc.coef32, nc);
+        }
+    }
+    const LevelBuf& lc = c->lv[c->L - 1];
+    launch_dense_lu(s, lc.g, lc.radius, lc.coef64, c->dense, c->piv);
+    return check_launch(c);
+}
+
+bool is_dev_ptr_ok(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % 8) == 0; }
+
+mg_solve_opts default_solve_opts() {
+    mg_solve_opts o;
+    o.nu_pre = 1;
+    o.nu_post = 1;
+    o.omega = 4.5;
+    o.max_cycles = 500;
+    o.precision = MG_FP64;
+    o.divergence = 1e8;
+    return o;
+}
+
+mg_status check_solve_args(mg_ctx* c, int nrhs, double tol, int cyc, int smoother, const mg_solve_opts& o) {
+    if (nrhs < 1 || nrhs > c->max_batch) { c->err = "nrhs must be in [1, max_batch]"; return MG_E_ARG; }
+    if (!(tol > 0.0)) { c->err = "tol must be > 0"; return MG_E_ARG; }
+    if (cyc != MG_V && cyc != MG_W) { c->err = "cycle must be MG_V or MG_W"; return MG_E_ARG; }
+    if (smoother != MG_JACOBI && smoother != MG_GMRES3) { c->err = "unknown smoother"; return MG_E_ARG; }
+    if (o.nu_pre < 0 || o.nu_post < 0 || o.nu_pre + o.nu_post > 64) { c->err = "nu out of range"; return MG_E_ARG; }
+    if (!(o.omega > 0.0)) { c->err = "omega must be > 0"; return MG_E_ARG; }
+    if (o.max_cycles < 1) { c->err = "max_cycles must be >= 1"; return MG_E_ARG; }
+    if (o.precision != MG_FP64 && o.precision != MG_FP32_REFINED) { c->err = "unknown precision"; return MG_E_ARG; }
+    if (o.precision == MG_FP32_REFINED && !c->has32) {
+        c->err = "handle was set up without FP32 copies";
+        return MG_E_STATE;
+    }
+    if (!(o.divergence > 1.0)) { c->err = "divergence factor must be > 1"; return MG_E_ARG; }
+    return MG_OK;
+}
+
+// Core solve of A_s x = f_s on level-0 buffers: f_s already in lv[0].f64, the
+// initial guess in lv[0].u64. Leaves every solution in lv[0].u64.
+mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, int smoother, const mg_solve_opts& o,
+                     mg_solve_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    LevelBuf& l0 = c->lv[0];
+    const CycleParams cp{cyc, smoother, o.nu_pre, o.nu_post, o.omega};
+    const bool fp32 = (o.precision == MG_FP32_REFINED);
+    const LevelOp<double> op0 = level_op<double>(c, 0);
+    c->cur_buf = 0;
+    c->final_buf.assign(nrhs, -1);
+    for (int b = 0; b < nrhs; ++b) c->h_active[b] = 1;
+    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    LaunchCtx lc = launch_ctx(c, s, nrhs);
+    launch_norm<double>(lc, l0.g, vec<double>(l0.f64, l0), c->norms);
+    if (fp32)
+        launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), vec<float>(l0.f32, l0),
+                               c->norms);
+    else
+        launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    std::vector<double> rel0(nrhs), rel(nrhs);
+    std::vector<int> cycles(nrhs, 0), state(nrhs, 0);  // state: 0 running, 1 converged, 2 diverged
+    int running = 0;
+    for (int b = 0; b < nrhs; ++b) {
+        const double f2 = c->h_norms[b].f2;
+        if (f2 == 0.0) {
+            // zero right-hand side: the solution is zero
+            launch_zero<double>(s, l0.u64 + (long long)b * l0.g.plane, l0.g.plane);
+            rel0[b] = rel[b] = 0.0;
+            state[b] = 1;
+        } else {
+            rel0[b] = rel[b] = std::sqrt(c->h_norms[b].r2 / f2);
+            if (!std::isfinite(rel0[b])) state[b] = 2;
+            else if (rel0[b] <= tol) state[b] = 1;
+        }
+        if (state[b] != 0) {
+            c->h_active[b] = 0;
+            c->final_buf[b] = 0;
+        } else {
+            ++running;
+        }
+    }
+    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    int it = 0;
+    while (running > 0 && it < o.max_cycles) {
+        ++it;
+        if (fp32) {
+            LevelBuf& lb = l0;
+            launch_zero<float>(s, lb.u32, lb.g.plane * nrhs);
+            cycle<float>(c, lc, 0, cp);
+            cplx<double>* xin = c->cur_buf == 0 ? l0.u64 : l0.t64;
+            cplx<double>* xout = c->cur_buf == 0 ? l0.t64 : l0.u64;
+            launch_correct_residual(lc, op0, vec<double>(xin, l0), vec<float>(lb.u32, lb), vec<double>(xout, l0),
+                                    vec<double>(l0.f64, l0), vec<float>(l0.f32, l0), c->norms);
+            c->cur_buf ^= 1;
+        } else {
+            cycle<double>(c, lc, 0, cp);
+            launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
+        }
+        if (mg_status st = check_launch(c)) return st;
+        HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+        HM_HIP(hipStreamSynchronize(s));
+        harvest_timing(c);
+        bool changed = false;
+        for (int b = 0; b < nrhs; ++b) {
+            if (state[b] != 0) {
+                if (stats && stats->history) stats->history[(size_t)(it - 1) * nrhs + b] = NAN;
+                continue;
+            }
+            const double r = std::sqrt(c->h_norms[b].r2 / c->h_norms[b].f2);
+            rel[b] = r;
+            cycles[b] = it;
+            if (stats && stats->history) stats->history[(size_t)(it - 1) * nrhs + b] = r;
+            int ns = 0;
+            if (!std::isfinite(r) || r > o.divergence * rel0[b]) ns = 2;
+            else if (r <= tol) ns = 1;
+            if (ns) {
+                state[b] = ns;
+                c->h_active[b] = 0;
+                c->final_buf[b] = c->cur_buf;
+                --running;
+                changed = true;
+            }
+        }
+        if (changed && running > 0)
+            HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    }
+    for (int b = 0; b < nrhs; ++b)
+        if (c->final_buf[b] < 0) c->final_buf[b] = c->cur_buf;
+    if (fp32) {
+        // buffer 0 = u64, buffer 1 = t64 (pointers never swapped in this path)
+        for (int b = 0; b < nrhs; ++b)
+            if (c->final_buf[b] == 1)
+                HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
+                                      size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
+    } else {
+        // Jacobi on level 0 swaps the u64 / t64 pointers (cur_buf counts the
+        // parity); a right-hand side that stopped at another parity than the
+        // current one has its iterate in t64 now.
+        for (int b = 0; b < nrhs; ++b)
+            if (c->final_buf[b] != c->cur_buf)
+                HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
+                                      size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
+    }
+    HM_HIP(hipStreamSynchronize(s));
+    mg_status result = MG_OK;
+    for (int b = 0; b < nrhs; ++b) {
+        if (state[b] == 2) result = MG_E_DIVERGED;
+        else if (state[b] == 0 && result == MG_OK) result = MG_NOT_CONVERGED;
+    }
+    if (stats) {
+        for (int b = 0; b < nrhs; ++b) {
+            if (stats->cycles) stats->cycles[b] = cycles[b];
+            if (stats->relres) stats->relres[b] = rel[b];
+        }
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (result == MG_E_DIVERGED) c->err = "residual diverged";
+    return result;
+}
+
+mg_status check_level(mg_ctx* c, int level, int precision, bool allow_last) {
+    if (level < 0 || level >= c->L || (!allow_last && level == c->L - 1)) {
+        c->err = "level out of range";
+        return MG_E_ARG;
+    }
+    if (precision != MG_FP64 && precision != MG_FP32_REFINED) { c->err = "unknown precision"; return MG_E_ARG; }
+    if (precision == MG_FP32_REFINED && !c->has32) { c->err = "no FP32 copies"; return MG_E_STATE; }
+    return MG_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+size_t mg_workspace_bytes(int n, int levels, int transfer, const mg_setup_opts* opts) {
+    const int max_batch = opts ? opts->max_batch : 1;
+    const int coarsest_n = (opts && opts->coarsest_n > 0) ? opts->coarsest_n : 4;
+    const int has32 = opts ? (opts->precision == MG_FP32_REFINED) : 0;
+    if (max_batch < 1 || (transfer != MG_TRANSFER_BEZIER && transfer != MG_TRANSFER_LINEAR)) return 0;
+    int L;
+    std::string why;
+    if (!levels_for(n, levels, coarsest_n, &L, &why)) return 0;
+    return carve(nullptr, nullptr, n, L, transfer, max_batch, has32);
+}
+
+mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, int transfer,
+                   const mg_setup_opts* opts, void* workspace, size_t ws_bytes, void* stream, mg_handle* out) {
+    if (!out) { g_setup_error = "out is NULL"; return MG_E_ARG; }
+    *out = nullptr;
+    const int max_batch = opts ? opts->max_batch : 1;
+    const int coarsest_n = (opts && opts->coarsest_n > 0) ? opts->coarsest_n : 4;
+    const int has32 = opts ? (opts->precision == MG_FP32_REFINED) : 0;
+    if (!is_dev_ptr_ok(k2)) { g_setup_error = "k2 is NULL or misaligned"; return MG_E_ARG; }
+    if (!(h > 0.0) || !std::isfinite(h)) { g_setup_error = "h must be > 0"; return MG_E_ARG; }
+    if (!(shift >= 0.0) || !std::isfinite(shift)) { g_setup_error = "shift must be >= 0"; return MG_E_ARG; }
+    if (transfer != MG_TRANSFER_BEZIER && transfer != MG_TRANSFER_LINEAR) { g_setup_error = "bad transfer"; return MG_E_ARG; }
+    if (max_batch < 1 || max_batch > 4096) { g_setup_error = "max_batch out of range"; return MG_E_ARG; }
+    if (opts && opts->precision != MG_FP64 && opts->precision != MG_FP32_REFINED) {
+        g_setup_error = "unknown precision";
+        return MG_E_ARG;
+    }
+    int L;
+    if (!levels_for(n, levels, coarsest_n, &L, &g_setup_error)) return MG_E_ARG;
+    const size_t need = carve(nullptr, nullptr, n, L, transfer, max_batch, has32);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) {
+        g_setup_error = "workspace is NULL or not 256-byte aligned";
+        return MG_E_WORKSPACE;
+    }
+    if (ws_bytes < need) {
+        g_setup_error = "workspace too small: need " + std::to_string(need) + " bytes";
+        return MG_E_WORKSPACE;
+    }
+    mg_ctx* c = new mg_ctx();
+    c->n = n;
+    c->L = L;
+    c->transfer = transfer;
+    c->max_batch = max_batch;
+    c->has32 = has32;
+    c->coarsest_n = coarsest_n;
+    c->h = h;
+    c->shift = shift;
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = need;
+    carve(c, c->ws, n, L, transfer, max_batch, has32);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_active), sizeof(int) * max_batch, hipHostMallocDefault) !=
+            hipSuccess) {
+        g_setup_error = "hipHostMalloc failed";
+        mg_destroy(c);
+        return MG_E_HIP;
+    }
+    mg_status st = zero_workspace(c, s);
+    if (st == MG_OK) st = build_hierarchy(c, k2, s);
+    if (st == MG_OK && hipStreamSynchronize(s) != hipSuccess) {
+        c->err = "setup synchronisation failed";
+        st = MG_E_HIP;
+    }
+    if (st != MG_OK) {
+        g_setup_error = c->err;
+        mg_destroy(c);
+        return st;
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_update_k2(mg_handle c, const double* k2, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (!is_dev_ptr_ok(k2)) { c->err = "k2 is NULL or misaligned"; return MG_E_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (mg_status st = build_hierarchy(c, k2, s)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+mg_status mg_solve(mg_handle c, const void* rhs, void* x, int nrhs, double tol, int cyc, int smoother,
+                   const mg_solve_opts* opts, mg_solve_stats* stats, void* stream) {
+    if (!c) return MG_E_ARG;
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    if (mg_status st = check_solve_args(c, nrhs, tol, cyc, smoother, o)) return st;
+    if (!is_dev_ptr_ok(rhs) || !is_dev_ptr_ok(x)) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LevelBuf& l0 = c->lv[0];
+    LaunchCtx lc = launch_ctx(c, s, nrhs);
+    lc.active = nullptr;
+    launch_copy_in<double>(lc, l0.g, rhs, false, vec<double>(l0.f64, l0), true, false);
+    launch_copy_in<double>(lc, l0.g, x, false, vec<double>(l0.u64, l0), false, false);
+    if (mg_status st = check_launch(c)) return st;
+    const mg_status res = solve_core(c, s, nrhs, tol, cyc, smoother, o, stats);
+    if (res == MG_E_HIP || res == MG_E_ARG) return res;
+    launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), x, false, false, false);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return res;
+}
+
+mg_status mg_grad(mg_handle c, const void* u, const void* grad_u, int nsrc, double tol, int cyc, int smoother,
+                  const mg_solve_opts* opts, double* grad_k2, void* grad_rhs, mg_solve_stats* stats, void* stream) {
+    if (!c) return MG_E_ARG;
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    if (mg_status st = check_solve_args(c, nsrc, tol, cyc, smoother, o)) return st;
+    if (!is_dev_ptr_ok(u) || !is_dev_ptr_ok(grad_u) || !is_dev_ptr_ok(grad_k2)) {
+        c->err = "u / grad_u / grad_k2 NULL or misaligned";
+        return MG_E_ARG;
+    }
+    if (grad_rhs && !is_dev_ptr_ok(grad_rhs)) { c->err = "grad_rhs misaligned"; return MG_E_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LevelBuf& l0 = c->lv[0];
+    LaunchCtx lc = launch_ctx(c, s, nsrc);
+    lc.active = nullptr;
+    // A_s^H lambda = g  <=>  A_s mu = conj(g), lambda = conj(mu)  (A_s complex symmetric)
+    launch_copy_in<double>(lc, l0.g, grad_u, false, vec<double>(l0.f64, l0), false, true);
+    launch_zero<double>(s, l0.u64, l0.g.plane * nsrc);
+    if (mg_status st = check_launch(c)) return st;
+    const mg_status res = solve_core(c, s, nsrc, tol, cyc, smoother, o, stats);
+    if (res == MG_E_HIP || res == MG_E_ARG) return res;
+    // forward solutions into the (idle) level-0 Arnoldi planes
+    launch_copy_in<double>(lc, l0.g, u, false, vec<double>(l0.V64, l0), false, false);
+    launch_grad_k2(lc, l0.g, c->h, c->k2_64, vec<double>(l0.V64, l0), vec<double>(l0.u64, l0), grad_k2);
+    if (grad_rhs) launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), grad_rhs, false, true, true);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return res;
+}
+
+mg_status mg_destroy(mg_handle c) {
+    if (!c) return MG_OK;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->h_norms) (void)hipHostFree(c->h_norms);
+    if (c->h_active) (void)hipHostFree(c->h_active);
+    delete c;
+    return MG_OK;
+}
+
+const char* mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "MG_OK";
+        case MG_NOT_CONVERGED: return "MG_NOT_CONVERGED";
+        case MG_E_ARG: return "MG_E_ARG";
+        case MG_E_HIP: return "MG_E_HIP";
+        case MG_E_DIVERGED: return "MG_E_DIVERGED";
+        case MG_E_WORKSPACE: return "MG_E_WORKSPACE";
+        case MG_E_STATE: return "MG_E_STATE";
+    }
+    return "unknown status";
+}
+
+const char* mg_last_error(mg_handle c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+mg_status mg_level_info(mg_handle c, int level, int* n_l, int* radius, int* levels) {
+    if (!c) return MG_E_ARG;
+    if (levels) *levels = c->L;
+    if (level < 0 || level >= c->L) { c->err = "level out of range"; return MG_E_ARG; }
+    if (n_l) *n_l = c->lv[level].g.n;
+    if (radius) *radius = c->lv[level].radius;
+    return MG_OK;
+}
+
+mg_status mg_get_stencil(mg_handle c, int level, void* out, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (level < 1 || level >= c->L) { c->err = "stencils exist on levels 1 .. L-1"; return MG_E_ARG; }
+    if (!is_dev_ptr_ok(out)) { c->err = "out NULL or misaligned"; return MG_E_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const LevelBuf& lb = c->lv[level];
+    launch_stencil_out(s, lb.g, lb.radius, lb.coef64, out);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+}  // extern "C"
+
+// Level operations run on the level's own buffers: inputs are copied in, the
+// step runs, outputs are copied out.
+namespace {
+template <typename T>
+mg_status level_op_run(mg_ctx* c, int kind, int level, const void* a, const void* b, void* out, int nvec,
+                       int smoother, int nsteps, double omega, hipStream_t s) {
+    LevelBuf& lb = c->lv[level];
+    const bool f32 = sizeof(T) == 4;
+    LaunchCtx lc = launch_ctx(c, s, nvec);
+    lc.active = nullptr;
+    auto V = [&](cplx<T>* p) { return vec<T>(p, lb); };
+    cplx<T>* U = Prec<T>::u(lb);
+    cplx<T>* F = Prec<T>::f(lb);
+    cplx<T>* Wv = Prec<T>::w(lb);
+    switch (kind) {
+        case 0:  // apply
+            launch_copy_in<T>(lc, lb.g, a, f32, V(U), false, false);
+            launch_apply<T>(lc, level_op<T>(c, level), V(U), V(Wv));
+            launch_copy_out<T>(lc, lb.g, V(Wv), out, f32, false, false);
+            break;
+        case 1:  // residual
+            launch_copy_in<T>(lc, lb.g, a, f32, V(U), false, false);
+            launch_copy_in<T>(lc, lb.g, b, f32, V(F), false, false);
+            launch_residual<T>(lc, level_op<T>(c, level), V(U), V(F), V(Wv));
+            launch_copy_out<T>(lc, lb.g, V(Wv), out, f32, false, false);
+            break;
+        case 2: {  // smooth
+            launch_copy_in<T>(lc, lb.g, out, f32, V(U), false, false);
+            launch_copy_in<T>(lc, lb.g, b, f32, V(F), false, false);
+            for (int i = 0; i < nvec; ++i) c->h_active[i] = 1;
+            HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+            lc.active = c->active;
+            const CycleParams cp{1, smoother, 0, 0, omega};
+            const int saved = c->cur_buf;
+            for (int k = 0; k < nsteps; ++k) smooth<T>(c, lc, level, cp);
+            c->cur_buf = saved;
+            launch_copy_out<T>(lc, lb.g, V(Prec<T>::u(lb)), out, f32, false, false);
+            break;
+        }
+        case 3: {  // restrict
+            LevelBuf& cb = c->lv[level + 1];
+            launch_copy_in<T>(lc, lb.g, a, f32, V(Wv), false, false);
+            launch_restrict<T>(lc, lb.g, cb.g, c->transfer, V(Wv), vec<T>(Prec<T>::f(cb), cb));
+            launch_copy_out<T>(lc, cb.g, vec<T>(Prec<T>::f(cb), cb), out, f32, false, false);
+            break;
+        }
+        case 4: {  // prolong-add
+            LevelBuf& cb = c->lv[level + 1];
+            launch_copy_in<T>(lc, cb.g, a, f32, vec<T>(Prec<T>::u(cb), cb), false, false);
+            launch_copy_in<T>(lc, lb.g, out, f32, V(U), false, false);
+            launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, vec<T>(Prec<T>::u(cb), cb), V(U));
+            launch_copy_out<T>(lc, lb.g, V(U), out, f32, false, false);
+            break;
+        }
+        case 5: {  // coarsest solve
+            launch_copy_in<T>(lc, lb.g, a, f32, V(F), false, false);
+            launch_coarse_solve<T>(lc, lb.g, c->dense, c->piv, V(F), V(U));
+            launch_copy_out<T>(lc, lb.g, V(U), out, f32, false, false);
+            break;
+        }
+    }
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+mg_status level_entry(mg_ctx* c, int kind, int level, const void* a, const void* b, void* out, int nvec,
+                      int precision, int smoother, int nsteps, double omega, void* stream) {
+    if (nvec < 1 || nvec > c->max_batch) { c->err = "nvec must be in [1, max_batch]"; return MG_E_ARG; }
+    if (precision == MG_FP64)
+        return level_op_run<double>(c, kind, level, a, b, out, nvec, smoother, nsteps, omega,
+                                    static_cast<hipStream_t>(stream));
+    return level_op_run<float>(c, kind, level, a, b, out, nvec, smoother, nsteps, omega,
+                               static_cast<hipStream_t>(stream));
+}
+}  // namespace
+
+extern "C" {
+
+mg_status mg_apply(mg_handle c, int level, const void* x, void* y, int nvec, int precision, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, true)) return st;
+    if (!is_dev_ptr_ok(x) || !is_dev_ptr_ok(y)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 0, level, x, nullptr, y, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_residual(mg_handle c, int level, const void* x, const void* f, void* r, int nvec, int precision,
+                      void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, true)) return st;
+    if (!is_dev_ptr_ok(x) || !is_dev_ptr_ok(f) || !is_dev_ptr_ok(r)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 1, level, x, f, r, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_smooth(mg_handle c, int level, int smoother, int nsteps, double omega, void* u, const void* f, int nvec,
+                    int precision, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, true)) return st;
+    if (smoother != MG_JACOBI && smoother != MG_GMRES3) { c->err = "unknown smoother"; return MG_E_ARG; }
+    if (nsteps < 0 || !(omega > 0.0)) { c->err = "nsteps >= 0 and omega > 0 required"; return MG_E_ARG; }
+    if (!is_dev_ptr_ok(u) || !is_dev_ptr_ok(f)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 2, level, nullptr, f, u, nvec, precision, smoother, nsteps, omega, stream);
+}
+
+mg_status mg_restrict(mg_handle c, int level, const void* fine, void* coarse, int nvec, int precision, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, false)) return st;
+    if (!is_dev_ptr_ok(fine) || !is_dev_ptr_ok(coarse)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 3, level, fine, nullptr, coarse, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_prolong_add(mg_handle c, int level, const void* coarse, void* fine, int nvec, int precision,
+                         void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, false)) return st;
+    if (!is_dev_ptr_ok(fine) || !is_dev_ptr_ok(coarse)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 4, level, coarse, nullptr, fine, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_coarse_solve(mg_handle c, const void* f, void* u, int nvec, int precision, void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, c->L - 1, precision, true)) return st;
+    if (!is_dev_ptr_ok(f) || !is_dev_ptr_ok(u)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    return level_entry(c, 5, c->L - 1, f, nullptr, u, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_cycle(mg_handle c, void* u, const void* f_s, int nvec, int cyc, int smoother, const mg_solve_opts* opts,
+                   void* stream) {
+    if (!c) return MG_E_ARG;
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    if (mg_status st = check_solve_args(c, nvec, 1.0, cyc, smoother, o)) return st;
+    if (o.precision != MG_FP64) { c->err = "mg_cycle runs FP64 cycles"; return MG_E_ARG; }
+    if (!is_dev_ptr_ok(u) || !is_dev_ptr_ok(f_s)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LevelBuf& l0 = c->lv[0];
+    LaunchCtx lc = launch_ctx(c, s, nvec);
+    lc.active = nullptr;
+    launch_copy_in<double>(lc, l0.g, f_s, false, vec<double>(l0.f64, l0), false, false);
+    launch_copy_in<double>(lc, l0.g, u, false, vec<double>(l0.u64, l0), false, false);
+    for (int i = 0; i < nvec; ++i) c->h_active[i] = 1;
+    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+    lc.active = c->active;
+    const CycleParams cp{cyc, smoother, o.nu_pre, o.nu_post, o.omega};
+    cycle<double>(c, lc, 0, cp);
+    launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), u, false, false, false);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return MG_OK;
+}
+
+mg_status mg_set_timing(mg_handle c, int kernel_class) {
+    if (!c) return MG_E_ARG;
+    if (kernel_class < 0 || kernel_class > 4) { c->err = "unknown kernel class"; return MG_E_ARG; }
+    c->timing_class = kernel_class;
+    c->ev_pending.clear();
+    c->t_launches = 0;
+    c->t_ms = 0.0;
+    c->t_nodes = 0.0;
+    return MG_OK;
+}
+
+mg_status mg_get_timing(mg_handle c, int* launches, double* total_ms, double* nodes_per_launch) {
+    if (!c) return MG_E_ARG;
+    harvest_timing(c);
+    if (launches) *launches = c->t_launches;
+    if (total_ms) *total_ms = c->t_ms;
+    if (nodes_per_launch) *nodes_per_launch = c->t_launches ? c->t_nodes / c->t_launches : 0.0;
+    return MG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// Setup kernels: k^2 layout, Galerkin coarse operators on the complex
+// shifted Laplacian, FP32 copies, the coarsest dense LU and its solves.
+#include "hm_ops.hpp"
+
+namespace hm {
+namespace {
+
+constexpr int kThreads = kBX * kBY;
+constexpr int kMaxCoarse = 1089;  // coarsest grid of at most 32 x 32 intervals
+
+// 1D prolongation weight of the §4 formula for a fine node at offset d from
+// the fine image 2K of coarse node K: Bézier [1 4 6 4 1]/8, linear [1 2 1]/2.
+__device__ __forceinline__ double mask1(int d, bool bez) {
+    const int a = d < 0 ? -d : d;
+    if (bez) return a == 0 ? 0.75 : a == 1 ? 0.5 : a == 2 ? 0.125 : 0.0;
+    return a == 0 ? 1.0 : a == 1 ? 0.5 : 0.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_k2_in(Grid g, const double* src, double* k64, float* k32) {
+    const long long m = g.n + 1;
+    for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < m * m; q += (long long)gridDim.x * kThreads) {
+        const int i = int(q % m), j = int(q / m);
+        const double v = src[q];
+        k64[g.at(i, j)] = v;
+        if (k32) k32[g.at(i, j)] = float(v);
+    }
+}
+
+// Coupling A(p, p + e) of the fine operator of a Galerkin product.
+// Level 0: the shifted Laplacian C_s = A_s - i beta2 W K^2, i.e. the scaled
+// 5-point operator of §2 with k^2 replaced by (1 + i beta2) k^2 (§4, §5).
+struct FineCoupling {
+    int level;
+    Grid g;
+    int r;
+    const cplx<double>* coef;
+    const double* k2;
+    double ih2, two_h, shift;
+    __device__ cplx<double> operator()(int px, int py, int ex, int ey) const {
+        if (level > 0) {
+            const int D = 2 * r + 1;
+            return coef[(long long)((ey + r) * D + ex + r) * g.plane + g.at(px, py)];
+        }
+        const int n = g.n;
+        if (ex == 0 && ey == 0) {
+            const double W = line_w<double>(px, n) * line_w<double>(py, n);
+            const int s = (px == 0 || px == n) + (py == 0 || py == n);
+            const double kk = k2[g.at(px, py)];
+            const double im = -shift * kk - (s ? two_h * s * sqrt(kk) : 0.0);
+            return {W * (4.0 * ih2 - kk), W * im};
+        }
+        if (ey == 0 && (ex == 1 || ex == -1)) return {-ih2 * line_w<double>(py, n), 0.0};
+        if (ex == 0 && (ey == 1 || ey == -1)) return {-ih2 * line_w<double>(px, n), 0.0};
+        return {0.0, 0.0};
+    }
+};
+
+// One coarse coefficient per thread: A_c(I, I + D) = sum_p R(I, p) sum_q A(p, q) P(q, I + D)
+// with R = P^T / 4 (§3 Galerkin condition, §4 transfers).
+__global__ __launch_bounds__(kThreads) void k_galerkin(FineCoupling A, Grid gc, int rc, int bez, cplx<double>* out) {
+    const long long mc = gc.n + 1;
+    const int Dc = 2 * rc + 1;
+    const long long total = mc * mc * Dc * Dc;
+    const int nf = A.g.n;
+    const int rf = A.r;
+    for (long long t = blockIdx.x * (long long)kThreads + threadIdx.x; t < total; t += (long long)gridDim.x * kThreads) {
+        const long long node = t % (mc * mc);
+        const int d = int(t / (mc * mc));
+        const int Ix = int(node % mc), Iy = int(node / mc);
+        const int Dx = d % Dc - rc, Dy = d / Dc - rc;
+        const int Kx = Ix + Dx, Ky = Iy + Dy;
+        cplx<double> acc{0.0, 0.0};
+        if (Kx >= 0 && Kx <= gc.n && Ky >= 0 && Ky <= gc.n) {
+            for (int ay = -2; ay <= 2; ++ay) {
+                const int py = 2 * Iy + ay;
+                if (py < 0 || py > nf) continue;
+                for (int ax = -2; ax <= 2; ++ax) {
+                    const int px = 2 * Ix + ax;
+                    if (px < 0 || px > nf) continue;
+                    const double rw = 0.25 * mask1(ax, bez) * mask1(ay, bez);
+                    if (rw == 0.0) continue;
+                    const int ey0 = max(-rf, 2 * Ky - 2 - py), ey1 = min(rf, 2 * Ky + 2 - py);
+                    const int ex0 = max(-rf, 2 * Kx - 2 - px), ex1 = min(rf, 2 * Kx + 2 - px);
+                    for (int ey = ey0; ey <= ey1; ++ey) {
+                        const int qy = py + ey;
+                        if (qy < 0 || qy > nf) continue;
+                        const double wy = mask1(qy - 2 * Ky, bez);
+                        if (wy == 0.0) continue;
+                        for (int ex = ex0; ex <= ex1; ++ex) {
+                            const int qx = px + ex;
+                            if (qx < 0 || qx > nf) continue;
+                            const double w = rw * wy * mask1(qx - 2 * Kx, bez);
+                            if (w == 0.0) continue;
+                            const cplx<double> a = A(px, py, ex, ey);
+                            acc.re += w * a.re;
+                            acc.im += w * a.im;
+                        }
+                    }
+                }
+            }
+        }
+        out[(long long)d * gc.plane + gc.at(Ix, Iy)] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cast_coef(const cplx<double>* src, cplx<float>* dst, long long count) {
+    for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < count; q += (long long)gridDim.x * kThreads)
+        dst[q] = cast<float>(src[q]);
+}
+
+// Dense coarsest matrix, row P = J m + I, column Q = P + (Dy m + Dx).
+__global__ __launch_bounds__(kThreads) void k_dense(Grid g, int r, const cplx<double>* coef, cplx<double>* dense) {
+    const int m = g.n + 1;
+    const int N = m * m;
+    const int D = 2 * r + 1;
+    for (long long t = blockIdx.x * (long long)kThreads + threadIdx.x; t < (long long)N * N;
+         t += (long long)gridDim.x * kThreads)
+        dense[t] = {0.0, 0.0};
+    __syncthreads();
+    // single block: the zero fill above and the scatter below are ordered by the barrier
+    for (long long t = threadIdx.x; t < (long long)N * D * D; t += kThreads) {
+        const int P = int(t % N), d = int(t / N);
+        const int I = P % m, J = P / m;
+        const int dx = d % D - r, dy = d / D - r;
+        const int Kx = I + dx, Ky = J + dy;
+        if (Kx < 0 || Kx > g.n || Ky < 0 || Ky > g.n) continue;
+        dense[(long long)P * N + Ky * m + Kx] = coef[(long long)d * g.plane + g.at(I, J)];
+    }
+}
+
+__device__ __forceinline__ double cabs1(cplx<double> a) { return fabs(a.re) + fabs(a.im); }
+
+// In-place LU with partial pivoting (largest |re| + |im| in the column, first
+// index on ties), row-major; piv[k] is the row swapped with row k at step k.
+__global__ __launch_bounds__(kThreads) void k_lu(int N, cplx<double>* A, int* piv) {
+    __shared__ double sv[kThreads];
+    __shared__ int si[kThreads];
+    const int tid = threadIdx.x;
+    for (int k = 0; k < N; ++k) {
+        double best = -1.0;
+        int bi = N;
+        for (int i = k + tid; i < N; i += kThreads) {
+            const double v = cabs1(A[(long long)i * N + k]);
+            if (v > best) { best = v; bi = i; }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int s = kThreads / 2; s > 0; s >>= 1) {
+            if (tid < s) {
+                const double v2 = sv[tid + s];
+                const int i2 = si[tid + s];
+                if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) { sv[tid] = v2; si[tid] = i2; }
+            }
+            __syncthreads();
+        }
+        const int p = si[0];
+        if (tid == 0) piv[k] = p;
+        if (p != k)
+            for (int c = tid; c < N; c += kThreads) {
+                const cplx<double> t = A[(long long)k * N + c];
+                A[(long long)k * N + c] = A[(long long)p * N + c];
+                A[(long long)p * N + c] = t;
+            }
+        __syncthreads();
+        const cplx<double> pivot = A[(long long)k * N + k];
+        for (int i = k + 1 + tid; i < N; i += kThreads) A[(long long)i * N + k] = cdiv(A[(long long)i * N + k], pivot);
+        __syncthreads();
+        const int rem = N - k - 1;
+        for (long long t = tid; t < (long long)rem * rem; t += kThreads) {
+            const int i = k + 1 + int(t / rem), c = k + 1 + int(t % rem);
+            const cplx<double> l = A[(long long)i * N + k];
+            const cplx<double> uu = A[(long long)k * N + c];
+            const cplx<double> a = A[(long long)i * N + c];
+            A[(long long)i * N + c] = a - l * uu;
+        }
+        __syncthreads();
+    }
+}
+
+// One block per right-hand side: permute, unit-lower forward and upper back
+// substitution in FP64 (also for complex64 data, which is widened).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_coarse_solve(Grid g, const cplx<double>* LU, const int* piv, Vec<T> f,
+                                                           Vec<T> u, const int* active) {
+    const int b = blockIdx.x;
+    if (!rhs_active(active, b)) return;
+    __shared__ cplx<double> x[kMaxCoarse];
+    const int m = g.n + 1;
+    const int N = m * m;
+    const int tid = threadIdx.x;
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* ub = u.rhs(b);
+    for (int P = tid; P < N; P += kThreads) x[P] = cast<double>(fb[g.at(P % m, P / m)]);
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 0; k < N; ++k) {
+            const int p = piv[k];
+            if (p != k) {
+                const cplx<double> t = x[k];
+                x[k] = x[p];
+                x[p] = t;
+            }
+        }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const cplx<double> xk = x[k];
+        for (int i = k + 1 + tid; i < N; i += kThreads) x[i] = x[i] - LU[(long long)i * N + k] * xk;
+        __syncthreads();
+    }
+    for (int k = N - 1; k >= 0; --k) {
+        if (tid == 0) x[k] = cdiv(x[k], LU[(long long)k * N + k]);
+        __syncthreads();
+        const cplx<double> xk = x[k];
+        for (int i = tid; i < k; i += kThreads) x[i] = x[i] - LU[(long long)i * N + k] * xk;
+        __syncthreads();
+    }
+    for (int P = tid; P < N; P += kThreads) ub[g.at(P % m, P / m)] = cast<T>(x[P]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_stencil_out(Grid g, int r, const cplx<double>* coef, cplx<double>* out) {
+    const long long m = g.n + 1;
+    const int D = 2 * r + 1;
+    const long long total = m * m * D * D;
+    for (long long t = blockIdx.x * (long long)kThreads + threadIdx.x; t < total; t += (long long)gridDim.x * kThreads) {
+        const long long node = t % (m * m);
+        const int d = int(t / (m * m));
+        out[t] = coef[(long long)d * g.plane + g.at(int(node % m), int(node / m))];
+    }
+}
+
+unsigned blocks_for(long long work) {
+    long long b = (work + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+void launch_k2_in(hipStream_t s, Grid g, const double* k2_dense, double* k2_64, float* k2_32) {
+    const long long m = g.n + 1;
+    hipLaunchKernelGGL(k_k2_in, dim3(blocks_for(m * m)), dim3(kThreads), 0, s, g, k2_dense, k2_64, k2_32);
+}
+
+void launch_galerkin(hipStream_t s, int fine_level, Grid fine, int fine_radius, const cplx<double>* fine_coef,
+                     const double* k2_64, double h, double shift, int transfer, Grid coarse, int coarse_radius,
+                     cplx<double>* coarse_coef) {
+    FineCoupling A{fine_level, fine, fine_radius, fine_coef, k2_64, 1.0 / (h * h), 2.0 / h, shift};
+    const long long mc = coarse.n + 1;
+    const long long D = 2 * coarse_radius + 1;
+    hipLaunchKernelGGL(k_galerkin, dim3(blocks_for(mc * mc * D * D)), dim3(kThreads), 0, s, A, coarse, coarse_radius,
+                       int(transfer == 0), coarse_coef);
+}
+
+void launch_cast_coef(hipStream_t s, const cplx<double>* src, cplx<float>* dst, long long count) {
+    hipLaunchKernelGGL(k_cast_coef, dim3(blocks_for(count)), dim3(kThreads), 0, s, src, dst, count);
+}
+
+void launch_dense_lu(hipStream_t s, Grid g, int radius, const cplx<double>* coef, cplx<double>* dense, int* piv) {
+    const int m = g.n + 1;
+    hipLaunchKernelGGL(k_dense, dim3(1), dim3(kThreads), 0, s, g, radius, coef, dense);
+    hipLaunchKernelGGL(k_lu, dim3(1), dim3(kThreads), 0, s, m * m, dense, piv);
+}
+
+template <typename T>
+void launch_coarse_solve(const LaunchCtx& ctx, Grid g, const cplx<double>* lu, const int* piv, Vec<T> f, Vec<T> u) {
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(ctx.nrhs), dim3(kThreads), 0, ctx.stream, g, lu, piv, f, u,
+                       ctx.active);
+}
+template void launch_coarse_solve<double>(const LaunchCtx&, Grid, const cplx<double>*, const int*, Vec<double>,
+                                          Vec<double>);
+template void launch_coarse_solve<float>(const LaunchCtx&, Grid, const cplx<double>*, const int*, Vec<float>,
+                                         Vec<float>);
+
+void launch_stencil_out(hipStream_t s, Grid g, int radius, const cplx<double>* coef, void* out) {
+    const long long m = g.n + 1;
+    const long long D = 2 * radius + 1;
+    hipLaunchKernelGGL(k_stencil_out, dim3(blocks_for(m * m * D * D)), dim3(kThreads), 0, s, g, radius, coef,
+                       static_cast<cplx<double>*>(out));
+}
+
+}  // namespace hm

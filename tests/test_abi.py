@@ -1,0 +1,63 @@
+"""The C ABI library builds, loads and exports every declared entry point;
+argument checks that run before any HIP call work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helmg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", text)))
+
+
+def _lib():
+    from paper_2308_13476_amd import _binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libhelmg.so not built")
+    return B.lib(), B
+
+
+def test_header_declares_the_expected_entry_points():
+    decl = _declared()
+    for name in ["mg_setup", "mg_solve", "mg_grad", "mg_destroy", "mg_workspace_bytes", "mg_update_k2"]:
+        assert name in decl
+
+
+def test_library_exports_every_declared_symbol():
+    L, B = _lib()
+    decl = _declared()
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(B.EXPORTED) == decl
+
+
+def test_workspace_size_and_argument_checks_without_gpu():
+    L, B = _lib()
+    opts = B.SetupOpts(B.MG_FP64, 1, 4)
+    assert L.mg_workspace_bytes(64, 0, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) > 0
+    assert L.mg_workspace_bytes(63, 0, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # not halvable to 4
+    assert L.mg_workspace_bytes(64, 9, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # too many levels
+    assert L.mg_workspace_bytes(4096, 3, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # coarsest too large
+    big = B.SetupOpts(B.MG_FP32_REFINED, 4, 4)
+    assert L.mg_workspace_bytes(64, 0, 0, ctypes.byref(big)) > L.mg_workspace_bytes(64, 0, 0, ctypes.byref(opts))
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: the checks fail first
+    assert L.mg_setup(fake, 64, -1.0, 0.1, 0, 0, ctypes.byref(opts), fake, 1 << 30, None, ctypes.byref(h)) == B.MG_E_ARG
+    assert b"h must be" in L.mg_last_error(None)
+    assert L.mg_setup(fake, 64, 1 / 64, -0.5, 0, 0, ctypes.byref(opts), fake, 1 << 30, None,
+                      ctypes.byref(h)) == B.MG_E_ARG
+    assert L.mg_setup(fake, 63, 1 / 63, 0.1, 0, 0, ctypes.byref(opts), fake, 1 << 30, None,
+                      ctypes.byref(h)) == B.MG_E_ARG
+    assert L.mg_setup(fake, 64, 1 / 64, 0.1, 0, 7, ctypes.byref(opts), fake, 1 << 30, None,
+                      ctypes.byref(h)) == B.MG_E_ARG
+    small = ctypes.c_size_t(16)
+    assert L.mg_setup(fake, 64, 1 / 64, 0.1, 0, 0, ctypes.byref(opts), fake, small, None,
+                      ctypes.byref(h)) == B.MG_E_WORKSPACE
+    assert L.mg_solve(None, fake, fake, 1, 1e-6, 1, 1, None, None, None) == B.MG_E_ARG
+    assert L.mg_status_string(B.MG_E_DIVERGED) == b"MG_E_DIVERGED"

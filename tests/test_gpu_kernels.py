@@ -1,0 +1,175 @@
+"""Kernel-by-kernel parity of the HIP path with the CPU oracle (FP64 and FP32).
+
+Grids span several 64 x 4 thread tiles with ragged tails (65, 97 and 201 nodes
+per side); one case has a variable wavenumber and one uses linear transfers.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+from paper_2308_13476_amd import workloads as W
+from tests.gpu_common import rel, require_gpu, stencil_to_csr, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+# (name, n, k2 builder, shift, transfer, coarsest_n)
+CASES = [
+    ("const_n64", 64, lambda n: W.constant_k2(n, 20.0), 0.7, "bezier", 4),
+    ("varying_n96", 96, lambda n: W.random_k2(n, 3, 10.0, 25.0), 0.05, "bezier", 3),
+    ("const_n200", 200, lambda n: W.constant_k2(n, 30.0), 1.0 / 30.0, "bezier", 25),
+    ("linear_n64", 64, lambda n: W.constant_k2(n, 10.0), 0.5, "linear", 4),
+]
+
+_cache = {}
+
+
+def _pair(case):
+    if case[0] in _cache:
+        return _cache[case[0]]
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    name, n, k2f, beta, transfer, nc = case
+    k2 = k2f(n)
+    H = O.build_hierarchy(k2, 1.0 / n, beta, transfer=transfer, coarsest_n=nc)
+    S = Solver(to_gpu(k2), 1.0 / n, beta, levels=H.levels, transfer=transfer, precision="fp32_refined", max_batch=3)
+    _cache[case[0]] = (H, S)
+    return H, S
+
+
+def _rand(n_l, nb, seed):
+    return W.random_complex((nb, n_l + 1, n_l + 1), seed)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_level_count_and_radius(case):
+    H, S = _pair(case)
+    assert S.levels == H.levels
+    for l in range(H.levels):
+        n_l, r = S.level_info(l)
+        assert n_l == H.n[l]
+        if l == 0:
+            assert r == 1
+        elif case[4] == "bezier":
+            assert r == (2 if l == 1 else 3)
+        else:
+            assert r == 1
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_galerkin_stencils(case):
+    H, S = _pair(case)
+    for l in range(1, H.levels):
+        got = stencil_to_csr(to_np(S.stencil(l)))
+        ref = H.A[l]
+        scale = abs(ref).max()
+        assert abs(got - ref).max() <= 1e-13 * scale, (l, abs(got - ref).max() / scale)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_operator_apply_and_residual(case):
+    H, S = _pair(case)
+    for l in range(H.levels):
+        x = _rand(H.n[l], 3, 10 + l)
+        f = _rand(H.n[l], 3, 20 + l)
+        y = to_np(S.apply(l, to_gpu(x)))
+        r = to_np(S.residual(l, to_gpu(x), to_gpu(f)))
+        for b in range(3):
+            yr = H.A[l] @ x[b].ravel()
+            assert rel(y[b], yr) <= 1e-13, (l, b)
+            assert rel(r[b], f[b].ravel() - yr) <= 1e-13
+        y32 = to_np(S.apply(l, to_gpu(x.astype(np.complex64)), precision="fp32_refined"))
+        assert y32.dtype == np.complex64
+        assert rel(y32[0], H.A[l] @ x[0].ravel()) <= 2e-5
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_restriction_and_prolongation(case):
+    H, S = _pair(case)
+    for l in range(H.levels - 1):
+        fine = _rand(H.n[l], 2, 30 + l)
+        coarse = _rand(H.n[l + 1], 2, 40 + l)
+        rc = to_np(S.restrict(l, to_gpu(fine)))
+        pf = to_np(S.prolong_add(l, to_gpu(coarse), to_gpu(fine)))
+        for b in range(2):
+            assert rel(rc[b], H.R[l] @ fine[b].ravel()) <= 1e-14
+            assert rel(pf[b], fine[b].ravel() + H.P[l] @ coarse[b].ravel()) <= 1e-14
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_jacobi_and_gmres_smoothing(case):
+    H, S = _pair(case)
+    for l in [0, 1, H.levels - 2]:
+        u = _rand(H.n[l], 2, 50 + l)
+        f = _rand(H.n[l], 2, 60 + l)
+        uj = to_np(S.smooth(l, to_gpu(u), to_gpu(f), "jacobi", nsteps=3, omega=4.5))
+        ug = to_np(S.smooth(l, to_gpu(u), to_gpu(f), "gmres", nsteps=2))
+        for b in range(2):
+            ref = u[b].ravel()
+            for _ in range(3):
+                ref = O.jacobi_step(H.A[l], ref, f[b].ravel(), 4.5)
+            assert rel(uj[b], ref) <= 1e-12, (l, b)
+            ref = u[b].ravel()
+            for _ in range(2):
+                ref = O.gmres_step(H.A[l], ref, f[b].ravel())
+            assert rel(ug[b], ref) <= 1e-10, (l, b, rel(ug[b], ref))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fp32_smoothing_close_to_fp32_oracle(case):
+    H, S = _pair(case)
+    l = 0
+    u = _rand(H.n[l], 1, 70).astype(np.complex64)
+    f = _rand(H.n[l], 1, 71).astype(np.complex64)
+    ug = to_np(S.smooth(l, to_gpu(u), to_gpu(f), "gmres", nsteps=1, precision="fp32_refined"))
+    ref = O.gmres_step(H.A32[l], u[0].ravel(), f[0].ravel(), breakdown=1e-6)
+    assert rel(ug[0], ref) <= 1e-4
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_coarsest_direct_solve(case):
+    H, S = _pair(case)
+    f = _rand(H.n[-1], 3, 80)
+    u = to_np(S.coarse_solve(to_gpu(f)))
+    for b in range(3):
+        ref = sla.lu_solve(H.lu, f[b].ravel())
+        assert rel(u[b], ref) <= 1e-12
+    u32 = to_np(S.coarse_solve(to_gpu(f.astype(np.complex64)), precision="fp32_refined"))
+    assert rel(u32[0], sla.lu_solve(H.lu, f[0].ravel().astype(np.complex64).astype(complex))) <= 1e-6
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("cyc,smoother", [("V", "jacobi"), ("W", "jacobi"), ("V", "gmres"), ("W", "gmres")])
+def test_one_cycle(case, cyc, smoother):
+    H, S = _pair(case)
+    n = H.n[0]
+    u = _rand(n, 2, 90)
+    f = _rand(n, 2, 91)
+    got = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, smoother=smoother))
+    opts = O.CycleOptions(gamma=1 if cyc == "V" else 2, smoother=smoother)
+    for b in range(2):
+        ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
+        assert rel(got[b], ref) <= 1e-10, (b, rel(got[b], ref))
+
+
+def test_full_size_level_operations_on_sampled_rows():
+    """n = 1024 (the benchmarked grid), shift 1/k, k = 200: Galerkin rows and level
+    applies at sampled nodes against rows of the oracle's matrices."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    n, k = 1024, 200.0
+    k2 = W.constant_k2(n, k)
+    H = O.build_hierarchy(k2, 1.0 / n, 1.0 / k)
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k)
+    rng = np.random.default_rng(5)
+    for l in range(H.levels):
+        m = H.n[l] + 1
+        x = W.random_complex((1, m, m), 100 + l)
+        y = to_np(S.apply(l, to_gpu(x)))[0].ravel()
+        rows = np.concatenate([[0, m - 1, m * m - 1, (m // 2) * m + m // 2], rng.integers(0, m * m, size=64)])
+        ref = H.A[l][rows] @ x[0].ravel()
+        assert rel(y[rows], ref) <= 1e-13, l
+        if l >= 1:
+            st = stencil_to_csr(to_np(S.stencil(l)))
+            diff = abs(st[rows] - H.A[l][rows]).max()
+            assert diff <= 1e-13 * abs(H.A[l]).max(), l
