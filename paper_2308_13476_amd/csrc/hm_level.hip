@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_residual(Op op, Vec<T> u, Vec<T
     if (!rhs_active(active, b)) return;
     const cplx<T>* ub = u.rhs(b);
     const cplx<T>* fb = f.rhs(b);
-    cplx<T>* vb = v0.rhs(b);
+    cplx<T>* vb = v0.p + (long long)(b * 4) * v0.plane;  // Arnoldi block of 4 planes per right-hand side
     double acc[1] = {0.0};
     for_nodes(op.g, rpt, [&](int i, int j, long long p) {
         const cplx<T> z = fb[p] - op.apply(ub, i, j, p);
