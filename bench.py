@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X stand-alone Helmholtz multigrid (one GPU).
+
+Workload (MP 2-A of the paper at the benchmarked size): n = 1024 intervals per
+side (1,050,625 unknowns), k = 200 (kh ~ 0.2), unit point source 1/h^2 at the
+centre, absorbing boundary, Bézier transfers, shift 1/k, GMRES(3) V(1,1)
+cycles, coarsening to 4 x 4 intervals, relative residual 1e-6.
+
+One step = rebuild of the Galerkin hierarchy for the k^2 field (setup) + an
+FP32-in-FP64-refined solve to tolerance, with all inputs resident in HBM. The
+plain FP64 solve of the same problem is timed beside it. `value` is V-cycle
+throughput in unknowns x cycles per second over the timed steps.
+
+Prints one JSON line. `--gpus N` with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time to rel.res 1e-6 & V-cycle DOF/s, FP32-refined vs FP64; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per node (one read of every input, one write of every
+# output) of the kernel classes the library can time with HIP events.
+# Class 1: level-0 GMRES Arnoldi apply pass w = A z_J with inner products
+# <z_i, w>, i <= J: reads z_0..z_J and k^2, writes w. In the FP32 cycle a
+# vector is 8 B and k^2 is 4 B: 20 + 8 J bytes, 28 B on average over J = 0, 1, 2.
+KERNEL_CLASSES = {
+    1: {"name": "level-0 GMRES(3) apply + inner products (complex64)", "bytes_per_node": 28.0},
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--k", type=float, default=200.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=12, help="oracle cycles in the CPU sample")
+    ap.add_argument("--kernel-class", type=int, default=1)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, k, cycles):
+    """The CPU oracle on a bounded sample of the same workload: FP64 hierarchy
+    setup (not counted) and `cycles` GMRES(3) V(1,1) cycles, single thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import oracle as O
+    from paper_2308_13476_amd import workloads as W
+
+    import contextlib
+    with (threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()):
+        k2 = W.constant_k2(n, k)
+        fs = O.scaled_rhs(W.point_source_rhs(n, [W.center_node(n)])[0]).ravel()
+        H = O.build_hierarchy(k2, 1.0 / n, 1.0 / k)
+        opts = O.CycleOptions(smoother="gmres")
+        t0 = time.perf_counter()
+        O.solve(H, fs, opts, tol=1e-30, max_cycles=cycles)
+        dt = time.perf_counter() - t0
+    return {"value": (n + 1) ** 2 * cycles / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cycles} FP64 GMRES(3) V(1,1) cycles of the same n={n}, k={k:g} problem "
+                      f"(oracle setup excluded), {dt:.1f} s on one host thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    n, k = args.n, args.k
+    beta = 1.0 / k
+    nodes = (n + 1) ** 2
+    k2 = torch.from_numpy(W.constant_k2(n, k)).to(dev)
+    f = torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev)
+    S = Solver(k2, 1.0 / n, beta, precision="fp32_refined")
+    solve_kw = dict(tol=1e-6, cycle="V", smoother="gmres", nu_pre=1, nu_post=1, max_cycles=500)
+    print(f"bench: n={n} k={k:g} levels={S.levels} warmup={args.warmup} steps={args.steps}", file=sys.stderr,
+          flush=True)
+
+    def step(precision):
+        S.update_k2(k2)
+        return S.solve(f, precision=precision, **solve_kw)
+
+    def timed(precision, steps, kernel_class=0):
+        for _ in range(args.warmup):
+            step(precision)
+        S.set_timing(kernel_class)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cycles, solve_s, x = 0, 0.0, None
+        for _ in range(steps):
+            x, info = step(precision)
+            assert info["status"] == 0, info
+            cycles += info["cycles"][0]
+            solve_s += info["seconds"]
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = S.get_timing()
+        S.set_timing(0)
+        return {"ms_total": ms, "ms_per_step": ms / steps, "cycles_per_solve": cycles / steps,
+                "solve_ms_per_step": 1e3 * solve_s / steps, "x": x, "kernel": kt}
+
+    r32 = timed("fp32_refined", args.steps)
+    print(f"bench: fp32-refined {r32['ms_per_step']:.2f} ms/step, {r32['cycles_per_solve']:.0f} cycles",
+          file=sys.stderr, flush=True)
+    # the same steps again with HIP events around every launch of the roofline
+    # kernel (kernel-by-kernel launches instead of captured graphs)
+    rk = timed("fp32_refined", max(1, args.steps // 2), args.kernel_class)
+    r64 = timed("fp64", max(2, args.steps // 2))
+    print(f"bench: fp64 {r64['ms_per_step']:.2f} ms/step, {r64['cycles_per_solve']:.0f} cycles", file=sys.stderr,
+          flush=True)
+
+    value = nodes * r32["cycles_per_solve"] * args.steps / (r32["ms_total"] * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 cycle in c128 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"MP 2-A, n={n} ({nodes} unknowns), k={k:g}, centre point source, GMRES(3) "
+                               f"V(1,1), Bezier transfers, shift 1/k, coarsest 4x4, tol 1e-6, "
+                               f"setup + FP32-refined solve per step",
+                   "n": n, "k": k, "levels": S.levels},
+        "time_to_tol_ms": {"fp32_refined": r32["ms_per_step"], "fp64": r64["ms_per_step"]},
+        "solve_only_ms": {"fp32_refined": r32["solve_ms_per_step"], "fp64": r64["solve_ms_per_step"]},
+        "cycles": {"fp32_refined": r32["cycles_per_solve"], "fp64": r64["cycles_per_solve"]},
+        "vcycle_dof_per_s": {"fp32_refined": value,
+                             "fp64": nodes * r64["cycles_per_solve"] / (r64["ms_per_step"] * 1e-3)},
+        "fp32_refined_speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
+    }
+    # error of both GPU results against the stored FP64 oracle iterate and exact solution
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
+    if n == 1024 and k == 200.0 and os.path.exists(gold):
+        g = json.load(open(gold))
+        if "samples" in g:
+            idx = np.array(g["samples"]["index"])
+            mg = np.array(g["samples"]["fp64_mg_re"]) + 1j * np.array(g["samples"]["fp64_mg_im"])
+            ex = np.array(g["samples"]["exact_re"]) + 1j * np.array(g["samples"]["exact_im"])
+            errs = {}
+            for name, r in [("fp32_refined", r32), ("fp64", r64)]:
+                xs = r["x"][0].reshape(-1).cpu().numpy()[idx]
+                errs[name] = {"vs_fp64_oracle_iterate": float(np.linalg.norm(xs - mg) / np.linalg.norm(mg)),
+                              "vs_exact_discrete_solution": float(np.linalg.norm(xs - ex) / np.linalg.norm(ex))}
+            out["rel_error_on_4096_sampled_nodes"] = errs
+    launches, kms, knodes = rk["kernel"]
+    if launches > 0 and args.kernel_class in KERNEL_CLASSES:
+        kc = KERNEL_CLASSES[args.kernel_class]
+        avg_ms = kms / launches
+        achieved = kc["bytes_per_node"] * knodes / (avg_ms * 1e-3) / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kc["name"],
+                           "avg_launch_us": avg_ms * 1e3, "launches": launches,
+                           "timed_in": "repeat of the timed steps with HIP events per launch (no graphs)"}
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_cycles)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -188,7 +188,8 @@ mg_status mg_cycle(mg_handle h, void* u, const void* f_s, int nvec, int cycle, i
 /* ---- Timing hook: HIP events around every launch of one kernel class on
  * the solve stream, accumulated until read. kernel_class: 0 off, 1 level-0
  * GMRES Arnoldi apply pass, 2 level-0 Jacobi sweep, 3 level-0 residual +
- * restriction, 4 level-1 stencil apply pass. ---- */
+ * restriction, 4 level-1 stencil apply pass. While a class is set, cycles are
+ * launched kernel by kernel instead of as captured HIP graphs. ---- */
 mg_status mg_set_timing(mg_handle h, int kernel_class);
 mg_status mg_get_timing(mg_handle h, int* launches, double* total_ms, double* nodes_per_launch);
 

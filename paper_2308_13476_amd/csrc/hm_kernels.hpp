@@ -29,7 +29,7 @@ struct LaunchCtx {
     hipStream_t stream;
     int nrhs;              // batch size (grid z)
     const int* active;     // [nrhs] device flags; 0 skips that right-hand side
-    double* partials;      // reduction scratch [nrhs][max_blocks][8]
+    double* partials;      // reduction slots [nrhs][max_blocks][8], armed with the empty pattern
     unsigned* counters;    // [nrhs] zeroed completion counters
     long long max_blocks;  // capacity of `partials` per right-hand side
     int rpt;               // rows per thread of the level kernels
@@ -59,8 +59,9 @@ template <typename T> void launch_apply(const LaunchCtx&, const LevelOp<T>&, Vec
 template <typename T> void launch_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> r);
 template <typename T>
 void launch_jacobi(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
+// fc = R r; when uc.p is not null the coarse iterate uc is zeroed in the same pass.
 template <typename T>
-void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc);
+void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc);
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
@@ -95,7 +96,8 @@ void launch_copy_in(const LaunchCtx&, Grid g, const void* src, bool src_is_f32, 
 template <typename T>
 void launch_copy_out(const LaunchCtx&, Grid g, Vec<T> src, void* dst, bool dst_is_f32, bool scale_w, bool conj);
 template <typename T> void launch_zero(hipStream_t, cplx<T>* p, long long count);
-void launch_zero_real(hipStream_t, void* p, long long bytes);
+// Fills `bytes` (a multiple of 4) with a 32-bit pattern.
+void launch_fill_words(hipStream_t, void* p, long long bytes, unsigned value);
 
 // Adjoint gradient: g_p = sum_b Re[mu_b,p W_p (1 + i s_p / (h k_p)) u_b,p], mu = conj(lambda).
 void launch_grad_k2(const LaunchCtx&, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,

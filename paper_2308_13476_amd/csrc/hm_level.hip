@@ -72,14 +72,18 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
 // Restriction R = P^T / 4 of the §4 prolongation: the 2D row is the outer
 // product of [1 4 6 4 1]/16 (Bézier) or [1 2 1]/4 (linear) centred on the
 // fine node (2I, 2J); fine ghosts are zero, which truncates at the boundary.
+// The coarse iterate that the next cycle starts from (zero) is written in the
+// same pass when `uc` is given.
 template <typename T, bool kBez>
-__global__ __launch_bounds__(kThreads) void k_restrict(Grid gf, Grid gc, Vec<T> r, Vec<T> fc, const int* active,
-                                                       int rpt) {
+__global__ __launch_bounds__(kThreads) void k_restrict(Grid gf, Grid gc, Vec<T> r, Vec<T> fc, Vec<T> uc,
+                                                       const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* rb = r.rhs(b);
     cplx<T>* fb = fc.rhs(b);
+    cplx<T>* ub = uc.p ? uc.rhs(b) : nullptr;
     for_nodes(gc, rpt, [&](int I, int J, long long pc) {
+        if (ub) ub[pc] = cplx<T>{T(0), T(0)};
         const long long pf = gf.at(2 * I, 2 * J);
         cplx<T> acc{T(0), T(0)};
         if constexpr (kBez) {
@@ -501,9 +505,9 @@ __global__ __launch_bounds__(kThreads) void k_zero(cplx<T>* p, long long count) 
         p[q] = cplx<T>{T(0), T(0)};
 }
 
-__global__ __launch_bounds__(kThreads) void k_zero_bytes(unsigned* p, long long words) {
+__global__ __launch_bounds__(kThreads) void k_fill_words(unsigned* p, long long words, unsigned value) {
     for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < words; q += (long long)gridDim.x * kThreads)
-        p[q] = 0u;
+        p[q] = value;
 }
 
 // ---------------------------------------------------------------- gradient
@@ -559,14 +563,14 @@ void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T>
 }
 
 template <typename T>
-void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc) {
+void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc) {
     const int rpt = level_rpt(coarse, ctx.rpt);
     const dim3 grid = level_grid(coarse, rpt, ctx.nrhs);
     if (transfer == 0)
-        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc, HM_ACTIVE,
-                           rpt);
+        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc, uc,
+                           HM_ACTIVE, rpt);
     else
-        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc,
+        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc, uc,
                            HM_ACTIVE, rpt);
 }
 
@@ -696,12 +700,13 @@ void launch_zero(hipStream_t s, cplx<T>* p, long long count) {
     hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)blocks), dim3(kThreads), 0, s, p, count);
 }
 
-void launch_zero_real(hipStream_t s, void* p, long long bytes) {
+void launch_fill_words(hipStream_t s, void* p, long long bytes, unsigned value) {
     const long long words = bytes / 4;
     if (words <= 0) return;
     long long blocks = (words + kThreads - 1) / kThreads;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)blocks), dim3(kThreads), 0, s, static_cast<unsigned*>(p), words);
+    hipLaunchKernelGGL(k_fill_words, dim3((unsigned)blocks), dim3(kThreads), 0, s, static_cast<unsigned*>(p), words,
+                       value);
 }
 
 void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,
@@ -715,7 +720,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_apply<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>);                         \
     template void launch_residual<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>);              \
     template void launch_jacobi<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, double);        \
-    template void launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                        \
+    template void launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>);                \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gm_residual<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, GmState*); \
     template void launch_gm_apply<T>(const LaunchCtx&, const LevelOp<T>&, int, Vec<T>, Vec<T>, GmState*);       \

@@ -85,10 +85,42 @@ __device__ __forceinline__ void for_nodes(const Grid& g, int rpt, F&& f) {
 
 __device__ __forceinline__ bool rhs_active(const int* active, int b) { return active == nullptr || active[b] != 0; }
 
+// Grid-wide reduction slots. Every slot of the partials array holds the
+// "empty" bit pattern between uses (armed at setup). A block publishes its
+// partial with an agent-scope atomic store; the last block to arrive reads
+// every slot with agent-scope atomic loads, waiting (bounded) until the slot
+// is no longer empty, and re-arms it. Coherence of each atomic location is
+// all this needs: no fence, hence no L2 write-back or invalidation in the
+// streaming kernels that end in a reduction.
+constexpr unsigned long long kEmptySlot = ~0ull;
+constexpr int kSlotSpinLimit = 1 << 20;
+
+__device__ __forceinline__ void slot_publish(double* slot, double v) {
+    unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (v != v) bits = 0x7ff8000000000000ull;  // canonical NaN: never the empty pattern
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(slot), bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// `budget` bounds the total wait of the calling thread over all its slots.
+__device__ __forceinline__ double slot_take(double* slot, int& budget) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(slot);
+    unsigned long long bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    while (bits == kEmptySlot && budget > 0) {
+        --budget;
+        __builtin_amdgcn_s_sleep(1);
+        bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_store(p, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a slot that never filled (cannot happen while every block publishes) yields NaN,
+    // which the residual checks report as divergence instead of hanging
+    return bits == kEmptySlot ? __longlong_as_double(0x7ff8000000000000ll) : __longlong_as_double((long long)bits);
+}
+
 // Deterministic grid-wide reduction of K doubles per thread for right-hand
-// side blockIdx.z: block sums go to `partials`, and the last block to arrive
-// (counted with an agent-scope atomic) adds them in block order and returns
-// true with the totals in `tot` (all its threads). The counter is re-armed.
+// side blockIdx.z: block sums go to `partials`; the last block to arrive
+// (agent-scope atomic counter) adds them in block order and returns true with
+// the totals in `tot` (all its threads). The counter is re-armed.
 template <int K>
 __device__ bool reduce_last(double (&v)[K], double* partials, unsigned* counter, double (&tot)[K]) {
     __shared__ double sh[K][kBY];
@@ -109,21 +141,20 @@ __device__ bool reduce_last(double (&v)[K], double* partials, unsigned* counter,
             double s = 0.0;
 #pragma unroll
             for (int w = 0; w < kBY; ++w) s += sh[k][w];
-            __hip_atomic_store(&partials[blk * K + k], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            slot_publish(&partials[blk * K + k], s);
         }
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == (unsigned)(nblk - 1));
     }
     __syncthreads();
     if (!s_last) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    int budget = kSlotSpinLimit;
     for (long long q = tid; q < nblk; q += kBX * kBY) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            acc[k] += __hip_atomic_load(&partials[q * K + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int k = 0; k < K; ++k) acc[k] += slot_take(&partials[q * K + k], budget);
     }
     __syncthreads();
 #pragma unroll

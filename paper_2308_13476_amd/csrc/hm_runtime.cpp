@@ -97,12 +97,24 @@ struct mg_ctx {
     RhsNorms* h_norms = nullptr;
     int* h_active = nullptr;
     std::string err;
-    // kernel timing hook
+    // kernel timing hook: event pairs of eager launches, and of the graph run last
     int timing_class = 0;
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     int t_launches = 0;
     double t_ms = 0.0, t_nodes = 0.0;
+    // captured cycles (one per configuration and buffer assignment)
+    struct GraphEntry {
+        std::vector<uintptr_t> key;
+        hipGraphExec_t exec = nullptr;
+        std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+        double timed_nodes = 0.0;
+        std::vector<void*> after_ptrs;
+        int after_cur = 0;
+    };
+    std::vector<GraphEntry> graphs;
+    int last_graph = -1;
+    hipStream_t cap_stream = nullptr;
+    bool use_graph = true;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -256,36 +268,135 @@ struct TimedScope {
     mg_ctx* c;
     hipStream_t s;
     bool on;
-    int e0 = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     double nodes;
-    TimedScope(mg_ctx* c_, hipStream_t s_, int cls, double nodes_) : c(c_), s(s_), on(c_->timing_class == cls), nodes(nodes_) {
+    TimedScope(mg_ctx* c_, hipStream_t s_, int cls, double nodes_)
+        : c(c_), s(s_), on(c_->timing_class == cls && cls > 0), nodes(nodes_) {
         if (!on) return;
-        const size_t need = 2 * (c->ev_pending.size() + 1);
-        while (c->ev_pool.size() < need) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
-            c->ev_pool.push_back(e);
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            on = false;
+            return;
         }
-        e0 = int(2 * c->ev_pending.size());
-        (void)hipEventRecord(c->ev_pool[e0], s);
+        (void)hipEventRecord(e0, s);
     }
     ~TimedScope() {
         if (!on) return;
-        (void)hipEventRecord(c->ev_pool[e0 + 1], s);
-        c->ev_pending.push_back({e0, e0 + 1});
+        (void)hipEventRecord(e1, s);
+        c->ev_pending.push_back({e0, e1});
         c->t_nodes += nodes;
     }
 };
 
-void harvest_timing(mg_ctx* c) {
-    for (auto& pr : c->ev_pending) {
+void harvest_pairs(mg_ctx* c, const std::vector<std::pair<hipEvent_t, hipEvent_t>>& pairs) {
+    for (auto& pr : pairs) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, c->ev_pool[pr.first], c->ev_pool[pr.second]) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
             c->t_ms += ms;
             c->t_launches += 1;
         }
     }
+}
+
+void destroy_pairs(std::vector<std::pair<hipEvent_t, hipEvent_t>>& pairs) {
+    for (auto& pr : pairs) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    pairs.clear();
+}
+
+// Called after the stream has been synchronised.
+void harvest_timing(mg_ctx* c) {
+    harvest_pairs(c, c->ev_pending);
+    destroy_pairs(c->ev_pending);
+    if (c->last_graph >= 0) {
+        const auto& e = c->graphs[c->last_graph];
+        harvest_pairs(c, e.timed);
+        c->t_nodes += e.timed_nodes;
+        c->last_graph = -1;
+    }
+}
+
+std::vector<void*> pointer_state(const mg_ctx* c) {
+    std::vector<void*> v;
+    for (const LevelBuf& l : c->lv) {
+        v.push_back(l.u64);
+        v.push_back(l.t64);
+        v.push_back(l.u32);
+        v.push_back(l.t32);
+    }
+    return v;
+}
+
+void restore_pointer_state(mg_ctx* c, const std::vector<void*>& v) {
+    size_t q = 0;
+    for (LevelBuf& l : c->lv) {
+        l.u64 = static_cast<cplx<double>*>(v[q++]);
+        l.t64 = static_cast<cplx<double>*>(v[q++]);
+        l.u32 = static_cast<cplx<float>*>(v[q++]);
+        l.t32 = static_cast<cplx<float>*>(v[q++]);
+    }
+}
+
+// Runs body(stream) once: eagerly, or as a captured graph cached under `params`
+// plus the current buffer assignment. The host-side buffer bookkeeping that the
+// body performs is replayed from the cache on later launches.
+template <typename F>
+mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, F&& body) {
+    // per-kernel event timing needs eager launches (events recorded inside a
+    // capture cannot be queried for elapsed time)
+    if (!c->use_graph || c->timing_class != 0) {
+        body(s);
+        return check_launch(c);
+    }
+    const std::vector<void*> before = pointer_state(c);
+    for (void* p : before) key.push_back(reinterpret_cast<uintptr_t>(p));
+    key.push_back(uintptr_t(c->cur_buf));
+    for (size_t i = 0; i < c->graphs.size(); ++i) {
+        if (c->graphs[i].key != key) continue;
+        restore_pointer_state(c, c->graphs[i].after_ptrs);
+        c->cur_buf = c->graphs[i].after_cur;
+        HM_HIP(hipGraphLaunch(c->graphs[i].exec, s));
+        c->last_graph = int(i);
+        return MG_OK;
+    }
+    if (!c->cap_stream) HM_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    const int cur_before = c->cur_buf;
+    const double nodes_before = c->t_nodes;
+    destroy_pairs(c->ev_pending);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+        body(c->cap_stream);
+        ok = hipStreamEndCapture(c->cap_stream, &graph) == hipSuccess && graph != nullptr;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {
+        // fall back to eager launches for the rest of this handle's life
+        c->use_graph = false;
+        destroy_pairs(c->ev_pending);
+        c->t_nodes = nodes_before;
+        restore_pointer_state(c, before);
+        c->cur_buf = cur_before;
+        body(s);
+        return check_launch(c);
+    }
+    mg_ctx::GraphEntry e;
+    e.key = std::move(key);
+    e.exec = exec;
+    e.timed = std::move(c->ev_pending);
     c->ev_pending.clear();
+    e.timed_nodes = c->t_nodes - nodes_before;
+    c->t_nodes = nodes_before;
+    e.after_ptrs = pointer_state(c);
+    e.after_cur = c->cur_buf;
+    c->graphs.push_back(std::move(e));
+    HM_HIP(hipGraphLaunch(c->graphs.back().exec, s));
+    c->last_graph = int(c->graphs.size() - 1);
+    return MG_OK;
 }
 
 // ---------------------------------------------------------------- cycle
@@ -333,16 +444,18 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
     for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp);
     launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                        vec<T>(Prec<T>::w(lb), lb));
-    launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::f(cb), cb));
-    launch_zero<T>(lc.stream, Prec<T>::u(cb), cb.g.plane * lc.nrhs);
+    launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::f(cb), cb),
+                       vec<T>(Prec<T>::u(cb), cb));
     for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp);
     launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, vec<T>(Prec<T>::u(cb), cb), vec<T>(Prec<T>::u(lb), lb));
     for (int s = 0; s < cp.nu2; ++s) smooth<T>(c, lc, l, cp);
 }
 
-// Zeroes every vector and coefficient plane (ghost frames must read zero).
+// Zeroes every vector and coefficient plane (ghost frames must read zero) and
+// arms the reduction slots with the empty pattern.
 mg_status zero_workspace(mg_ctx* c, hipStream_t s) {
-    launch_zero_real(s, c->ws, (long long)(c->ws_bytes / 4 * 4));
+    launch_fill_words(s, c->ws, (long long)(c->ws_bytes / 4 * 4), 0u);
+    launch_fill_words(s, c->partials, (long long)c->max_blocks * 8 * 8 * c->max_batch, 0xffffffffu);
     return check_launch(c);
 }
 
@@ -441,21 +554,30 @@ mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, in
     }
     HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
     int it = 0;
-    while (running > 0 && it < o.max_cycles) {
-        ++it;
+    uint64_t omega_bits;
+    std::memcpy(&omega_bits, &o.omega, sizeof(omega_bits));
+    const std::vector<uintptr_t> key{uintptr_t(fp32), uintptr_t(cyc), uintptr_t(smoother), uintptr_t(o.nu_pre),
+                                     uintptr_t(o.nu_post), uintptr_t(omega_bits), uintptr_t(nrhs),
+                                     uintptr_t(c->timing_class)};
+    auto body = [&](hipStream_t st) {
+        LaunchCtx l2 = lc;
+        l2.stream = st;
         if (fp32) {
-            LevelBuf& lb = l0;
-            launch_zero<float>(s, lb.u32, lb.g.plane * nrhs);
-            cycle<float>(c, lc, 0, cp);
+            launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
+            cycle<float>(c, l2, 0, cp);
             cplx<double>* xin = c->cur_buf == 0 ? l0.u64 : l0.t64;
             cplx<double>* xout = c->cur_buf == 0 ? l0.t64 : l0.u64;
-            launch_correct_residual(lc, op0, vec<double>(xin, l0), vec<float>(lb.u32, lb), vec<double>(xout, l0),
+            launch_correct_residual(l2, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0), vec<double>(xout, l0),
                                     vec<double>(l0.f64, l0), vec<float>(l0.f32, l0), c->norms);
             c->cur_buf ^= 1;
         } else {
-            cycle<double>(c, lc, 0, cp);
-            launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
+            cycle<double>(c, l2, 0, cp);
+            launch_resnorm<double>(l2, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
         }
+    };
+    while (running > 0 && it < o.max_cycles) {
+        ++it;
+        if (mg_status st = run_cycle_graph(c, s, key, body)) return st;
         if (mg_status st = check_launch(c)) return st;
         HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
         HM_HIP(hipStreamSynchronize(s));
@@ -582,6 +704,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->shift = shift;
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
+    if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
     carve(c, c->ws, n, L, transfer, max_batch, has32);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=
@@ -668,7 +791,12 @@ mg_status mg_grad(mg_handle c, const void* u, const void* grad_u, int nsrc, doub
 
 mg_status mg_destroy(mg_handle c) {
     if (!c) return MG_OK;
-    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    destroy_pairs(c->ev_pending);
+    for (auto& g : c->graphs) {
+        destroy_pairs(g.timed);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    }
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_norms) (void)hipHostFree(c->h_norms);
     if (c->h_active) (void)hipHostFree(c->h_active);
     delete c;
@@ -755,7 +883,7 @@ mg_status level_op_run(mg_ctx* c, int kind, int level, const void* a, const void
         case 3: {  // restrict
             LevelBuf& cb = c->lv[level + 1];
             launch_copy_in<T>(lc, lb.g, a, f32, V(Wv), false, false);
-            launch_restrict<T>(lc, lb.g, cb.g, c->transfer, V(Wv), vec<T>(Prec<T>::f(cb), cb));
+            launch_restrict<T>(lc, lb.g, cb.g, c->transfer, V(Wv), vec<T>(Prec<T>::f(cb), cb), Vec<T>{nullptr, 0});
             launch_copy_out<T>(lc, cb.g, vec<T>(Prec<T>::f(cb), cb), out, f32, false, false);
             break;
         }
@@ -867,7 +995,8 @@ mg_status mg_set_timing(mg_handle c, int kernel_class) {
     if (!c) return MG_E_ARG;
     if (kernel_class < 0 || kernel_class > 4) { c->err = "unknown kernel class"; return MG_E_ARG; }
     c->timing_class = kernel_class;
-    c->ev_pending.clear();
+    destroy_pairs(c->ev_pending);
+    c->last_graph = -1;
     c->t_launches = 0;
     c->t_ms = 0.0;
     c->t_nodes = 0.0;

@@ -178,21 +178,13 @@ __global__ __launch_bounds__(kThreads) void k_lu(int N, cplx<double>* A, int* pi
     }
 }
 
-// One block per right-hand side: permute, unit-lower forward and upper back
-// substitution in FP64 (also for complex64 data, which is widened).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_coarse_solve(Grid g, const cplx<double>* LU, const int* piv, Vec<T> f,
-                                                           Vec<T> u, const int* active) {
-    const int b = blockIdx.x;
-    if (!rhs_active(active, b)) return;
-    __shared__ cplx<double> x[kMaxCoarse];
-    const int m = g.n + 1;
-    const int N = m * m;
-    const int tid = threadIdx.x;
-    const cplx<T>* fb = f.rhs(b);
-    cplx<T>* ub = u.rhs(b);
-    for (int P = tid; P < N; P += kThreads) x[P] = cast<double>(fb[g.at(P % m, P / m)]);
-    __syncthreads();
+// One wavefront per right-hand side: permute, unit-lower forward and upper
+// back substitution in FP64 (complex64 data is widened). Small factors are
+// staged in LDS so that the N sequential steps read no global memory.
+constexpr int kSolveThreads = 64;
+constexpr int kMaxLdsLU = 45 * 45;
+
+__device__ __forceinline__ void lu_substitute(const cplx<double>* LU, const int* piv, cplx<double>* x, int N, int tid) {
     if (tid == 0)
         for (int k = 0; k < N; ++k) {
             const int p = piv[k];
@@ -205,17 +197,41 @@ __global__ __launch_bounds__(kThreads) void k_coarse_solve(Grid g, const cplx<do
     __syncthreads();
     for (int k = 0; k < N; ++k) {
         const cplx<double> xk = x[k];
-        for (int i = k + 1 + tid; i < N; i += kThreads) x[i] = x[i] - LU[(long long)i * N + k] * xk;
+        for (int i = k + 1 + tid; i < N; i += kSolveThreads) x[i] = x[i] - LU[i * N + k] * xk;
         __syncthreads();
     }
     for (int k = N - 1; k >= 0; --k) {
-        if (tid == 0) x[k] = cdiv(x[k], LU[(long long)k * N + k]);
+        if (tid == 0) x[k] = cdiv(x[k], LU[k * N + k]);
         __syncthreads();
         const cplx<double> xk = x[k];
-        for (int i = tid; i < k; i += kThreads) x[i] = x[i] - LU[(long long)i * N + k] * xk;
+        for (int i = tid; i < k; i += kSolveThreads) x[i] = x[i] - LU[i * N + k] * xk;
         __syncthreads();
     }
-    for (int P = tid; P < N; P += kThreads) ub[g.at(P % m, P / m)] = cast<T>(x[P]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSolveThreads) void k_coarse_solve(Grid g, const cplx<double>* LU, const int* piv, Vec<T> f,
+                                                                Vec<T> u, const int* active) {
+    const int b = blockIdx.x;
+    if (!rhs_active(active, b)) return;
+    __shared__ cplx<double> x[kMaxCoarse];
+    __shared__ cplx<double> lu_s[kMaxLdsLU];
+    __shared__ int piv_s[kMaxCoarse];
+    const int m = g.n + 1;
+    const int N = m * m;
+    const int tid = threadIdx.x;
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* ub = u.rhs(b);
+    const bool staged = N * N <= kMaxLdsLU;
+    for (int P = tid; P < N; P += kSolveThreads) {
+        x[P] = cast<double>(fb[g.at(P % m, P / m)]);
+        piv_s[P] = piv[P];
+    }
+    if (staged)
+        for (int q = tid; q < N * N; q += kSolveThreads) lu_s[q] = LU[q];
+    __syncthreads();
+    lu_substitute(staged ? lu_s : LU, piv_s, x, N, tid);
+    for (int P = tid; P < N; P += kSolveThreads) ub[g.at(P % m, P / m)] = cast<T>(x[P]);
 }
 
 __global__ __launch_bounds__(kThreads) void k_stencil_out(Grid g, int r, const cplx<double>* coef, cplx<double>* out) {
@@ -265,7 +281,7 @@ void launch_dense_lu(hipStream_t s, Grid g, int radius, const cplx<double>* coef
 
 template <typename T>
 void launch_coarse_solve(const LaunchCtx& ctx, Grid g, const cplx<double>* lu, const int* piv, Vec<T> f, Vec<T> u) {
-    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(ctx.nrhs), dim3(kThreads), 0, ctx.stream, g, lu, piv, f, u,
+    hipLaunchKernelGGL((k_coarse_solve<T>), dim3(ctx.nrhs), dim3(kSolveThreads), 0, ctx.stream, g, lu, piv, f, u,
                        ctx.active);
 }
 template void launch_coarse_solve<double>(const LaunchCtx&, Grid, const cplx<double>*, const int*, Vec<double>,
