@@ -29,11 +29,12 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per node (one read of every input, one write of every
 # output) of the kernel classes the library can time with HIP events.
-# Class 1: level-0 GMRES Arnoldi apply pass w = A z_J with inner products
-# <z_i, w>, i <= J: reads z_0..z_J and k^2, writes w. In the FP32 cycle a
-# vector is 8 B and k^2 is 4 B: 20 + 8 J bytes, 28 B on average over J = 0, 1, 2.
+# Class 1: the level-0 GMRES(3) pass that orthogonalises the second Arnoldi
+# vector and applies the operator to it: reads w_1, z_0, z_1 and k^2, writes
+# z_2 and w_2 = A z_2 (inner products <z_i, w_2> and ||z_2||^2 ride along).
+# In the FP32 cycle a vector is 8 B and k^2 is 4 B: 3*8 + 4 + 2*8 = 44 B.
 KERNEL_CLASSES = {
-    1: {"name": "level-0 GMRES(3) apply + inner products (complex64)", "bytes_per_node": 28.0},
+    1: {"name": "level-0 GMRES(3) orthogonalise + apply pass (complex64)", "bytes_per_node": 44.0},
 }
 
 

@@ -65,6 +65,11 @@ struct Grid {
 constexpr int kBX = 64;
 constexpr int kBY = 4;
 
+// A level kernel launches at most kMaxPartialBlocks blocks per right-hand
+// side; reductions keep up to 8 partial sums per block in each of two regions.
+constexpr int kMaxPartialBlocks = 640;
+constexpr long long kPartStride = (long long)kMaxPartialBlocks * 8;  // doubles per (region, right-hand side)
+
 // Boundary weight w of a grid line position (1/2 at both ends).
 template <typename T>
 __device__ __forceinline__ T line_w(int i, int n) { return (i == 0 || i == n) ? T(0.5) : T(1); }

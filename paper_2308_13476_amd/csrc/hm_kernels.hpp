@@ -27,12 +27,11 @@ struct RhsNorms {
 // Shared launch parameters of one batched call.
 struct LaunchCtx {
     hipStream_t stream;
-    int nrhs;              // batch size (grid z)
-    const int* active;     // [nrhs] device flags; 0 skips that right-hand side
-    double* partials;      // reduction slots [nrhs][max_blocks][8], armed with the empty pattern
-    unsigned* counters;    // [nrhs] zeroed completion counters
-    long long max_blocks;  // capacity of `partials` per right-hand side
-    int rpt;               // rows per thread of the level kernels
+    int nrhs;           // batch size (grid z)
+    const int* active;  // [nrhs] device flags; 0 skips that right-hand side
+    double* partials;   // per-block partial sums: 2 regions x nrhs_cap x kPartStride doubles
+    int nrhs_cap;       // right-hand sides the partials were sized for
+    int rpt;            // unused: rows per thread follow from the level size
 };
 
 // The operator of one level: analytic on level 0 (from k^2), stored Galerkin
@@ -65,14 +64,14 @@ void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
-// GMRES(3) passes (one smoothing step = residual, 3 x (apply, orth), update).
+// One GMRES(3) smoothing step (§5.3) on A u = f: six passes (residual; apply;
+// two fused orthogonalise + apply passes; last norm; least squares + update).
+// Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
+// products A z. `between(arg, i)` (may be null) is called on the host after
+// the i-th launch of the Arnoldi passes (timing hook).
 template <typename T>
-void launch_gm_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> v0, GmState* st);
-template <typename T>
-void launch_gm_apply(const LaunchCtx&, const LevelOp<T>&, int j, Vec<T> V, Vec<T> w, GmState* st);
-template <typename T>
-void launch_gm_orth(const LaunchCtx&, Grid g, int j, Vec<T> V, Vec<T> w, GmState* st, double breakdown);
-template <typename T> void launch_gm_update(const LaunchCtx&, Grid g, Vec<T> V, Vec<T> u, GmState* st);
+void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
+                       GmState* st, double breakdown, void (*between)(void*, int), void* between_arg);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

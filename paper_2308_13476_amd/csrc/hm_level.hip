@@ -7,7 +7,14 @@ namespace {
 
 constexpr int kThreads = kBX * kBY;
 
-int level_rpt(const Grid& g, int rpt) { return (g.n + 1) < 256 ? 1 : rpt; }
+// Rows per thread: enough that a level grid has at most kMaxPartialBlocks
+// blocks (the reductions read every block's partial sums).
+int level_rpt(const Grid& g, int) {
+    const long long m = g.n + 1;
+    const long long bx = (m + kBX - 1) / kBX;
+    const long long r = (m * bx + (long long)kBY * kMaxPartialBlocks - 1) / ((long long)kBY * kMaxPartialBlocks);
+    return int(r < 1 ? 1 : r);
+}
 
 dim3 level_grid(const Grid& g, int rpt, int nrhs) {
     return dim3((g.n + 1 + kBX - 1) / kBX, (g.n + 1 + kBY * rpt - 1) / (kBY * rpt), nrhs);
@@ -249,184 +256,286 @@ __device__ __noinline__ void gm_least_squares(GmState& st, LsWork& w) {
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void acc_dot(double& re, double& im, cplx<T> a, cplx<T> w) {
+    // conj(a) * w
+    re += double(a.re) * double(w.re) + double(a.im) * double(w.im);
+    im += double(a.re) * double(w.im) - double(a.im) * double(w.re);
+}
+
+__device__ __forceinline__ bool lead_thread() { return block_linear() == 0 && thread_linear() == 0; }
+
+// Pass 1: z0 = f - A u; partials ||z0||^2.
 template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_residual(Op op, Vec<T> u, Vec<T> f, Vec<T> v0, GmState* st,
-                                                          const int* active, int rpt, double* partials,
-                                                          long long pstride, unsigned* counters) {
+__global__ __launch_bounds__(kThreads) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Vec<T> Z, double* pout,
+                                                   const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* ub = u.rhs(b);
     const cplx<T>* fb = f.rhs(b);
-    cplx<T>* vb = v0.p + (long long)(b * 4) * v0.plane;  // Arnoldi block of 4 planes per right-hand side
+    cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     double acc[1] = {0.0};
     for_nodes(op.g, rpt, [&](int i, int j, long long p) {
         const cplx<T> z = fb[p] - op.apply(ub, i, j, p);
-        vb[p] = z;
+        z0[p] = z;
         acc[0] += dnorm2(z);
     });
-    double tot[1];
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0) {
-        GmState& s = st[b];
-        s.beta = sqrt(tot[0]);
-        if (s.beta > 0.0) {
-            s.s[0] = 1.0 / s.beta;
-            s.k = 3;
-            s.arnoldi_done = 0;
-        } else {
-            s.k = 0;
-            s.arnoldi_done = 1;
-        }
-    }
+    block_partials<1>(acc, pout + b * kPartStride);
 }
 
-// w = A z_J (unscaled); inner products <z_i, w> for i <= J.
-template <typename Op, typename T, int J>
-__global__ __launch_bounds__(kThreads) void k_gm_apply(Op op, Vec<T> V, Vec<T> w, GmState* st, const int* active,
-                                                       int rpt, double* partials, long long pstride,
-                                                       unsigned* counters) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
-    const cplx<T>* z[J + 1];
-#pragma unroll
-    for (int i = 0; i <= J; ++i) z[i] = V.p + (long long)(b * 4 + i) * V.plane;
-    cplx<T>* wb = w.rhs(b);
-    double acc[2 * (J + 1)];
-#pragma unroll
-    for (int i = 0; i < 2 * (J + 1); ++i) acc[i] = 0.0;
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<T> a = op.apply(z[J], i, j, p);
-        wb[p] = a;
-        const double wr = double(a.re), wi = double(a.im);
-#pragma unroll
-        for (int q = 0; q <= J; ++q) {
-            const cplx<T> v = z[q][p];
-            const double vr = double(v.re), vi = double(v.im);
-            acc[2 * q] += vr * wr + vi * wi;
-            acc[2 * q + 1] += vr * wi - vi * wr;
-        }
-    });
-    double tot[2 * (J + 1)];
-    if (reduce_last<2 * (J + 1)>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 &&
-        threadIdx.y == 0) {
-        GmState& s = st[b];
-        // H[i][J] = <v_i, A v_J> = s_i s_J <z_i, A z_J>
-        for (int q = 0; q <= J; ++q) {
-            const double sc = s.s[q] * s.s[J];
-            s.hr[q][J] = sc * tot[2 * q];
-            s.hi[q][J] = sc * tot[2 * q + 1];
-        }
-    }
-}
-
-// z_{J+1} = s_J w - sum_i H[i][J] s_i z_i, its norm -> H[J+1][J]; at the end of
-// the Arnoldi process (breakdown or J = 2) the least-squares problem is solved.
-template <typename T, int J>
-__global__ __launch_bounds__(kThreads) void k_gm_orth(Grid g, Vec<T> V, Vec<T> w, GmState* st, double breakdown,
-                                                      const int* active, int rpt, double* partials,
-                                                      long long pstride, unsigned* counters) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
-    const GmState& s0 = st[b];
-    const T sJ = T(s0.s[J]);
-    cplx<T> c[J + 1];
-#pragma unroll
-    for (int q = 0; q <= J; ++q) c[q] = {T(s0.hr[q][J] * s0.s[q]), T(s0.hi[q][J] * s0.s[q])};
-    const cplx<T>* z[J + 1];
-#pragma unroll
-    for (int q = 0; q <= J; ++q) z[q] = V.p + (long long)(b * 4 + q) * V.plane;
-    cplx<T>* znew = V.p + (long long)(b * 4 + J + 1) * V.plane;
-    const cplx<T>* wb = w.rhs(b);
-    double acc[1] = {0.0};
-    for_nodes(g, rpt, [&](int i, int j, long long p) {
-        cplx<T> v = sJ * wb[p];
-#pragma unroll
-        for (int q = 0; q <= J; ++q) {
-            const cplx<T> zq = z[q][p];
-            v.re -= c[q].re * zq.re - c[q].im * zq.im;
-            v.im -= c[q].re * zq.im + c[q].im * zq.re;
-        }
-        if (J < 2) znew[p] = v;
-        acc[0] += dnorm2(v);
-    });
-    double tot[1];
-    __shared__ LsWork ls;
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0) {
-        GmState& s = st[b];
-        const double hn = sqrt(tot[0]);
-        s.hr[J + 1][J] = hn;
-        s.hi[J + 1][J] = 0.0;
-        bool done = false;
-        if (hn <= breakdown * s.beta) {
-            s.k = J + 1;
-            done = true;
-        } else {
-            s.s[J + 1] = 1.0 / hn;
-            if (J == 2) {
-                s.k = 3;
-                done = true;
-            }
-        }
-        if (done) {
-            s.arnoldi_done = 1;
-            gm_least_squares(s, ls);
-        }
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_update(Grid g, Vec<T> V, Vec<T> u, GmState* st, const int* active,
-                                                        int rpt) {
+// Pass 2: beta = ||z0|| from pass 1; w0 = A z0 (unnormalised); partials <z0, w0>.
+template <typename Op, typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
+                                                    int nblk_in, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
-    const GmState& s = st[b];
-    const int k = s.k;
-    if (k == 0) return;
+    double t[1];
+    reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
+    const double beta = sqrt(t[0]);
+    const bool go = beta > 0.0;  // false for a zero or non-finite residual
+    if (lead_thread()) {
+        GmState& S = st[b];
+        S.beta = beta;
+        S.s[0] = go ? 1.0 / beta : 0.0;
+        S.k = go ? 3 : 0;
+        S.arnoldi_done = go ? 0 : 1;
+    }
+    if (!go) return;
+    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    cplx<T>* wb = Wout.rhs(b);
+    double acc[2] = {0.0, 0.0};
+    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
+        const cplx<T> w = op.apply(z0, i, j, p);
+        wb[p] = w;
+        acc_dot(acc[0], acc[1], z0[p], w);
+    });
+    block_partials<2>(acc, pout + b * kPartStride);
+}
+
+// Passes 3 and 4 (J = 1, 2): finish Arnoldi column J-1 from the previous
+// pass's sums, then build z_J = s_{J-1} w_{J-1} - sum_i H[i][J-1] s_i z_i,
+// w_J = A z_J (z_J recomputed at the stencil neighbours), partials
+// ||z_J||^2 and <z_i, w_J> for i <= J.
+template <typename Op, typename T, int J>
+__global__ __launch_bounds__(kThreads) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
+                                                    double breakdown, const double* pin, int nblk_in, double* pout,
+                                                    const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
+    constexpr int KIN = (J == 1) ? 2 : 5;  // previous pass: [||z_{J-1}||^2 (J > 1)], <z_i, w_{J-1}>
+    double t[KIN];
+    reduce_partials<KIN>(pin + b * kPartStride, nblk_in, t);
+    const GmState& S0 = st[b];
+    double sv[J];  // s_0 .. s_{J-1}
+    sv[0] = S0.s[0];
+    double hn = 0.0;
+    bool broke = false;
+    if (J > 1) {
+        hn = sqrt(t[0]);
+        broke = !(hn > breakdown * S0.beta);
+        sv[J - 1] = broke ? 0.0 : 1.0 / hn;
+    }
+    constexpr int D0 = (J > 1) ? 1 : 0;  // offset of the inner products in t
+    double hr[J], hi[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        hr[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q];
+        hi[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q + 1];
+    }
+    if (lead_thread()) {
+        GmState& S = st[b];
+        if (J > 1) {
+            S.hr[J - 1][J - 2] = hn;
+            S.hi[J - 1][J - 2] = 0.0;
+            if (broke) {
+                S.k = J - 1;
+                S.arnoldi_done = 1;
+            } else {
+                S.s[J - 1] = sv[J - 1];
+            }
+        }
+        if (!broke)
+#pragma unroll
+            for (int q = 0; q < J; ++q) {
+                S.hr[q][J - 1] = hr[q];
+                S.hi[q][J - 1] = hi[q];
+            }
+    }
+    if (broke) return;
+    // z_J = s_{J-1} w_{J-1} - sum_q c_q z_q with c_q = H[q][J-1] s_q
+    const T sJ1 = T(sv[J - 1]);
+    cplx<T> c[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) c[q] = {T(hr[q] * sv[q]), T(hi[q] * sv[q])};
+    const cplx<T>* z[J];
+#pragma unroll
+    for (int q = 0; q < J; ++q) z[q] = Z.p + (long long)(b * 4 + q) * Z.plane;
+    cplx<T>* zJ = Z.p + (long long)(b * 4 + J) * Z.plane;
+    const cplx<T>* wi = Win.rhs(b);
+    cplx<T>* wo = Wout.rhs(b);
+    auto znew = [&](long long q) {
+        cplx<T> v = sJ1 * wi[q];
+#pragma unroll
+        for (int a = 0; a < J; ++a) {
+            const cplx<T> zq = z[a][q];
+            v.re -= c[a].re * zq.re - c[a].im * zq.im;
+            v.im -= c[a].re * zq.im + c[a].im * zq.re;
+        }
+        return v;
+    };
+    double acc[1 + 2 * (J + 1)];
+#pragma unroll
+    for (int q = 0; q < 1 + 2 * (J + 1); ++q) acc[q] = 0.0;
+    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
+        const cplx<T> zp = znew(p);
+        const cplx<T> w = op.apply_at(znew, i, j, p);
+        zJ[p] = zp;
+        wo[p] = w;
+        acc[0] += dnorm2(zp);
+#pragma unroll
+        for (int q = 0; q < J; ++q) acc_dot(acc[1 + 2 * q], acc[2 + 2 * q], z[q][p], w);
+        acc_dot(acc[1 + 2 * J], acc[2 + 2 * J], zp, w);
+    });
+    block_partials<1 + 2 * (J + 1)>(acc, pout + b * kPartStride);
+}
+
+// Pass 5: finish column 2 from pass 4, and the norm of z_3 = s_2 w_2 - sum H[i][2] s_i z_i.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_o3(Grid g, Vec<T> Z, Vec<T> Win, GmState* st, double breakdown,
+                                                    const double* pin, int nblk_in, double* pout, const int* active,
+                                                    int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
+    double t[7];
+    reduce_partials<7>(pin + b * kPartStride, nblk_in, t);
+    const GmState& S0 = st[b];
+    const double hn = sqrt(t[0]);
+    const bool broke = !(hn > breakdown * S0.beta);
+    const double s2 = broke ? 0.0 : 1.0 / hn;
+    const double sv[3] = {S0.s[0], S0.s[1], s2};
+    double hr[3], hi[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        hr[q] = sv[q] * s2 * t[1 + 2 * q];
+        hi[q] = sv[q] * s2 * t[2 + 2 * q];
+    }
+    if (lead_thread()) {
+        GmState& S = st[b];
+        S.hr[2][1] = hn;
+        S.hi[2][1] = 0.0;
+        if (broke) {
+            S.k = 2;
+            S.arnoldi_done = 1;
+        } else {
+            S.s[2] = s2;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                S.hr[q][2] = hr[q];
+                S.hi[q][2] = hi[q];
+            }
+        }
+    }
+    if (broke) return;
     cplx<T> c[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = {T(s.yr[q]), T(s.yi[q])};
-    const cplx<T>* z0 = V.p + (long long)(b * 4) * V.plane;
+    for (int q = 0; q < 3; ++q) c[q] = {T(hr[q] * sv[q]), T(hi[q] * sv[q])};
+    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    const cplx<T>* wi = Win.rhs(b);
+    const T sT = T(s2);
+    double acc[1] = {0.0};
+    for_nodes(g, rpt, [&](int, int, long long p) {
+        cplx<T> v = sT * wi[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cplx<T> zq = z0[p + (long long)a * Z.plane];
+            v.re -= c[a].re * zq.re - c[a].im * zq.im;
+            v.im -= c[a].re * zq.im + c[a].im * zq.re;
+        }
+        acc[0] += dnorm2(v);
+    });
+    block_partials<1>(acc, pout + b * kPartStride);
+}
+
+// Pass 6: H[3][2] from pass 5 (unless the Arnoldi process stopped early), the
+// small least-squares problem (one thread, shared memory), u += sum y_i s_i z_i.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, GmState* st, const double* pin,
+                                                   int nblk_in, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    const int k0 = st[b].k;
+    if (k0 == 0) return;
+    const bool full = !st[b].arnoldi_done;
+    double t[1] = {0.0};
+    if (full) reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
+    __shared__ GmState S;
+    __shared__ LsWork ls;
+    if (thread_linear() == 0) {
+        S = st[b];
+        if (full) {
+            S.hr[3][2] = sqrt(t[0]);
+            S.hi[3][2] = 0.0;
+            S.k = 3;
+        }
+        gm_least_squares(S, ls);
+    }
+    __syncthreads();
+    const int k = S.k;
+    cplx<T> c[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[q] = {T(S.yr[q]), T(S.yi[q])};
+    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     cplx<T>* ub = u.rhs(b);
-    for_nodes(g, rpt, [&](int i, int j, long long p) {
+    for_nodes(g, rpt, [&](int, int, long long p) {
         cplx<T> x = ub[p];
-        for (int q = 0; q < k; ++q) x = cfma(x, c[q], z0[p + (long long)q * V.plane]);
+        x = cfma(x, c[0], z0[p]);
+        if (k > 1) x = cfma(x, c[1], z0[p + Z.plane]);
+        if (k > 2) x = cfma(x, c[2], z0[p + 2 * Z.plane]);
         ub[p] = x;
     });
 }
 
 // ---------------------------------------------------------------- norms
 template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_resnorm(Op op, Vec<T> x, Vec<T> f, RhsNorms* norms, const int* active,
-                                                      int rpt, double* partials, long long pstride,
-                                                      unsigned* counters) {
+__global__ __launch_bounds__(kThreads) void k_resnorm(Op op, Vec<T> x, Vec<T> f, double* pout, const int* active,
+                                                      int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     double acc[1] = {0.0};
     for_nodes(op.g, rpt, [&](int i, int j, long long p) { acc[0] += dnorm2(fb[p] - op.apply(xb, i, j, p)); });
-    double tot[1];
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0)
-        norms[b].r2 = tot[0];
+    block_partials<1>(acc, pout + b * kPartStride);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_norm(Grid g, Vec<T> f, RhsNorms* norms, const int* active, int rpt,
-                                                   double* partials, long long pstride, unsigned* counters) {
+__global__ __launch_bounds__(kThreads) void k_norm(Grid g, Vec<T> f, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* fb = f.rhs(b);
     double acc[1] = {0.0};
     for_nodes(g, rpt, [&](int, int, long long p) { acc[0] += dnorm2(fb[p]); });
-    double tot[1];
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0)
-        norms[b].f2 = tot[0];
+    block_partials<1>(acc, pout + b * kPartStride);
+}
+
+// One block per right-hand side: sum the partials of a norm kernel into
+// norms[b].f2 (which = 0) or norms[b].r2 (which = 1).
+__global__ __launch_bounds__(kThreads) void k_sum_norms(const double* pin, int nblk_in, RhsNorms* norms, int which,
+                                                        const int* active) {
+    const int b = blockIdx.x;
+    if (!rhs_active(active, b)) return;
+    double t[1];
+    reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
+    if (thread_linear() == 0) {
+        if (which == 0) norms[b].f2 = t[0];
+        else norms[b].r2 = t[0];
+    }
 }
 
 // ---------------------------------------------------------------- refinement
 __global__ __launch_bounds__(kThreads) void k_refine_residual(FineOp<double> op, Vec<double> x, Vec<double> f,
-                                                              Vec<float> r32, RhsNorms* norms, const int* active,
-                                                              int rpt, double* partials, long long pstride,
-                                                              unsigned* counters) {
+                                                              Vec<float> r32, double* pout, const int* active,
+                                                              int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<double>* xb = x.rhs(b);
@@ -438,16 +547,12 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(FineOp<double> op,
         rb[p] = cast<float>(r);
         acc[0] += dnorm2(r);
     });
-    double tot[1];
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0)
-        norms[b].r2 = tot[0];
+    block_partials<1>(acc, pout + b * kPartStride);
 }
 
 __global__ __launch_bounds__(kThreads) void k_correct_residual(FineOp<double> op, Vec<double> x_in, Vec<float> e,
                                                                Vec<double> x_out, Vec<double> f, Vec<float> r32,
-                                                               RhsNorms* norms, const int* active, int rpt,
-                                                               double* partials, long long pstride,
-                                                               unsigned* counters) {
+                                                               double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<double>* xb = x_in.rhs(b);
@@ -463,9 +568,7 @@ __global__ __launch_bounds__(kThreads) void k_correct_residual(FineOp<double> op
         rb[p] = cast<float>(r);
         acc[0] += dnorm2(r);
     });
-    double tot[1];
-    if (reduce_last<1>(acc, partials + b * pstride, counters + b, tot) && threadIdx.x == 0 && threadIdx.y == 0)
-        norms[b].r2 = tot[0];
+    block_partials<1>(acc, pout + b * kPartStride);
 }
 
 // ---------------------------------------------------------------- layout
@@ -533,7 +636,6 @@ __global__ __launch_bounds__(kThreads) void k_grad_k2(Grid g, double h, const do
 
 // ======================================================================= launchers
 #define HM_ACTIVE ctx.active
-#define HM_RED ctx.partials, ctx.max_blocks * 8, ctx.counters
 
 template <typename T>
 void launch_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> y) {
@@ -586,53 +688,44 @@ void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transf
                            HM_ACTIVE, rpt);
 }
 
-template <typename T>
-void launch_gm_residual(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> v0, GmState* st) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
-    with_op(lop, [&](auto op) {
-        hipLaunchKernelGGL((k_gm_residual<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, u, f, v0, st, HM_ACTIVE, rpt, HM_RED);
-    });
+double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }
+
+int level_blocks(const Grid& g, int rpt) {
+    const dim3 d = level_grid(g, rpt, 1);
+    return int(d.x * d.y);
 }
 
 template <typename T>
-void launch_gm_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, int j, Vec<T> V, Vec<T> w, GmState* st) {
+void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
+                       Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg) {
     const int rpt = level_rpt(lop.g, ctx.rpt);
+    const dim3 grid = level_grid(lop.g, rpt, ctx.nrhs);
+    const int nb = level_blocks(lop.g, rpt);
+    double* A = region(ctx, 0);
+    double* B = region(ctx, 1);
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const dim3 grid = level_grid(lop.g, rpt, ctx.nrhs);
-        if (j == 0)
-            hipLaunchKernelGGL((k_gm_apply<Op, T, 0>), grid, dim3(kBX, kBY), 0, ctx.stream, op, V, w, st, HM_ACTIVE,
-                               rpt, HM_RED);
-        else if (j == 1)
-            hipLaunchKernelGGL((k_gm_apply<Op, T, 1>), grid, dim3(kBX, kBY), 0, ctx.stream, op, V, w, st, HM_ACTIVE,
-                               rpt, HM_RED);
-        else
-            hipLaunchKernelGGL((k_gm_apply<Op, T, 2>), grid, dim3(kBX, kBY), 0, ctx.stream, op, V, w, st, HM_ACTIVE,
-                               rpt, HM_RED);
+        hipLaunchKernelGGL((k_gm_r<Op, T>), grid, dim3(kBX, kBY), 0, ctx.stream, op, u, f, Z, A, HM_ACTIVE, rpt);
+        if (between) between(between_arg, 0);
+        hipLaunchKernelGGL((k_gm_a0<Op, T>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wa, st, A, nb, B, HM_ACTIVE,
+                           rpt);
+        if (between) between(between_arg, 1);
+        hipLaunchKernelGGL((k_gm_oa<Op, T, 1>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wa, Wb, st, breakdown, B,
+                           nb, A, HM_ACTIVE, rpt);
+        if (between) between(between_arg, 2);
+        hipLaunchKernelGGL((k_gm_oa<Op, T, 2>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wb, Wa, st, breakdown, A,
+                           nb, B, HM_ACTIVE, rpt);
+        if (between) between(between_arg, 3);
     });
-}
-
-template <typename T>
-void launch_gm_orth(const LaunchCtx& ctx, Grid g, int j, Vec<T> V, Vec<T> w, GmState* st, double breakdown) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    const dim3 grid = level_grid(g, rpt, ctx.nrhs);
-    if (j == 0)
-        hipLaunchKernelGGL((k_gm_orth<T, 0>), grid, dim3(kBX, kBY), 0, ctx.stream, g, V, w, st, breakdown, HM_ACTIVE,
-                           rpt, HM_RED);
-    else if (j == 1)
-        hipLaunchKernelGGL((k_gm_orth<T, 1>), grid, dim3(kBX, kBY), 0, ctx.stream, g, V, w, st, breakdown, HM_ACTIVE,
-                           rpt, HM_RED);
-    else
-        hipLaunchKernelGGL((k_gm_orth<T, 2>), grid, dim3(kBX, kBY), 0, ctx.stream, g, V, w, st, breakdown, HM_ACTIVE,
-                           rpt, HM_RED);
-}
-
-template <typename T>
-void launch_gm_update(const LaunchCtx& ctx, Grid g, Vec<T> V, Vec<T> u, GmState* st) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    hipLaunchKernelGGL((k_gm_update<T>), level_grid(g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, g, V, u, st,
+    hipLaunchKernelGGL((k_gm_o3<T>), grid, dim3(kBX, kBY), 0, ctx.stream, lop.g, Z, Wa, st, breakdown, B, nb, A,
                        HM_ACTIVE, rpt);
+    hipLaunchKernelGGL((k_gm_u<T>), grid, dim3(kBX, kBY), 0, ctx.stream, lop.g, Z, u, st, A, nb, HM_ACTIVE, rpt);
+}
+
+void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
+    // 64 x 4 threads: the block reduction indexes wavefronts by threadIdx.y
+    hipLaunchKernelGGL(k_sum_norms, dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, region(ctx, 0), nb, norms, which,
+                       HM_ACTIVE);
 }
 
 template <typename T>
@@ -640,15 +733,17 @@ void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T
     const int rpt = level_rpt(lop.g, ctx.rpt);
     with_op(lop, [&](auto op) {
         hipLaunchKernelGGL((k_resnorm<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, x, f, norms, HM_ACTIVE, rpt, HM_RED);
+                           ctx.stream, op, x, f, region(ctx, 0), HM_ACTIVE, rpt);
     });
+    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
 }
 
 template <typename T>
 void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
     const int rpt = level_rpt(g, ctx.rpt);
-    hipLaunchKernelGGL((k_norm<T>), level_grid(g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, g, f, norms,
-                       HM_ACTIVE, rpt, HM_RED);
+    hipLaunchKernelGGL((k_norm<T>), level_grid(g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, g, f,
+                       region(ctx, 0), HM_ACTIVE, rpt);
+    launch_sum_norms(ctx, level_blocks(g, rpt), norms, 0);
 }
 
 void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
@@ -656,7 +751,8 @@ void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Ve
     const int rpt = level_rpt(lop.g, ctx.rpt);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     hipLaunchKernelGGL(k_refine_residual, level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, op, x, f,
-                       r32, norms, HM_ACTIVE, rpt, HM_RED);
+                       r32, region(ctx, 0), HM_ACTIVE, rpt);
+    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
 }
 
 void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
@@ -664,7 +760,8 @@ void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, V
     const int rpt = level_rpt(lop.g, ctx.rpt);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     hipLaunchKernelGGL(k_correct_residual, level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, op, x_in,
-                       e, x_out, f, r32, norms, HM_ACTIVE, rpt, HM_RED);
+                       e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, rpt);
+    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
 }
 
 template <typename T>
@@ -722,10 +819,8 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_jacobi<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, double);        \
     template void launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>);                \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
-    template void launch_gm_residual<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, GmState*); \
-    template void launch_gm_apply<T>(const LaunchCtx&, const LevelOp<T>&, int, Vec<T>, Vec<T>, GmState*);       \
-    template void launch_gm_orth<T>(const LaunchCtx&, Grid, int, Vec<T>, Vec<T>, GmState*, double);             \
-    template void launch_gm_update<T>(const LaunchCtx&, Grid, Vec<T>, Vec<T>, GmState*);                        \
+    template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
+                                       Vec<T>, GmState*, double, void (*)(void*, int), void*);                  \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

@@ -85,81 +85,25 @@ __device__ __forceinline__ void for_nodes(const Grid& g, int rpt, F&& f) {
 
 __device__ __forceinline__ bool rhs_active(const int* active, int b) { return active == nullptr || active[b] != 0; }
 
-// Grid-wide reduction slots. Every slot of the partials array holds the
-// "empty" bit pattern between uses (armed at setup). A block publishes its
-// partial with an agent-scope atomic store; the last block to arrive reads
-// every slot with agent-scope atomic loads, waiting (bounded) until the slot
-// is no longer empty, and re-arms it. Coherence of each atomic location is
-// all this needs: no fence, hence no L2 write-back or invalidation in the
-// streaming kernels that end in a reduction.
-constexpr unsigned long long kEmptySlot = ~0ull;
-constexpr int kSlotSpinLimit = 1 << 20;
+// Grid-wide reductions without atomics. A producer kernel writes one partial
+// sum per block (`block_partials`); the kernel launched after it reduces all
+// partials itself (`reduce_partials`, identical order in every block, hence
+// deterministic), the kernel boundary making the partials visible. The
+// partials of right-hand side b and region r live at
+// partials + (r * nrhs_cap + b) * kPartStride.
 
-__device__ __forceinline__ void slot_publish(double* slot, double v) {
-    unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    if (v != v) bits = 0x7ff8000000000000ull;  // canonical NaN: never the empty pattern
-    __hip_atomic_store(reinterpret_cast<unsigned long long*>(slot), bits, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+__device__ __forceinline__ int thread_linear() { return threadIdx.y * kBX + threadIdx.x; }
 
-// `budget` bounds the total wait of the calling thread over all its slots.
-__device__ __forceinline__ double slot_take(double* slot, int& budget) {
-    unsigned long long* p = reinterpret_cast<unsigned long long*>(slot);
-    unsigned long long bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    while (bits == kEmptySlot && budget > 0) {
-        --budget;
-        __builtin_amdgcn_s_sleep(1);
-        bits = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __hip_atomic_store(p, kEmptySlot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // a slot that never filled (cannot happen while every block publishes) yields NaN,
-    // which the residual checks report as divergence instead of hanging
-    return bits == kEmptySlot ? __longlong_as_double(0x7ff8000000000000ll) : __longlong_as_double((long long)bits);
-}
-
-// Deterministic grid-wide reduction of K doubles per thread for right-hand
-// side blockIdx.z: block sums go to `partials`; the last block to arrive
-// (agent-scope atomic counter) adds them in block order and returns true with
-// the totals in `tot` (all its threads). The counter is re-armed.
+// Block sum for 64 x 4 thread blocks (wavefront = threadIdx.y).
 template <int K>
-__device__ bool reduce_last(double (&v)[K], double* partials, unsigned* counter, double (&tot)[K]) {
+__device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
     __shared__ double sh[K][kBY];
-    __shared__ int s_last;
     const int lane = threadIdx.x, wave = threadIdx.y;
-    const int tid = wave * kBX + lane;
+    __syncthreads();  // sh may still be read from an earlier call
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double s = wave_sum(v[k]);
-        if (lane == 0) sh[k][wave] = s;
-    }
-    __syncthreads();
-    const long long nblk = (long long)gridDim.x * gridDim.y;
-    const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-    if (tid == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBY; ++w) s += sh[k][w];
-            slot_publish(&partials[blk * K + k], s);
-        }
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == (unsigned)(nblk - 1));
-    }
-    __syncthreads();
-    if (!s_last) return false;
-    double acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    int budget = kSlotSpinLimit;
-    for (long long q = tid; q < nblk; q += kBX * kBY) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += slot_take(&partials[q * K + k], budget);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const double s = wave_sum(acc[k]);
         if (lane == 0) sh[k][wave] = s;
     }
     __syncthreads();
@@ -170,8 +114,30 @@ __device__ bool reduce_last(double (&v)[K], double* partials, unsigned* counter,
         for (int w = 0; w < kBY; ++w) s += sh[k][w];
         tot[k] = s;
     }
-    if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+}
+
+// Writes this block's K sums to out[block * K + k].
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* out) {
+    double tot[K];
+    block_sum<K>(v, tot);
+    if (thread_linear() == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[block_linear() * K + k] = tot[k];
+    }
+}
+
+// Sums the K partials of nblk producer blocks; every thread gets the totals.
+template <int K>
+__device__ __forceinline__ void reduce_partials(const double* in, int nblk, double (&tot)[K]) {
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int q = thread_linear(); q < nblk; q += kBX * kBY) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += in[q * K + k];
+    }
+    block_sum<K>(acc, tot);
 }
 
 }  // namespace hm

@@ -45,10 +45,6 @@ int default_rpt(int n) {
     return n >= 2048 ? 4 : n >= 512 ? 2 : 1;
 }
 
-long long blocks_per_rhs(const Grid& g, int rpt) {
-    const int r = (g.n + 1) < 256 ? 1 : rpt;
-    return (long long)((g.n + 1 + kBX - 1) / kBX) * ((g.n + 1 + kBY * r - 1) / (kBY * r));
-}
 
 struct LevelBuf {
     Grid g;
@@ -89,8 +85,6 @@ struct mg_ctx {
     RhsNorms* norms = nullptr;
     int* active = nullptr;
     double* partials = nullptr;
-    unsigned* counters = nullptr;
-    long long max_blocks = 0;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     // host mirrors (pinned)
@@ -149,7 +143,6 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     Carver cv{base};
     if (c) c->lv.assign(L, LevelBuf());
     int r = 1;
-    long long max_blocks = 0;
     const int rpt = default_rpt(n);
     const size_t B = size_t(max_batch);
     for (int l = 0; l < L; ++l) {
@@ -176,7 +169,6 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
             lb.w32 = cv.take<cplx<float>>(B * pl * 8);
             lb.V32 = cv.take<cplx<float>>(4 * B * pl * 8);
         }
-        max_blocks = std::max(max_blocks, blocks_per_rhs(g, rpt));
         r = next_radius(lb.radius, transfer);
     }
     const Grid g0 = make_grid(n);
@@ -189,8 +181,7 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     GmState* gm = cv.take<GmState>(B * sizeof(GmState));
     RhsNorms* norms = cv.take<RhsNorms>(B * sizeof(RhsNorms));
     int* active = cv.take<int>(B * 4);
-    unsigned* counters = cv.take<unsigned>(B * 4);
-    double* partials = cv.take<double>(B * size_t(max_blocks) * 8 * 8);
+    double* partials = cv.take<double>(2 * B * size_t(kPartStride) * 8);
     if (c) {
         c->k2_64 = k64;
         c->k2_32 = k32;
@@ -199,9 +190,7 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
         c->gm = gm;
         c->norms = norms;
         c->active = active;
-        c->counters = counters;
         c->partials = partials;
-        c->max_blocks = max_blocks;
         c->rpt = rpt;
     }
     return align_up(cv.off, kAlign);
@@ -260,7 +249,7 @@ template <typename T>
 Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
-    return LaunchCtx{s, nrhs, c->active, c->partials, c->counters, c->max_blocks, c->rpt};
+    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->rpt};
 }
 
 // Timing hook: events around the launches of one kernel class.
@@ -420,17 +409,35 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
         return;
     }
-    Vec<T> V = vec<T>(Prec<T>::V(lb), lb);
-    Vec<T> W = vec<T>(Prec<T>::w(lb), lb);
-    launch_gm_residual<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), V, c->gm);
-    for (int j = 0; j < 3; ++j) {
-        {
-            TimedScope ts(c, lc.stream, l == 0 ? 1 : (l == 1 ? 4 : -1), nodes);
-            launch_gm_apply<T>(lc, op, j, V, W, c->gm);
+    // timing hook: events around the fused orthogonalise + apply pass that
+    // builds the third Arnoldi vector (launch 3 of the step)
+    struct Hook {
+        mg_ctx* c;
+        hipStream_t s;
+        double nodes;
+        hipEvent_t e0 = nullptr;
+        static void cb(void* arg, int i) {
+            Hook* h = static_cast<Hook*>(arg);
+            if (i == 2) {
+                if (hipEventCreate(&h->e0) == hipSuccess) (void)hipEventRecord(h->e0, h->s);
+                else h->e0 = nullptr;
+            } else if (i == 3 && h->e0) {
+                hipEvent_t e1;
+                if (hipEventCreate(&e1) == hipSuccess) {
+                    (void)hipEventRecord(e1, h->s);
+                    h->c->ev_pending.push_back({h->e0, e1});
+                    h->c->t_nodes += h->nodes;
+                } else {
+                    (void)hipEventDestroy(h->e0);
+                }
+                h->e0 = nullptr;
+            }
         }
-        launch_gm_orth<T>(lc, lb.g, j, V, W, c->gm, Prec<T>::breakdown);
-    }
-    launch_gm_update<T>(lc, lb.g, V, vec<T>(Prec<T>::u(lb), lb), c->gm);
+    } hook{c, lc.stream, nodes};
+    const bool timed = c->timing_class == (l == 0 ? 1 : (l == 1 ? 4 : -1));
+    launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
+                         vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::t_ref(lb), lb), c->gm, Prec<T>::breakdown,
+                         timed ? &Hook::cb : nullptr, &hook);
 }
 
 template <typename T>
@@ -451,11 +458,9 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
     for (int s = 0; s < cp.nu2; ++s) smooth<T>(c, lc, l, cp);
 }
 
-// Zeroes every vector and coefficient plane (ghost frames must read zero) and
-// arms the reduction slots with the empty pattern.
+// Zeroes every vector and coefficient plane (ghost frames must read zero).
 mg_status zero_workspace(mg_ctx* c, hipStream_t s) {
     launch_fill_words(s, c->ws, (long long)(c->ws_bytes / 4 * 4), 0u);
-    launch_fill_words(s, c->partials, (long long)c->max_blocks * 8 * 8 * c->max_batch, 0xffffffffu);
     return check_launch(c);
 }
 
