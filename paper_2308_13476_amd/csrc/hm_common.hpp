@@ -63,7 +63,8 @@ struct Grid {
 // Blocks are 64 x 4 threads (one wavefront per row of 64 nodes); a block
 // covers 64 columns and 4 * rows_per_thread rows of a level.
 constexpr int kBX = 64;
-constexpr int kBY = 4;
+constexpr int kBY = 4;      // short blocks (register-heavy stencils, small grids)
+constexpr int kMaxBY = 16;  // tall blocks (light kernels on large grids)
 
 // A level kernel launches at most kMaxPartialBlocks blocks per right-hand
 // side; reductions keep up to 8 partial sums per block in each of two regions.

@@ -102,6 +102,33 @@ void launch_fill_words(hipStream_t, void* p, long long bytes, unsigned value);
 void launch_grad_k2(const LaunchCtx&, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,
                     double* grad_k2_dense);
 
+// Coarse tail: the whole sub-cycle on levels l0 .. L-1 (at most kMaxTailLevels)
+// in one launch, one workgroup per right-hand side. Pointers are those of
+// right-hand side 0; Z holds 4 planes per right-hand side.
+constexpr int kMaxTailLevels = 8;
+template <typename T>
+struct TailLevel {
+    Grid g;
+    int radius;
+    const cplx<T>* coef;
+    cplx<T>* u;
+    cplx<T>* f;
+    cplx<T>* t;
+    cplx<T>* w;
+    cplx<T>* Z;
+};
+template <typename T>
+struct TailArgs {
+    int nlev;
+    TailLevel<T> lv[kMaxTailLevels];
+    const cplx<double>* lu;  // LU factor of the coarsest operator (FP64)
+    const int* piv;
+    int gamma, smoother, nu1, nu2;  // smoother: 0 Jacobi, 1 GMRES(3)
+    double omega, breakdown;
+    int bez;
+};
+template <typename T> void launch_tail(const LaunchCtx&, const TailArgs<T>&);
+
 // ---- setup ----
 // Padded k^2 planes from the caller's dense array (FP64 and optionally FP32).
 void launch_k2_in(hipStream_t, Grid g, const double* k2_dense, double* k2_64, float* k2_32);

@@ -1,5 +1,8 @@
 // Level kernels of the multigrid cycle: operator apply, residual, weighted
 // Jacobi, transfers, GMRES(3) passes, norms, FP32 refinement, adjoint gradient.
+#include <cstdlib>
+#include <type_traits>
+
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -7,17 +10,58 @@ namespace {
 
 constexpr int kThreads = kBX * kBY;
 
+// Block height. 64 x 4 blocks by default: measured on the n = 1024 level
+// grid, 64 x 16 blocks were slower (at 70+ VGPRs one 16-wave block fills a
+// CU, so the capped block count runs in more than two rounds).
+// HELMG_TALL_BLOCKS=1 selects 64 x 16 blocks for light kernels on grids of
+// 256 or more intervals.
+bool tall_blocks_enabled() {
+    static const bool on = [] {
+        const char* e = std::getenv("HELMG_TALL_BLOCKS");
+        return e && std::atoi(e) != 0;
+    }();
+    return on;
+}
+int block_rows(const Grid& g, bool heavy) { return (tall_blocks_enabled() && !heavy && g.n >= 256) ? kMaxBY : kBY; }
+
 // Rows per thread: enough that a level grid has at most kMaxPartialBlocks
 // blocks (the reductions read every block's partial sums).
-int level_rpt(const Grid& g, int) {
+int level_rpt(const Grid& g, int by) {
     const long long m = g.n + 1;
     const long long bx = (m + kBX - 1) / kBX;
-    const long long r = (m * bx + (long long)kBY * kMaxPartialBlocks - 1) / ((long long)kBY * kMaxPartialBlocks);
+    const long long r = (m * bx + (long long)by * kMaxPartialBlocks - 1) / ((long long)by * kMaxPartialBlocks);
     return int(r < 1 ? 1 : r);
 }
 
-dim3 level_grid(const Grid& g, int rpt, int nrhs) {
-    return dim3((g.n + 1 + kBX - 1) / kBX, (g.n + 1 + kBY * rpt - 1) / (kBY * rpt), nrhs);
+dim3 level_grid(const Grid& g, int rpt, int nrhs, int by) {
+    return dim3((g.n + 1 + kBX - 1) / kBX, (g.n + 1 + by * rpt - 1) / (by * rpt), nrhs);
+}
+
+struct Geom {
+    int by, rpt, nblk;
+    dim3 grid, block;
+};
+
+Geom geom(const Grid& g, bool heavy, int nrhs) {
+    Geom q;
+    q.by = block_rows(g, heavy);
+    q.rpt = level_rpt(g, q.by);
+    q.grid = level_grid(g, q.rpt, nrhs, q.by);
+    q.block = dim3(kBX, q.by);
+    q.nblk = int(q.grid.x * q.grid.y);
+    return q;
+}
+
+// Calls f(integral_constant<int, BY>) for the runtime block height; kernels
+// of register-heavy operators are only instantiated with short blocks.
+template <bool kHeavy = false, typename F>
+void with_by(int by, F&& f) {
+    if constexpr (kHeavy) {
+        f(std::integral_constant<int, kBY>{});
+    } else {
+        if (by == kMaxBY) f(std::integral_constant<int, kMaxBY>{});
+        else f(std::integral_constant<int, kBY>{});
+    }
 }
 
 // Calls f(op) with the concrete operator type of the level.
@@ -40,8 +84,8 @@ __device__ __forceinline__ double dnorm2(cplx<T> z) {
 }
 
 // ---------------------------------------------------------------- operator
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_apply(Op op, Vec<T> x, Vec<T> y, const int* active, int rpt) {
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_apply(Op op, Vec<T> x, Vec<T> y, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* xb = x.rhs(b);
@@ -49,8 +93,8 @@ __global__ __launch_bounds__(kThreads) void k_apply(Op op, Vec<T> x, Vec<T> y, c
     for_nodes(op.g, rpt, [&](int i, int j, long long p) { yb[p] = op.apply(xb, i, j, p); });
 }
 
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_residual(Op op, Vec<T> x, Vec<T> f, Vec<T> r, const int* active,
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_residual(Op op, Vec<T> x, Vec<T> f, Vec<T> r, const int* active,
                                                        int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -61,8 +105,8 @@ __global__ __launch_bounds__(kThreads) void k_residual(Op op, Vec<T> x, Vec<T> f
 }
 
 // Weighted Jacobi of §3: y = x + (omega diag(A))^{-1} (f - A x).
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_jacobi(Op op, Vec<T> x, Vec<T> f, Vec<T> y, T inv_omega,
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_jacobi(Op op, Vec<T> x, Vec<T> f, Vec<T> y, T inv_omega,
                                                      const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -81,8 +125,8 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
 // fine node (2I, 2J); fine ghosts are zero, which truncates at the boundary.
 // The coarse iterate that the next cycle starts from (zero) is written in the
 // same pass when `uc` is given.
-template <typename T, bool kBez>
-__global__ __launch_bounds__(kThreads) void k_restrict(Grid gf, Grid gc, Vec<T> r, Vec<T> fc, Vec<T> uc,
+template <typename T, bool kBez, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_restrict(Grid gf, Grid gc, Vec<T> r, Vec<T> fc, Vec<T> uc,
                                                        const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -141,8 +185,8 @@ __device__ __forceinline__ void taps(int i, bool bez, T (&w)[3]) {
     }
 }
 
-template <typename T, bool kBez>
-__global__ __launch_bounds__(kThreads) void k_prolong_add(Grid gc, Grid gf, Vec<T> e, Vec<T> u, const int* active,
+template <typename T, bool kBez, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_prolong_add(Grid gc, Grid gf, Vec<T> e, Vec<T> u, const int* active,
                                                           int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -177,85 +221,6 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(Grid gc, Grid gf, Vec<
 // Gram-Schmidt with the new vector's norm computed directly (two passes per
 // Arnoldi step: apply + inner products, orthogonalise + norm).
 
-// Least-squares min || beta e1 - H y || over the k Arnoldi columns by complex
-// Givens rotations, then y_i s_i into st.yr / st.yi. Run by one thread on a
-// shared-memory copy of H so that it costs the calling kernel no registers.
-struct LsWork {
-    double hr[4][3], hi[4][3], gr[4], gi[4], cs[3], sr[3], si[3], yr[3], yi[3];
-};
-
-__device__ __noinline__ void gm_least_squares(GmState& st, LsWork& w) {
-    const int k = st.k;
-#pragma unroll 1
-    for (int a = 0; a < 4; ++a)
-#pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
-            w.hr[a][c] = st.hr[a][c];
-            w.hi[a][c] = st.hi[a][c];
-        }
-    w.gr[0] = st.beta;
-    w.gi[0] = 0.0;
-    for (int a = 1; a < 4; ++a) w.gr[a] = w.gi[a] = 0.0;
-#pragma unroll 1
-    for (int j = 0; j < k; ++j) {
-#pragma unroll 1
-        for (int i = 0; i < j; ++i) {  // earlier rotations on column j
-            const double ar = w.hr[i][j], ai = w.hi[i][j], br = w.hr[i + 1][j], bi = w.hi[i + 1][j];
-            const double c = w.cs[i], s_r = w.sr[i], s_i = w.si[i];
-            // a' = c a + s b ; b' = -conj(s) a + c b
-            w.hr[i][j] = c * ar + (s_r * br - s_i * bi);
-            w.hi[i][j] = c * ai + (s_r * bi + s_i * br);
-            w.hr[i + 1][j] = -(s_r * ar + s_i * ai) + c * br;
-            w.hi[i + 1][j] = -(s_r * ai - s_i * ar) + c * bi;
-        }
-        const double ar = w.hr[j][j], ai = w.hi[j][j], br = w.hr[j + 1][j], bi = w.hi[j + 1][j];
-        const double na = hypot(ar, ai), nb = hypot(br, bi);
-        const double rho = hypot(na, nb);
-        double c, s_r, s_i;
-        if (na == 0.0) {
-            c = 0.0;
-            s_r = br / nb;
-            s_i = -bi / nb;
-        } else {
-            c = na / rho;
-            // s = (a / |a|) conj(b) / rho
-            const double ur = ar / na, ui = ai / na;
-            s_r = (ur * br + ui * bi) / rho;
-            s_i = (ui * br - ur * bi) / rho;
-        }
-        w.cs[j] = c;
-        w.sr[j] = s_r;
-        w.si[j] = s_i;
-        w.hr[j][j] = c * ar + (s_r * br - s_i * bi);
-        w.hi[j][j] = c * ai + (s_r * bi + s_i * br);
-        w.hr[j + 1][j] = 0.0;
-        w.hi[j + 1][j] = 0.0;
-        const double g0r = w.gr[j], g0i = w.gi[j], g1r = w.gr[j + 1], g1i = w.gi[j + 1];
-        w.gr[j] = c * g0r + (s_r * g1r - s_i * g1i);
-        w.gi[j] = c * g0i + (s_r * g1i + s_i * g1r);
-        w.gr[j + 1] = -(s_r * g0r + s_i * g0i) + c * g1r;
-        w.gi[j + 1] = -(s_r * g0i - s_i * g0r) + c * g1i;
-    }
-#pragma unroll 1
-    for (int j = k - 1; j >= 0; --j) {
-        double tr = w.gr[j], ti = w.gi[j];
-#pragma unroll 1
-        for (int c = j + 1; c < k; ++c) {
-            tr -= w.hr[j][c] * w.yr[c] - w.hi[j][c] * w.yi[c];
-            ti -= w.hr[j][c] * w.yi[c] + w.hi[j][c] * w.yr[c];
-        }
-        const double dr = w.hr[j][j], di = w.hi[j][j];
-        const double inv = 1.0 / (dr * dr + di * di);
-        w.yr[j] = (tr * dr + ti * di) * inv;
-        w.yi[j] = (ti * dr - tr * di) * inv;
-    }
-#pragma unroll 1
-    for (int j = 0; j < 3; ++j) {
-        st.yr[j] = (j < k) ? w.yr[j] * st.s[j] : 0.0;
-        st.yi[j] = (j < k) ? w.yi[j] * st.s[j] : 0.0;
-    }
-}
-
 template <typename T>
 __device__ __forceinline__ void acc_dot(double& re, double& im, cplx<T> a, cplx<T> w) {
     // conj(a) * w
@@ -266,8 +231,8 @@ __device__ __forceinline__ void acc_dot(double& re, double& im, cplx<T> a, cplx<
 __device__ __forceinline__ bool lead_thread() { return block_linear() == 0 && thread_linear() == 0; }
 
 // Pass 1: z0 = f - A u; partials ||z0||^2.
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Vec<T> Z, double* pout,
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Vec<T> Z, double* pout,
                                                    const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -284,8 +249,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Ve
 }
 
 // Pass 2: beta = ||z0|| from pass 1; w0 = A z0 (unnormalised); partials <z0, w0>.
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
                                                     int nblk_in, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -316,8 +281,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
 // pass's sums, then build z_J = s_{J-1} w_{J-1} - sum_i H[i][J-1] s_i z_i,
 // w_J = A z_J (z_J recomputed at the stencil neighbours), partials
 // ||z_J||^2 and <z_i, w_J> for i <= J.
-template <typename Op, typename T, int J>
-__global__ __launch_bounds__(kThreads) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
+template <typename Op, typename T, int J, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
                                                     const int* active, int rpt) {
     const int b = blockIdx.z;
@@ -400,8 +365,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
 }
 
 // Pass 5: finish column 2 from pass 4, and the norm of z_3 = s_2 w_2 - sum H[i][2] s_i z_i.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_o3(Grid g, Vec<T> Z, Vec<T> Win, GmState* st, double breakdown,
+template <typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_o3(Grid g, Vec<T> Z, Vec<T> Win, GmState* st, double breakdown,
                                                     const double* pin, int nblk_in, double* pout, const int* active,
                                                     int rpt) {
     const int b = blockIdx.z;
@@ -458,8 +423,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_o3(Grid g, Vec<T> Z, Vec<T> Win
 
 // Pass 6: H[3][2] from pass 5 (unless the Arnoldi process stopped early), the
 // small least-squares problem (one thread, shared memory), u += sum y_i s_i z_i.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, GmState* st, const double* pin,
+template <typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, GmState* st, const double* pin,
                                                    int nblk_in, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -496,8 +461,8 @@ __global__ __launch_bounds__(kThreads) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, G
 }
 
 // ---------------------------------------------------------------- norms
-template <typename Op, typename T>
-__global__ __launch_bounds__(kThreads) void k_resnorm(Op op, Vec<T> x, Vec<T> f, double* pout, const int* active,
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_resnorm(Op op, Vec<T> x, Vec<T> f, double* pout, const int* active,
                                                       int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
@@ -508,8 +473,8 @@ __global__ __launch_bounds__(kThreads) void k_resnorm(Op op, Vec<T> x, Vec<T> f,
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_norm(Grid g, Vec<T> f, double* pout, const int* active, int rpt) {
+template <typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_norm(Grid g, Vec<T> f, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* fb = f.rhs(b);
@@ -533,7 +498,8 @@ __global__ __launch_bounds__(kThreads) void k_sum_norms(const double* pin, int n
 }
 
 // ---------------------------------------------------------------- refinement
-__global__ __launch_bounds__(kThreads) void k_refine_residual(FineOp<double> op, Vec<double> x, Vec<double> f,
+template <int BY>
+__global__ __launch_bounds__(kBX * BY) void k_refine_residual(FineOp<double> op, Vec<double> x, Vec<double> f,
                                                               Vec<float> r32, double* pout, const int* active,
                                                               int rpt) {
     const int b = blockIdx.z;
@@ -550,7 +516,8 @@ __global__ __launch_bounds__(kThreads) void k_refine_residual(FineOp<double> op,
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
-__global__ __launch_bounds__(kThreads) void k_correct_residual(FineOp<double> op, Vec<double> x_in, Vec<float> e,
+template <int BY>
+__global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op, Vec<double> x_in, Vec<float> e,
                                                                Vec<double> x_out, Vec<double> f, Vec<float> r32,
                                                                double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
@@ -572,8 +539,8 @@ __global__ __launch_bounds__(kThreads) void k_correct_residual(FineOp<double> op
 }
 
 // ---------------------------------------------------------------- layout
-template <typename T, typename S>
-__global__ __launch_bounds__(kThreads) void k_copy_in(Grid g, const cplx<S>* src, Vec<T> dst, int scale_w,
+template <typename T, typename S, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_copy_in(Grid g, const cplx<S>* src, Vec<T> dst, int scale_w,
                                                       int conj_, int rpt) {
     const int b = blockIdx.z;
     const long long m = g.n + 1;
@@ -587,8 +554,8 @@ __global__ __launch_bounds__(kThreads) void k_copy_in(Grid g, const cplx<S>* src
     });
 }
 
-template <typename T, typename S>
-__global__ __launch_bounds__(kThreads) void k_copy_out(Grid g, Vec<T> src, cplx<S>* dst, int scale_w, int conj_,
+template <typename T, typename S, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_copy_out(Grid g, Vec<T> src, cplx<S>* dst, int scale_w, int conj_,
                                                        int rpt) {
     const int b = blockIdx.z;
     const long long m = g.n + 1;
@@ -637,89 +604,85 @@ __global__ __launch_bounds__(kThreads) void k_grad_k2(Grid g, double h, const do
 // ======================================================================= launchers
 #define HM_ACTIVE ctx.active
 
+// Launches KERNEL<..., BY> with the geometry q (BY = q.by).
+#define HM_LAUNCH(q, KERNEL_BY, ...)                                                                       \
+    with_by((q).by, [&](auto byc) {                                                                        \
+        constexpr int BY = decltype(byc)::value;                                                          \
+        hipLaunchKernelGGL(KERNEL_BY, (q).grid, (q).block, 0, ctx.stream, __VA_ARGS__);                   \
+    })
+// Same for kernels templated on an operator type Op (heavy operators: short blocks only).
+#define HM_LAUNCH_OP(q, KERNEL_BY, ...)                                                                    \
+    with_by<Op::kHeavy>((q).by, [&](auto byc) {                                                            \
+        constexpr int BY = decltype(byc)::value;                                                          \
+        hipLaunchKernelGGL(KERNEL_BY, (q).grid, (q).block, 0, ctx.stream, __VA_ARGS__);                   \
+    })
+
 template <typename T>
 void launch_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> y) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
     with_op(lop, [&](auto op) {
-        hipLaunchKernelGGL((k_apply<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, x, y, HM_ACTIVE, rpt);
+        using Op = decltype(op);
+        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        HM_LAUNCH_OP(q, (k_apply<Op, T, BY>), op, x, y, HM_ACTIVE, q.rpt);
     });
 }
 
 template <typename T>
 void launch_residual(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> r) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
     with_op(lop, [&](auto op) {
-        hipLaunchKernelGGL((k_residual<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, x, f, r, HM_ACTIVE, rpt);
+        using Op = decltype(op);
+        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        HM_LAUNCH_OP(q, (k_residual<Op, T, BY>), op, x, f, r, HM_ACTIVE, q.rpt);
     });
 }
 
 template <typename T>
 void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
     with_op(lop, [&](auto op) {
-        hipLaunchKernelGGL((k_jacobi<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, x, f, y, T(inv_omega), HM_ACTIVE, rpt);
+        using Op = decltype(op);
+        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        HM_LAUNCH_OP(q, (k_jacobi<Op, T, BY>), op, x, f, y, T(inv_omega), HM_ACTIVE, q.rpt);
     });
 }
 
 template <typename T>
 void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc) {
-    const int rpt = level_rpt(coarse, ctx.rpt);
-    const dim3 grid = level_grid(coarse, rpt, ctx.nrhs);
-    if (transfer == 0)
-        hipLaunchKernelGGL((k_restrict<T, true>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc, uc,
-                           HM_ACTIVE, rpt);
-    else
-        hipLaunchKernelGGL((k_restrict<T, false>), grid, dim3(kBX, kBY), 0, ctx.stream, fine, coarse, r, fc, uc,
-                           HM_ACTIVE, rpt);
+    const Geom q = geom(coarse, false, ctx.nrhs);
+    if (transfer == 0) HM_LAUNCH(q, (k_restrict<T, true, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
+    else HM_LAUNCH(q, (k_restrict<T, false, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
 }
 
 template <typename T>
 void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u) {
-    const int rpt = level_rpt(fine, ctx.rpt);
-    const dim3 grid = level_grid(fine, rpt, ctx.nrhs);
-    if (transfer == 0)
-        hipLaunchKernelGGL((k_prolong_add<T, true>), grid, dim3(kBX, kBY), 0, ctx.stream, coarse, fine, e, u,
-                           HM_ACTIVE, rpt);
-    else
-        hipLaunchKernelGGL((k_prolong_add<T, false>), grid, dim3(kBX, kBY), 0, ctx.stream, coarse, fine, e, u,
-                           HM_ACTIVE, rpt);
+    const Geom q = geom(fine, false, ctx.nrhs);
+    if (transfer == 0) HM_LAUNCH(q, (k_prolong_add<T, true, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
+    else HM_LAUNCH(q, (k_prolong_add<T, false, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
 }
 
 double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }
 
-int level_blocks(const Grid& g, int rpt) {
-    const dim3 d = level_grid(g, rpt, 1);
-    return int(d.x * d.y);
-}
-
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
-    const dim3 grid = level_grid(lop.g, rpt, ctx.nrhs);
-    const int nb = level_blocks(lop.g, rpt);
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
+    const Geom qv = geom(lop.g, false, ctx.nrhs);  // vector-only passes
+    int nb_op = 0;
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        hipLaunchKernelGGL((k_gm_r<Op, T>), grid, dim3(kBX, kBY), 0, ctx.stream, op, u, f, Z, A, HM_ACTIVE, rpt);
+        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        nb_op = q.nblk;
+        const int nb = q.nblk;
+        HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 0);
-        hipLaunchKernelGGL((k_gm_a0<Op, T>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wa, st, A, nb, B, HM_ACTIVE,
-                           rpt);
+        HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb, B, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 1);
-        hipLaunchKernelGGL((k_gm_oa<Op, T, 1>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wa, Wb, st, breakdown, B,
-                           nb, A, HM_ACTIVE, rpt);
+        HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 2);
-        hipLaunchKernelGGL((k_gm_oa<Op, T, 2>), grid, dim3(kBX, kBY), 0, ctx.stream, op, Z, Wb, Wa, st, breakdown, A,
-                           nb, B, HM_ACTIVE, rpt);
+        HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 3);
     });
-    hipLaunchKernelGGL((k_gm_o3<T>), grid, dim3(kBX, kBY), 0, ctx.stream, lop.g, Z, Wa, st, breakdown, B, nb, A,
-                       HM_ACTIVE, rpt);
-    hipLaunchKernelGGL((k_gm_u<T>), grid, dim3(kBX, kBY), 0, ctx.stream, lop.g, Z, u, st, A, nb, HM_ACTIVE, rpt);
+    HM_LAUNCH(qv, (k_gm_o3<T, BY>), lop.g, Z, Wa, st, breakdown, B, nb_op, A, HM_ACTIVE, qv.rpt);
+    HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, A, qv.nblk, HM_ACTIVE, qv.rpt);
 }
 
 void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
@@ -730,63 +693,60 @@ void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) 
 
 template <typename T>
 void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, RhsNorms* norms) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
+    int nb = 0;
     with_op(lop, [&](auto op) {
-        hipLaunchKernelGGL((k_resnorm<decltype(op), T>), level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0,
-                           ctx.stream, op, x, f, region(ctx, 0), HM_ACTIVE, rpt);
+        using Op = decltype(op);
+        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        nb = q.nblk;
+        HM_LAUNCH_OP(q, (k_resnorm<Op, T, BY>), op, x, f, region(ctx, 0), HM_ACTIVE, q.rpt);
     });
-    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
+    launch_sum_norms(ctx, nb, norms, 1);
 }
 
 template <typename T>
 void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    hipLaunchKernelGGL((k_norm<T>), level_grid(g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, g, f,
-                       region(ctx, 0), HM_ACTIVE, rpt);
-    launch_sum_norms(ctx, level_blocks(g, rpt), norms, 0);
+    const Geom q = geom(g, false, ctx.nrhs);
+    HM_LAUNCH(q, (k_norm<T, BY>), g, f, region(ctx, 0), HM_ACTIVE, q.rpt);
+    launch_sum_norms(ctx, q.nblk, norms, 0);
 }
 
 void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
                             Vec<float> r32, RhsNorms* norms) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
+    const Geom q = geom(lop.g, false, ctx.nrhs);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    hipLaunchKernelGGL(k_refine_residual, level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, op, x, f,
-                       r32, region(ctx, 0), HM_ACTIVE, rpt);
-    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
+    HM_LAUNCH(q, (k_refine_residual<BY>), op, x, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
+    launch_sum_norms(ctx, q.nblk, norms, 1);
 }
 
 void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
                              Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms) {
-    const int rpt = level_rpt(lop.g, ctx.rpt);
+    const Geom q = geom(lop.g, false, ctx.nrhs);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    hipLaunchKernelGGL(k_correct_residual, level_grid(lop.g, rpt, ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, op, x_in,
-                       e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, rpt);
-    launch_sum_norms(ctx, level_blocks(lop.g, rpt), norms, 1);
+    HM_LAUNCH(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
+    launch_sum_norms(ctx, q.nblk, norms, 1);
 }
 
 template <typename T>
 void launch_copy_in(const LaunchCtx& ctx, Grid g, const void* src, bool src_is_f32, Vec<T> dst, bool scale_w,
                     bool conj) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    const dim3 grid = level_grid(g, rpt, ctx.nrhs);
+    const Geom q = geom(g, false, ctx.nrhs);
     if (src_is_f32)
-        hipLaunchKernelGGL((k_copy_in<T, float>), grid, dim3(kBX, kBY), 0, ctx.stream, g,
-                           static_cast<const cplx<float>*>(src), dst, int(scale_w), int(conj), rpt);
+        HM_LAUNCH(q, (k_copy_in<T, float, BY>), g, static_cast<const cplx<float>*>(src), dst, int(scale_w),
+                  int(conj), q.rpt);
     else
-        hipLaunchKernelGGL((k_copy_in<T, double>), grid, dim3(kBX, kBY), 0, ctx.stream, g,
-                           static_cast<const cplx<double>*>(src), dst, int(scale_w), int(conj), rpt);
+        HM_LAUNCH(q, (k_copy_in<T, double, BY>), g, static_cast<const cplx<double>*>(src), dst, int(scale_w),
+                  int(conj), q.rpt);
 }
 
 template <typename T>
 void launch_copy_out(const LaunchCtx& ctx, Grid g, Vec<T> src, void* dst, bool dst_is_f32, bool scale_w, bool conj) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    const dim3 grid = level_grid(g, rpt, ctx.nrhs);
+    const Geom q = geom(g, false, ctx.nrhs);
     if (dst_is_f32)
-        hipLaunchKernelGGL((k_copy_out<T, float>), grid, dim3(kBX, kBY), 0, ctx.stream, g, src,
-                           static_cast<cplx<float>*>(dst), int(scale_w), int(conj), rpt);
+        HM_LAUNCH(q, (k_copy_out<T, float, BY>), g, src, static_cast<cplx<float>*>(dst), int(scale_w), int(conj),
+                  q.rpt);
     else
-        hipLaunchKernelGGL((k_copy_out<T, double>), grid, dim3(kBX, kBY), 0, ctx.stream, g, src,
-                           static_cast<cplx<double>*>(dst), int(scale_w), int(conj), rpt);
+        HM_LAUNCH(q, (k_copy_out<T, double, BY>), g, src, static_cast<cplx<double>*>(dst), int(scale_w), int(conj),
+                  q.rpt);
 }
 
 template <typename T>
@@ -808,8 +768,8 @@ void launch_fill_words(hipStream_t s, void* p, long long bytes, unsigned value) 
 
 void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,
                     double* grad_k2_dense) {
-    const int rpt = level_rpt(g, ctx.rpt);
-    hipLaunchKernelGGL(k_grad_k2, level_grid(g, rpt, 1), dim3(kBX, kBY), 0, ctx.stream, g, h, k2, u, mu,
+    const int rpt = level_rpt(g, kBY);
+    hipLaunchKernelGGL(k_grad_k2, level_grid(g, rpt, 1, kBY), dim3(kBX, kBY), 0, ctx.stream, g, h, k2, u, mu,
                        grad_k2_dense, ctx.nrhs, rpt);
 }
 

@@ -17,6 +17,7 @@ namespace hm {
 // is the edge weight 1).
 template <typename T>
 struct FineOp {
+    static constexpr bool kHeavy = false;  // few registers: tall blocks
     Grid g;
     const T* k2;
     T ih2;    // 1 / h^2
@@ -51,6 +52,7 @@ struct FineOp {
 // offset; ghost coefficients are zero.
 template <typename T, int R>
 struct StencilOp {
+    static constexpr bool kHeavy = R >= 2;  // 25/49-point stencils: many registers, short blocks
     Grid g;
     const cplx<T>* __restrict__ coef;
     static constexpr int D = 2 * R + 1;
@@ -76,8 +78,9 @@ template <typename F>
 __device__ __forceinline__ void for_nodes(const Grid& g, int rpt, F&& f) {
     const int i = blockIdx.x * kBX + threadIdx.x;
     if (i > g.n) return;
+    const int by = blockDim.y;
     for (int rr = 0; rr < rpt; ++rr) {
-        const int j = (blockIdx.y * rpt + rr) * kBY + threadIdx.y;
+        const int j = (blockIdx.y * rpt + rr) * by + threadIdx.y;
         if (j > g.n) return;
         f(i, j, g.at(i, j));
     }
@@ -95,10 +98,10 @@ __device__ __forceinline__ bool rhs_active(const int* active, int b) { return ac
 __device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
 __device__ __forceinline__ int thread_linear() { return threadIdx.y * kBX + threadIdx.x; }
 
-// Block sum for 64 x 4 thread blocks (wavefront = threadIdx.y).
+// Block sum for 64 x BY thread blocks, BY <= kMaxBY (wavefront = threadIdx.y).
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
-    __shared__ double sh[K][kBY];
+    __shared__ double sh[K][kMaxBY];
     const int lane = threadIdx.x, wave = threadIdx.y;
     __syncthreads();  // sh may still be read from an earlier call
 #pragma unroll
@@ -107,11 +110,11 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
         if (lane == 0) sh[k][wave] = s;
     }
     __syncthreads();
+    const int nw = blockDim.y;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBY; ++w) s += sh[k][w];
+        for (int w = 0; w < nw; ++w) s += sh[k][w];
         tot[k] = s;
     }
 }
@@ -133,11 +136,120 @@ __device__ __forceinline__ void reduce_partials(const double* in, int nblk, doub
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int q = thread_linear(); q < nblk; q += kBX * kBY) {
+    const int nt = blockDim.x * blockDim.y;
+    for (int q = thread_linear(); q < nblk; q += nt) {
 #pragma unroll
         for (int k = 0; k < K; ++k) acc[k] += in[q * K + k];
     }
     block_sum<K>(acc, tot);
+}
+
+// Least-squares min || beta e1 - H y || over the k Arnoldi columns by complex
+// Givens rotations, then y_i s_i into st.yr / st.yi. Run by one thread on a
+// shared-memory copy of H so that it costs the calling kernel no registers.
+struct LsWork {
+    double hr[4][3], hi[4][3], gr[4], gi[4], cs[3], sr[3], si[3], yr[3], yi[3];
+};
+
+static __device__ __noinline__ void gm_least_squares(GmState& st, LsWork& w) {
+    const int k = st.k;
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a)
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+            w.hr[a][c] = st.hr[a][c];
+            w.hi[a][c] = st.hi[a][c];
+        }
+    w.gr[0] = st.beta;
+    w.gi[0] = 0.0;
+    for (int a = 1; a < 4; ++a) w.gr[a] = w.gi[a] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+#pragma unroll 1
+        for (int i = 0; i < j; ++i) {  // earlier rotations on column j
+            const double ar = w.hr[i][j], ai = w.hi[i][j], br = w.hr[i + 1][j], bi = w.hi[i + 1][j];
+            const double c = w.cs[i], s_r = w.sr[i], s_i = w.si[i];
+            // a' = c a + s b ; b' = -conj(s) a + c b
+            w.hr[i][j] = c * ar + (s_r * br - s_i * bi);
+            w.hi[i][j] = c * ai + (s_r * bi + s_i * br);
+            w.hr[i + 1][j] = -(s_r * ar + s_i * ai) + c * br;
+            w.hi[i + 1][j] = -(s_r * ai - s_i * ar) + c * bi;
+        }
+        const double ar = w.hr[j][j], ai = w.hi[j][j], br = w.hr[j + 1][j], bi = w.hi[j + 1][j];
+        const double na = hypot(ar, ai), nb = hypot(br, bi);
+        const double rho = hypot(na, nb);
+        double c, s_r, s_i;
+        if (na == 0.0) {
+            c = 0.0;
+            s_r = br / nb;
+            s_i = -bi / nb;
+        } else {
+            c = na / rho;
+            // s = (a / |a|) conj(b) / rho
+            const double ur = ar / na, ui = ai / na;
+            s_r = (ur * br + ui * bi) / rho;
+            s_i = (ui * br - ur * bi) / rho;
+        }
+        w.cs[j] = c;
+        w.sr[j] = s_r;
+        w.si[j] = s_i;
+        w.hr[j][j] = c * ar + (s_r * br - s_i * bi);
+        w.hi[j][j] = c * ai + (s_r * bi + s_i * br);
+        w.hr[j + 1][j] = 0.0;
+        w.hi[j + 1][j] = 0.0;
+        const double g0r = w.gr[j], g0i = w.gi[j], g1r = w.gr[j + 1], g1i = w.gi[j + 1];
+        w.gr[j] = c * g0r + (s_r * g1r - s_i * g1i);
+        w.gi[j] = c * g0i + (s_r * g1i + s_i * g1r);
+        w.gr[j + 1] = -(s_r * g0r + s_i * g0i) + c * g1r;
+        w.gi[j + 1] = -(s_r * g0i - s_i * g0r) + c * g1i;
+    }
+#pragma unroll 1
+    for (int j = k - 1; j >= 0; --j) {
+        double tr = w.gr[j], ti = w.gi[j];
+#pragma unroll 1
+        for (int c = j + 1; c < k; ++c) {
+            tr -= w.hr[j][c] * w.yr[c] - w.hi[j][c] * w.yi[c];
+            ti -= w.hr[j][c] * w.yi[c] + w.hi[j][c] * w.yr[c];
+        }
+        const double dr = w.hr[j][j], di = w.hi[j][j];
+        const double inv = 1.0 / (dr * dr + di * di);
+        w.yr[j] = (tr * dr + ti * di) * inv;
+        w.yi[j] = (ti * dr - tr * di) * inv;
+    }
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+        st.yr[j] = (j < k) ? w.yr[j] * st.s[j] : 0.0;
+        st.yi[j] = (j < k) ? w.yi[j] * st.s[j] : 0.0;
+    }
+}
+
+// Forward and back substitution with a row-major LU factor (unit lower L,
+// upper U, row swaps piv[k] <-> k applied in order) for one right-hand side x
+// held in LDS; all nthreads threads of the block take part.
+__device__ __forceinline__ void lu_substitute(const cplx<double>* LU, const int* piv, cplx<double>* x, int N, int tid,
+                                              int nthreads) {
+    if (tid == 0)
+        for (int k = 0; k < N; ++k) {
+            const int p = piv[k];
+            if (p != k) {
+                const cplx<double> t = x[k];
+                x[k] = x[p];
+                x[p] = t;
+            }
+        }
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        const cplx<double> xk = x[k];
+        for (int i = k + 1 + tid; i < N; i += nthreads) x[i] = x[i] - LU[i * N + k] * xk;
+        __syncthreads();
+    }
+    for (int k = N - 1; k >= 0; --k) {
+        if (tid == 0) x[k] = cdiv(x[k], LU[k * N + k]);
+        __syncthreads();
+        const cplx<double> xk = x[k];
+        for (int i = tid; i < k; i += nthreads) x[i] = x[i] - LU[i * N + k] * xk;
+        __syncthreads();
+    }
 }
 
 }  // namespace hm

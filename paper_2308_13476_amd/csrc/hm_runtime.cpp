@@ -109,6 +109,8 @@ struct mg_ctx {
     int last_graph = -1;
     hipStream_t cap_stream = nullptr;
     bool use_graph = true;
+    // first level run by the single-workgroup coarse tail (-1: none)
+    int tail_level = -1;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -441,7 +443,32 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
 }
 
 template <typename T>
+void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams& cp) {
+    TailArgs<T> a{};
+    a.nlev = c->L - l0;
+    for (int q = 0; q < a.nlev; ++q) {
+        LevelBuf& lb = c->lv[l0 + q];
+        a.lv[q] = TailLevel<T>{lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::u(lb), Prec<T>::f(lb), Prec<T>::t_ref(lb),
+                               Prec<T>::w(lb), Prec<T>::V(lb)};
+    }
+    a.lu = c->dense;
+    a.piv = c->piv;
+    a.gamma = cp.gamma;
+    a.smoother = cp.smoother == MG_JACOBI ? 0 : 1;
+    a.nu1 = cp.nu1;
+    a.nu2 = cp.nu2;
+    a.omega = cp.omega;
+    a.breakdown = Prec<T>::breakdown;
+    a.bez = c->transfer == MG_TRANSFER_BEZIER;
+    launch_tail<T>(lc, a);
+}
+
+template <typename T>
 void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
+    if (l == c->tail_level) {
+        launch_tail_from<T>(c, lc, l, cp);
+        return;
+    }
     LevelBuf& lb = c->lv[l];
     if (l == c->L - 1) {
         launch_coarse_solve<T>(lc, lb.g, c->dense, c->piv, vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::u(lb), lb));
@@ -710,6 +737,20 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
+    {
+        // HELMG_TAIL_N = t > 0: levels of at most t intervals run in the
+        // single-workgroup tail. Off by default: on the n = 1024 benchmark the
+        // tail (about 4.5 us per in-block phase) was no faster than one launch
+        // per operation on those levels.
+        int tail_n = 0;
+        if (const char* e = std::getenv("HELMG_TAIL_N")) tail_n = std::atoi(e);
+        c->tail_level = -1;
+        for (int l = 1; l < L && tail_n > 0; ++l)
+            if ((n >> l) <= tail_n && L - l <= kMaxTailLevels) {
+                c->tail_level = l;
+                break;
+            }
+    }
     carve(c, c->ws, n, L, transfer, max_batch, has32);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=

@@ -184,31 +184,6 @@ __global__ __launch_bounds__(kThreads) void k_lu(int N, cplx<double>* A, int* pi
 constexpr int kSolveThreads = 64;
 constexpr int kMaxLdsLU = 45 * 45;
 
-__device__ __forceinline__ void lu_substitute(const cplx<double>* LU, const int* piv, cplx<double>* x, int N, int tid) {
-    if (tid == 0)
-        for (int k = 0; k < N; ++k) {
-            const int p = piv[k];
-            if (p != k) {
-                const cplx<double> t = x[k];
-                x[k] = x[p];
-                x[p] = t;
-            }
-        }
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-        const cplx<double> xk = x[k];
-        for (int i = k + 1 + tid; i < N; i += kSolveThreads) x[i] = x[i] - LU[i * N + k] * xk;
-        __syncthreads();
-    }
-    for (int k = N - 1; k >= 0; --k) {
-        if (tid == 0) x[k] = cdiv(x[k], LU[k * N + k]);
-        __syncthreads();
-        const cplx<double> xk = x[k];
-        for (int i = tid; i < k; i += kSolveThreads) x[i] = x[i] - LU[i * N + k] * xk;
-        __syncthreads();
-    }
-}
-
 template <typename T>
 __global__ __launch_bounds__(kSolveThreads) void k_coarse_solve(Grid g, const cplx<double>* LU, const int* piv, Vec<T> f,
                                                                 Vec<T> u, const int* active) {
@@ -230,7 +205,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_coarse_solve(Grid g, const cp
     if (staged)
         for (int q = tid; q < N * N; q += kSolveThreads) lu_s[q] = LU[q];
     __syncthreads();
-    lu_substitute(staged ? lu_s : LU, piv_s, x, N, tid);
+    lu_substitute(staged ? lu_s : LU, piv_s, x, N, tid, kSolveThreads);
     for (int P = tid; P < N; P += kSolveThreads) ub[g.at(P % m, P / m)] = cast<T>(x[P]);
 }
 

@@ -173,3 +173,23 @@ def test_full_size_level_operations_on_sampled_rows():
             st = stencil_to_csr(to_np(S.stencil(l)))
             diff = abs(st[rows] - H.A[l][rows]).max()
             assert diff <= 1e-13 * abs(H.A[l]).max(), l
+
+
+@pytest.mark.parametrize("cyc,smoother", [("V", "gmres"), ("W", "gmres"), ("W", "jacobi")])
+def test_one_cycle_with_single_workgroup_tail(monkeypatch, cyc, smoother):
+    """The coarse tail (levels of at most 16 intervals in one workgroup per right-hand
+    side) gives the same cycle as the oracle."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    monkeypatch.setenv("HELMG_TAIL_N", "16")
+    n = 64
+    k2 = W.random_k2(n, 9, 8.0, 18.0)
+    H = O.build_hierarchy(k2, 1.0 / n, 0.3)
+    S = Solver(to_gpu(k2), 1.0 / n, 0.3, max_batch=2)
+    u = _rand(n, 2, 120)
+    f = _rand(n, 2, 121)
+    got = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, smoother=smoother, nu_pre=2, nu_post=1))
+    opts = O.CycleOptions(gamma=1 if cyc == "V" else 2, smoother=smoother, nu1=2, nu2=1)
+    for b in range(2):
+        ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
+        assert rel(got[b], ref) <= 1e-10, (b, rel(got[b], ref))
