@@ -9,27 +9,39 @@ namespace hm {
 namespace {
 
 constexpr int kThreads = kBX * kBY;
+constexpr int kTallDefault = 4;
 
-// Block height. 64 x 4 blocks by default: measured on the n = 1024 level
-// grid, 64 x 16 blocks were slower (at 70+ VGPRs one 16-wave block fills a
-// CU, so the capped block count runs in more than two rounds).
-// HELMG_TALL_BLOCKS=1 selects 64 x 16 blocks for light kernels on grids of
-// 256 or more intervals.
-bool tall_blocks_enabled() {
-    static const bool on = [] {
-        const char* e = std::getenv("HELMG_TALL_BLOCKS");
-        return e && std::atoi(e) != 0;
+// Block height: 64 x 4 for register-heavy Galerkin stencils and small grids;
+// light kernels on grids of 256 or more intervals use tall_rows() rows
+// (HELMG_TALL_BLOCKS = 4, 8 or 16; default below).
+int tall_rows() {
+    static const int v = [] {
+        int r = kTallDefault;
+        if (const char* e = std::getenv("HELMG_TALL_BLOCKS")) r = std::atoi(e);
+        return (r == 8 || r == 16) ? r : kBY;
     }();
-    return on;
+    return v;
 }
-int block_rows(const Grid& g, bool heavy) { return (tall_blocks_enabled() && !heavy && g.n >= 256) ? kMaxBY : kBY; }
+int block_rows(const Grid& g, bool heavy) { return (!heavy && g.n >= 256) ? tall_rows() : kBY; }
 
-// Rows per thread: enough that a level grid has at most kMaxPartialBlocks
-// blocks (the reductions read every block's partial sums).
+// Block cap of a level grid: every consumer of a reduction reads all partial
+// sums of its producer, so more blocks cost more of those reads.
+// HELMG_MAX_BLOCKS overrides the default (at most kMaxPartialBlocks).
+int block_cap() {
+    static const int cap = [] {
+        int v = 640;
+        if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) v = std::atoi(e);
+        return v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
+    }();
+    return cap;
+}
+
+// Rows per thread: enough that a level grid has at most block_cap() blocks.
 int level_rpt(const Grid& g, int by) {
     const long long m = g.n + 1;
     const long long bx = (m + kBX - 1) / kBX;
-    const long long r = (m * bx + (long long)by * kMaxPartialBlocks - 1) / ((long long)by * kMaxPartialBlocks);
+    const long long cap = block_cap();
+    const long long r = (m * bx + (long long)by * cap - 1) / ((long long)by * cap);
     return int(r < 1 ? 1 : r);
 }
 
@@ -59,7 +71,8 @@ void with_by(int by, F&& f) {
     if constexpr (kHeavy) {
         f(std::integral_constant<int, kBY>{});
     } else {
-        if (by == kMaxBY) f(std::integral_constant<int, kMaxBY>{});
+        if (by == 16) f(std::integral_constant<int, 16>{});
+        else if (by == 8) f(std::integral_constant<int, 8>{});
         else f(std::integral_constant<int, kBY>{});
     }
 }
@@ -83,6 +96,37 @@ __device__ __forceinline__ double dnorm2(cplx<T> z) {
     return double(z.re) * double(z.re) + double(z.im) * double(z.im);
 }
 
+// Runs f(i, j, p, A x at p) over the thread's nodes, where x is given by the
+// element getter xget. Galerkin levels first stage x for the block tile plus
+// halo in LDS (one global read per tile node instead of one per stencil
+// entry); the level-0 five-point operator reads x directly.
+template <typename Op, typename T, typename XGet, typename F>
+__device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& xget, F&& f) {
+    if constexpr (is_stencil<Op>::value) {
+        constexpr int R = is_stencil<Op>::radius;
+        cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+        const Tile<R> tl = block_tile<R>(rpt);
+        fill_tile<T, R>(lds, tl, op.g, xget);
+        for_nodes(op.g, rpt, [&](int i, int j, long long p) {
+            const int li = tl.at(i, j);
+            f(i, j, p, lds[li], apply_tile(op, lds, li, p));
+        });
+    } else {
+        for_nodes(op.g, rpt, [&](int i, int j, long long p) { f(i, j, p, xget(p), op.apply_at(xget, i, j, p)); });
+    }
+}
+
+// Dynamic LDS bytes of an operator kernel launched with geometry (by, rpt).
+template <typename Op, typename T>
+size_t tile_bytes(int by, int rpt) {
+    if constexpr (is_stencil<Op>::value) {
+        constexpr int R = is_stencil<Op>::radius;
+        return size_t(Tile<R>::TW) * size_t(by * rpt + 2 * R) * sizeof(cplx<T>);
+    } else {
+        return 0;
+    }
+}
+
 // ---------------------------------------------------------------- operator
 template <typename Op, typename T, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_apply(Op op, Vec<T> x, Vec<T> y, const int* active, int rpt) {
@@ -90,7 +134,8 @@ __global__ __launch_bounds__(kBX * BY) void k_apply(Op op, Vec<T> x, Vec<T> y, c
     if (!rhs_active(active, b)) return;
     const cplx<T>* xb = x.rhs(b);
     cplx<T>* yb = y.rhs(b);
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) { yb[p] = op.apply(xb, i, j, p); });
+    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
+                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { yb[p] = ax; });
 }
 
 template <typename Op, typename T, int BY>
@@ -101,7 +146,8 @@ __global__ __launch_bounds__(kBX * BY) void k_residual(Op op, Vec<T> x, Vec<T> f
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* rb = r.rhs(b);
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) { rb[p] = fb[p] - op.apply(xb, i, j, p); });
+    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
+                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { rb[p] = fb[p] - ax; });
 }
 
 // Weighted Jacobi of §3: y = x + (omega diag(A))^{-1} (f - A x).
@@ -113,10 +159,11 @@ __global__ __launch_bounds__(kBX * BY) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* yb = y.rhs(b);
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<T> r = fb[p] - op.apply(xb, i, j, p);
-        yb[p] = xb[p] + inv_omega * cdiv(r, op.diag(i, j, p));
-    });
+    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
+                             [&](int i, int j, long long p, cplx<T> xp, cplx<T> ax) {
+                                 const cplx<T> r = fb[p] - ax;
+                                 yb[p] = xp + inv_omega * cdiv(r, op.diag(i, j, p));
+                             });
 }
 
 // ---------------------------------------------------------------- transfers
@@ -240,11 +287,12 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Ve
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     double acc[1] = {0.0};
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<T> z = fb[p] - op.apply(ub, i, j, p);
-        z0[p] = z;
-        acc[0] += dnorm2(z);
-    });
+    for_nodes_applied<Op, T>(op, rpt, [ub](long long q) { return ub[q]; },
+                             [&](int, int, long long p, cplx<T>, cplx<T> au) {
+                                 const cplx<T> z = fb[p] - au;
+                                 z0[p] = z;
+                                 acc[0] += dnorm2(z);
+                             });
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
@@ -269,11 +317,11 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     cplx<T>* wb = Wout.rhs(b);
     double acc[2] = {0.0, 0.0};
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<T> w = op.apply(z0, i, j, p);
-        wb[p] = w;
-        acc_dot(acc[0], acc[1], z0[p], w);
-    });
+    for_nodes_applied<Op, T>(op, rpt, [z0](long long q) { return z0[q]; },
+                             [&](int, int, long long p, cplx<T> zp, cplx<T> w) {
+                                 wb[p] = w;
+                                 acc_dot(acc[0], acc[1], zp, w);
+                             });
     block_partials<2>(acc, pout + b * kPartStride);
 }
 
@@ -351,9 +399,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     double acc[1 + 2 * (J + 1)];
 #pragma unroll
     for (int q = 0; q < 1 + 2 * (J + 1); ++q) acc[q] = 0.0;
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<T> zp = znew(p);
-        const cplx<T> w = op.apply_at(znew, i, j, p);
+    for_nodes_applied<Op, T>(op, rpt, znew, [&](int, int, long long p, cplx<T> zp, cplx<T> w) {
         zJ[p] = zp;
         wo[p] = w;
         acc[0] += dnorm2(zp);
@@ -469,7 +515,8 @@ __global__ __launch_bounds__(kBX * BY) void k_resnorm(Op op, Vec<T> x, Vec<T> f,
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     double acc[1] = {0.0};
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) { acc[0] += dnorm2(fb[p] - op.apply(xb, i, j, p)); });
+    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
+                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { acc[0] += dnorm2(fb[p] - ax); });
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
@@ -610,11 +657,13 @@ __global__ __launch_bounds__(kThreads) void k_grad_k2(Grid g, double h, const do
         constexpr int BY = decltype(byc)::value;                                                          \
         hipLaunchKernelGGL(KERNEL_BY, (q).grid, (q).block, 0, ctx.stream, __VA_ARGS__);                   \
     })
-// Same for kernels templated on an operator type Op (heavy operators: short blocks only).
+// Same for kernels templated on an operator type Op (heavy operators: short
+// blocks only; Galerkin levels get their LDS tile as dynamic shared memory).
 #define HM_LAUNCH_OP(q, KERNEL_BY, ...)                                                                    \
     with_by<Op::kHeavy>((q).by, [&](auto byc) {                                                            \
         constexpr int BY = decltype(byc)::value;                                                          \
-        hipLaunchKernelGGL(KERNEL_BY, (q).grid, (q).block, 0, ctx.stream, __VA_ARGS__);                   \
+        const size_t shm_ = tile_bytes<Op, T>((q).by, (q).rpt);                                           \
+        hipLaunchKernelGGL(KERNEL_BY, (q).grid, (q).block, shm_, ctx.stream, __VA_ARGS__);                \
     })
 
 template <typename T>

@@ -86,6 +86,66 @@ __device__ __forceinline__ void for_nodes(const Grid& g, int rpt, F&& f) {
     }
 }
 
+// ---------------------------------------------------------------- LDS tiles
+// A block of 64 x BY threads with rows_per_thread rpt covers columns
+// [c0, c0 + 64) and rows [r0, r0 + BY * rpt) of a level. Its LDS tile adds a
+// halo of R nodes on every side so that a radius-R stencil reads LDS only.
+extern __shared__ __align__(16) unsigned char hm_dyn_lds[];
+
+template <int R>
+struct Tile {
+    static constexpr int TW = kBX + 2 * R;
+    int c0, r0, rows;
+    __device__ __forceinline__ int at(int i, int j) const { return (j - r0 + R) * TW + (i - c0 + R); }
+    __device__ __forceinline__ int count() const { return TW * (rows + 2 * R); }
+};
+
+template <int R>
+__device__ __forceinline__ Tile<R> block_tile(int rpt) {
+    return Tile<R>{int(blockIdx.x) * kBX, int(blockIdx.y) * int(blockDim.y) * rpt, int(blockDim.y) * rpt};
+}
+
+// lds[t.at(i, j)] = get(g.at(i, j)) for every tile node inside the padded
+// frame (ghosts read as stored, zero); nodes beyond it hold zero and are
+// never used by an in-domain stencil.
+template <typename T, int R, typename Get>
+__device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const Grid& g, Get&& get) {
+    const int total = t.count();
+    const int nt = blockDim.x * blockDim.y;
+    for (int q = threadIdx.y * kBX + threadIdx.x; q < total; q += nt) {
+        const int i = t.c0 - R + q % Tile<R>::TW;
+        const int j = t.r0 - R + q / Tile<R>::TW;
+        cplx<T> v{T(0), T(0)};
+        if (i >= -R && j >= -R && i <= g.n + R && j <= g.n + R) v = get(g.at(i, j));
+        lds[q] = v;
+    }
+    __syncthreads();
+}
+
+// Stencil of radius R applied at node p whose tile index is li, values from LDS.
+template <typename T, int R>
+__device__ __forceinline__ cplx<T> apply_tile(const StencilOp<T, R>& op, const cplx<T>* lds, int li, long long p) {
+    constexpr int D = 2 * R + 1;
+    constexpr int TW = Tile<R>::TW;
+    cplx<T> y{T(0), T(0)};
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx)
+            y = cfma(y, op.coef[((dy + R) * D + dx + R) * op.g.plane + p], lds[li + dy * TW + dx]);
+    return y;
+}
+
+template <typename Op>
+struct is_stencil {
+    static constexpr bool value = false;
+};
+template <typename T, int R>
+struct is_stencil<StencilOp<T, R>> {
+    static constexpr bool value = true;
+    static constexpr int radius = R;
+};
+
 __device__ __forceinline__ bool rhs_active(const int* active, int b) { return active == nullptr || active[b] != 0; }
 
 // Grid-wide reductions without atomics. A producer kernel writes one partial
