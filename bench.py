@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=12, help="oracle cycles in the CPU sample")
     ap.add_argument("--kernel-class", type=int, default=1)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -87,6 +89,15 @@ def main():
     from paper_2308_13476_amd.solver import Solver
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        # reads and writes exactly copy_calibration_mib MiB per launch: the reference
+        # against which FETCH_SIZE / WRITE_SIZE of the solver kernels are scaled
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     n, k = args.n, args.k
     beta = 1.0 / k
     nodes = (n + 1) ** 2

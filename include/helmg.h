@@ -181,7 +181,10 @@ mg_status mg_prolong_add(mg_handle h, int level, const void* coarse, void* fine,
 mg_status mg_coarse_solve(mg_handle h, const void* f, void* u, int nvec, int precision, void* stream);
 
 /* One cycle on level 0 for A_s u = f_s: u [dev] in/out, f_s [dev] the already
- * scaled right-hand side W f. FP64 data only. */
+ * scaled right-hand side W f, both [nvec][n+1][n+1]. complex128 data and an
+ * FP64 cycle, or, when opts->precision is MG_FP32_REFINED, complex64 data and
+ * the FP32 cycle that the refined solve runs (MG_E_ARG if the setup holds no
+ * FP32 data). */
 mg_status mg_cycle(mg_handle h, void* u, const void* f_s, int nvec, int cycle, int smoother,
                    const mg_solve_opts* opts, void* stream);
 

@@ -103,31 +103,45 @@ void launch_grad_k2(const LaunchCtx&, Grid g, double h, const double* k2, Vec<do
                     double* grad_k2_dense);
 
 // Coarse tail: the whole sub-cycle on levels l0 .. L-1 (at most kMaxTailLevels)
-// in one launch, one workgroup per right-hand side. Pointers are those of
-// right-hand side 0; Z holds 4 planes per right-hand side.
+// in one launch, one workgroup per right-hand side, every vector of those
+// levels in LDS. Level q of the tail (q = 0: level l0) holds tail_planes(q)
+// planes of tail_pitch(n_q)^2 values: u and f, plus five scratch planes on
+// every level that is smoothed (all but the coarsest). Planes carry a zero
+// frame of kTailGhost nodes.
 constexpr int kMaxTailLevels = 8;
+constexpr int kTailGhost = 3;
+constexpr int kTailMaxCoarseNodes = 81;              // coarsest (n_c + 1)^2 solved by the explicit inverse
+constexpr long long kTailMaxLdsBytes = 156 * 1024;   // dynamic LDS of one tail workgroup
+__host__ __device__ inline int tail_pitch(int n) { return n + 1 + 2 * kTailGhost; }
+__host__ __device__ inline int tail_planes(int q, int nlev) { return q + 1 < nlev ? 7 : 2; }
+__host__ __device__ inline long long tail_plane_values(int n, int q, int nlev) {
+    const long long p = tail_pitch(n);
+    return tail_planes(q, nlev) * p * p;
+}
 template <typename T>
 struct TailLevel {
     Grid g;
     int radius;
     const cplx<T>* coef;
-    cplx<T>* u;
-    cplx<T>* f;
-    cplx<T>* t;
-    cplx<T>* w;
-    cplx<T>* Z;
 };
 template <typename T>
 struct TailArgs {
     int nlev;
+    long long lds_bytes;  // sum of tail_plane_values over the levels, in bytes
     TailLevel<T> lv[kMaxTailLevels];
-    const cplx<double>* lu;  // LU factor of the coarsest operator (FP64)
-    const int* piv;
+    cplx<T>* u_top;         // level l0 iterate (read, then overwritten), right-hand side 0; stride g.plane
+    const cplx<T>* f_top;   // level l0 right-hand side
+    const cplx<double>* inv;  // explicit inverse of the coarsest operator [N][N] (FP64)
     int gamma, smoother, nu1, nu2;  // smoother: 0 Jacobi, 1 GMRES(3)
     double omega, breakdown;
     int bez;
 };
 template <typename T> void launch_tail(const LaunchCtx&, const TailArgs<T>&);
+// Raises the dynamic-LDS limit of the tail kernels (once per process; call
+// before the first launch, outside stream capture).
+void tail_init();
+// inv = A^{-1} from the LU factor and pivots of launch_dense_lu, N <= kTailMaxCoarseNodes.
+void launch_lu_inverse(hipStream_t, int N, const cplx<double>* lu, const int* piv, cplx<double>* inv);
 
 // ---- setup ----
 // Padded k^2 planes from the caller's dense array (FP64 and optionally FP32).

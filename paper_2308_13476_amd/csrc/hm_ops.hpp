@@ -164,11 +164,18 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
     __shared__ double sh[K][kMaxBY];
     const int lane = threadIdx.x, wave = threadIdx.y;
     __syncthreads();  // sh may still be read from an earlier call
+    // butterfly over the K values together: the cross-lane exchanges of one
+    // step are independent and overlap (same sums as K separate wave_sum)
+    double w[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const double s = wave_sum(v[k]);
-        if (lane == 0) sh[k][wave] = s;
-    }
+    for (int k = 0; k < K; ++k) w[k] = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[k] += __shfl_xor(w[k], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh[k][wave] = w[k];
     __syncthreads();
     const int nw = blockDim.y;
 #pragma unroll
@@ -280,6 +287,97 @@ static __device__ __noinline__ void gm_least_squares(GmState& st, LsWork& w) {
     for (int j = 0; j < 3; ++j) {
         st.yr[j] = (j < k) ? w.yr[j] * st.s[j] : 0.0;
         st.yi[j] = (j < k) ? w.yi[j] * st.s[j] : 0.0;
+    }
+}
+
+// The same least-squares solve with every index fixed at compile time, so
+// that H, the rotations and y stay in registers: for kernels in which every
+// thread holds H. Columns at or beyond k are skipped; y_i s_i for i < k, zero
+// beyond.
+__device__ __forceinline__ void gm_least_squares_regs(const double (&Hr)[4][3], const double (&Hi)[4][3],
+                                                      const double (&s)[3], double beta, int k, double (&yr)[3],
+                                                      double (&yi)[3]) {
+    double hr[4][3], hi[4][3], gr[4], gi[4], cs[3], sr[3], si[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const bool used = (c < k) && (a <= c + 1);
+            hr[a][c] = used ? Hr[a][c] : 0.0;
+            hi[a][c] = used ? Hi[a][c] : 0.0;
+        }
+    gr[0] = beta;
+    gi[0] = 0.0;
+#pragma unroll
+    for (int a = 1; a < 4; ++a) gr[a] = gi[a] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (j < k) {
+#pragma unroll
+            for (int i = 0; i < j; ++i) {
+                const double ar = hr[i][j], ai = hi[i][j], br = hr[i + 1][j], bi = hi[i + 1][j];
+                const double c = cs[i], s_r = sr[i], s_i = si[i];
+                hr[i][j] = c * ar + (s_r * br - s_i * bi);
+                hi[i][j] = c * ai + (s_r * bi + s_i * br);
+                hr[i + 1][j] = -(s_r * ar + s_i * ai) + c * br;
+                hi[i + 1][j] = -(s_r * ai - s_i * ar) + c * bi;
+            }
+            // rotation zeroing b under a: c = |a| / rho, s = (a / |a|) conj(b) / rho,
+            // rho = sqrt(|a|^2 + |b|^2) (entries of H are bounded by the
+            // operator norm, so the squares stay far from overflow)
+            const double ar = hr[j][j], ai = hi[j][j], br = hr[j + 1][j], bi = hi[j + 1][j];
+            const double a2 = ar * ar + ai * ai;
+            const double rho = sqrt(a2 + (br * br + bi * bi));
+            double c, s_r, s_i;
+            if (a2 == 0.0) {
+                const double ir = 1.0 / rho;
+                c = 0.0;
+                s_r = br * ir;
+                s_i = -bi * ir;
+            } else {
+                const double na = sqrt(a2);
+                const double ir = 1.0 / rho;
+                const double inr = ir / na;
+                c = na * ir;
+                s_r = (ar * br + ai * bi) * inr;
+                s_i = (ai * br - ar * bi) * inr;
+            }
+            cs[j] = c;
+            sr[j] = s_r;
+            si[j] = s_i;
+            hr[j][j] = c * ar + (s_r * br - s_i * bi);
+            hi[j][j] = c * ai + (s_r * bi + s_i * br);
+            hr[j + 1][j] = 0.0;
+            hi[j + 1][j] = 0.0;
+            const double g0r = gr[j], g0i = gi[j], g1r = gr[j + 1], g1i = gi[j + 1];
+            gr[j] = c * g0r + (s_r * g1r - s_i * g1i);
+            gi[j] = c * g0i + (s_r * g1i + s_i * g1r);
+            gr[j + 1] = -(s_r * g0r + s_i * g0i) + c * g1r;
+            gi[j + 1] = -(s_r * g0i - s_i * g0r) + c * g1i;
+        }
+    }
+    double wr[3] = {0.0, 0.0, 0.0}, wi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 2; j >= 0; --j) {
+        if (j < k) {
+            double tr = gr[j], ti = gi[j];
+#pragma unroll
+            for (int c = j + 1; c < 3; ++c) {
+                if (c < k) {
+                    tr -= hr[j][c] * wr[c] - hi[j][c] * wi[c];
+                    ti -= hr[j][c] * wi[c] + hi[j][c] * wr[c];
+                }
+            }
+            const double dr = hr[j][j], di = hi[j][j];
+            const double inv = 1.0 / (dr * dr + di * di);
+            wr[j] = (tr * dr + ti * di) * inv;
+            wi[j] = (ti * dr - tr * di) * inv;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        yr[j] = (j < k) ? wr[j] * s[j] : 0.0;
+        yi[j] = (j < k) ? wi[j] * s[j] : 0.0;
     }
 }
 

@@ -81,6 +81,7 @@ struct mg_ctx {
     float* k2_32 = nullptr;
     cplx<double>* dense = nullptr;
     int* piv = nullptr;
+    cplx<double>* inv = nullptr;  // explicit coarsest inverse (small coarsest grids only)
     GmState* gm = nullptr;
     RhsNorms* norms = nullptr;
     int* active = nullptr;
@@ -109,8 +110,9 @@ struct mg_ctx {
     int last_graph = -1;
     hipStream_t cap_stream = nullptr;
     bool use_graph = true;
-    // first level run by the single-workgroup coarse tail (-1: none)
-    int tail_level = -1;
+    // first level run by the single-workgroup coarse tail (-1: none), per
+    // precision (index 0: FP64 cycles, 1: FP32 cycles)
+    int tail_level[2] = {-1, -1};
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -180,6 +182,7 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     const size_t Nc = size_t(nc + 1) * size_t(nc + 1);
     cplx<double>* dense = cv.take<cplx<double>>(Nc * Nc * 16);
     int* piv = cv.take<int>(Nc * 4);
+    cplx<double>* inv = Nc <= size_t(kTailMaxCoarseNodes) ? cv.take<cplx<double>>(Nc * Nc * 16) : nullptr;
     GmState* gm = cv.take<GmState>(B * sizeof(GmState));
     RhsNorms* norms = cv.take<RhsNorms>(B * sizeof(RhsNorms));
     int* active = cv.take<int>(B * 4);
@@ -189,6 +192,7 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
         c->k2_32 = k32;
         c->dense = dense;
         c->piv = piv;
+        c->inv = inv;
         c->gm = gm;
         c->norms = norms;
         c->active = active;
@@ -446,13 +450,16 @@ template <typename T>
 void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams& cp) {
     TailArgs<T> a{};
     a.nlev = c->L - l0;
+    a.lds_bytes = 0;
     for (int q = 0; q < a.nlev; ++q) {
         LevelBuf& lb = c->lv[l0 + q];
-        a.lv[q] = TailLevel<T>{lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::u(lb), Prec<T>::f(lb), Prec<T>::t_ref(lb),
-                               Prec<T>::w(lb), Prec<T>::V(lb)};
+        a.lv[q] = TailLevel<T>{lb.g, lb.radius, Prec<T>::coef(lb)};
+        a.lds_bytes += tail_plane_values(lb.g.n, q, a.nlev) * (long long)sizeof(cplx<T>);
     }
-    a.lu = c->dense;
-    a.piv = c->piv;
+    LevelBuf& top = c->lv[l0];
+    a.u_top = Prec<T>::u(top);
+    a.f_top = Prec<T>::f(top);
+    a.inv = c->inv;
     a.gamma = cp.gamma;
     a.smoother = cp.smoother == MG_JACOBI ? 0 : 1;
     a.nu1 = cp.nu1;
@@ -465,7 +472,7 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
 
 template <typename T>
 void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
-    if (l == c->tail_level) {
+    if (l == c->tail_level[sizeof(T) == 4]) {
         launch_tail_from<T>(c, lc, l, cp);
         return;
     }
@@ -506,7 +513,34 @@ mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s) {
     }
     const LevelBuf& lc = c->lv[c->L - 1];
     launch_dense_lu(s, lc.g, lc.radius, lc.coef64, c->dense, c->piv);
+    if (c->inv) launch_lu_inverse(s, (lc.g.n + 1) * (lc.g.n + 1), c->dense, c->piv, c->inv);
     return check_launch(c);
+}
+
+// Levels of at most HELMG_TAIL_N intervals (default 32) run in the
+// single-workgroup tail when all of them fit its LDS budget at the cycle's
+// precision and the coarsest grid is small enough for the explicit inverse;
+// HELMG_TAIL_N = 0 turns the tail off.
+void pick_tail_levels(mg_ctx* c) {
+    int tail_n = 32;
+    if (const char* e = std::getenv("HELMG_TAIL_N")) tail_n = std::atoi(e);
+    const int L = c->L;
+    const int nc = c->n >> (L - 1);
+    const bool small_coarse = (nc + 1) * (nc + 1) <= kTailMaxCoarseNodes;
+    for (int prec = 0; prec < 2; ++prec) {
+        const long long elem = prec ? 8 : 16;
+        c->tail_level[prec] = -1;
+        if (tail_n <= 0 || !small_coarse) continue;
+        for (int l = 1; l < L; ++l) {
+            if ((c->n >> l) > tail_n || L - l > kMaxTailLevels) continue;
+            long long bytes = 0;
+            for (int q = 0; q < L - l; ++q) bytes += tail_plane_values(c->n >> (l + q), q, L - l) * elem;
+            if (bytes <= kTailMaxLdsBytes) {
+                c->tail_level[prec] = l;
+                break;
+            }
+        }
+    }
 }
 
 bool is_dev_ptr_ok(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) % 8) == 0; }
@@ -737,20 +771,8 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
-    {
-        // HELMG_TAIL_N = t > 0: levels of at most t intervals run in the
-        // single-workgroup tail. Off by default: on the n = 1024 benchmark the
-        // tail (about 4.5 us per in-block phase) was no faster than one launch
-        // per operation on those levels.
-        int tail_n = 0;
-        if (const char* e = std::getenv("HELMG_TAIL_N")) tail_n = std::atoi(e);
-        c->tail_level = -1;
-        for (int l = 1; l < L && tail_n > 0; ++l)
-            if ((n >> l) <= tail_n && L - l <= kMaxTailLevels) {
-                c->tail_level = l;
-                break;
-            }
-    }
+    pick_tail_levels(c);
+    tail_init();
     carve(c, c->ws, n, L, transfer, max_batch, has32);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=
@@ -1018,20 +1040,31 @@ mg_status mg_cycle(mg_handle c, void* u, const void* f_s, int nvec, int cyc, int
     if (!c) return MG_E_ARG;
     const mg_solve_opts o = opts ? *opts : default_solve_opts();
     if (mg_status st = check_solve_args(c, nvec, 1.0, cyc, smoother, o)) return st;
-    if (o.precision != MG_FP64) { c->err = "mg_cycle runs FP64 cycles"; return MG_E_ARG; }
+    const bool f32 = o.precision == MG_FP32_REFINED;
+    if (f32 && !c->has32) { c->err = "FP32 cycle needs a setup with FP32 data"; return MG_E_ARG; }
     if (!is_dev_ptr_ok(u) || !is_dev_ptr_ok(f_s)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
     hipStream_t s = static_cast<hipStream_t>(stream);
     LevelBuf& l0 = c->lv[0];
     LaunchCtx lc = launch_ctx(c, s, nvec);
     lc.active = nullptr;
-    launch_copy_in<double>(lc, l0.g, f_s, false, vec<double>(l0.f64, l0), false, false);
-    launch_copy_in<double>(lc, l0.g, u, false, vec<double>(l0.u64, l0), false, false);
+    if (f32) {
+        launch_copy_in<float>(lc, l0.g, f_s, true, vec<float>(l0.f32, l0), false, false);
+        launch_copy_in<float>(lc, l0.g, u, true, vec<float>(l0.u32, l0), false, false);
+    } else {
+        launch_copy_in<double>(lc, l0.g, f_s, false, vec<double>(l0.f64, l0), false, false);
+        launch_copy_in<double>(lc, l0.g, u, false, vec<double>(l0.u64, l0), false, false);
+    }
     for (int i = 0; i < nvec; ++i) c->h_active[i] = 1;
     HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nvec, hipMemcpyHostToDevice, s));
     lc.active = c->active;
     const CycleParams cp{cyc, smoother, o.nu_pre, o.nu_post, o.omega};
-    cycle<double>(c, lc, 0, cp);
-    launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), u, false, false, false);
+    if (f32) {
+        cycle<float>(c, lc, 0, cp);
+        launch_copy_out<float>(lc, l0.g, vec<float>(l0.u32, l0), u, true, false, false);
+    } else {
+        cycle<double>(c, lc, 0, cp);
+        launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), u, false, false, false);
+    }
     if (mg_status st = check_launch(c)) return st;
     HM_HIP(hipStreamSynchronize(s));
     return MG_OK;

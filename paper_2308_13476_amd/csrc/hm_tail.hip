@@ -1,8 +1,10 @@
 // Coarse tail of the cycle: one workgroup per right-hand side runs the whole
 // sub-cycle (§3 coarse grid correction, §5 V/W cycles) on the small levels at
-// the bottom of the hierarchy, with block-level reductions and barriers in
-// place of kernel launches. On these grids (at most 33 x 33 nodes) a launch
-// per operation costs far more than the arithmetic.
+// the bottom of the hierarchy. Every vector of those levels lives in LDS for
+// the whole sub-cycle; only the Galerkin stencil planes are read from global
+// memory (they stay in L2 between the passes). Barriers and block reductions
+// replace the kernel launches and grid-wide reductions of the level kernels,
+// which on grids of at most 33 x 33 nodes cost far more than the arithmetic.
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -10,94 +12,139 @@ namespace {
 
 constexpr int kTailBY = 8;
 constexpr int kTailThreads = kBX * kTailBY;
-constexpr int kTailMaxCoarse = 1089;
-constexpr int kTailMaxLdsLU = 45 * 45;
 
 template <typename T>
 __device__ __forceinline__ double tn2(cplx<T> z) {
     return double(z.re) * double(z.re) + double(z.im) * double(z.im);
 }
 
+// re + i im += conj(a) w
 template <typename T>
 __device__ __forceinline__ void tdot(double& re, double& im, cplx<T> a, cplx<T> w) {
     re += double(a.re) * double(w.re) + double(a.im) * double(w.im);
     im += double(a.re) * double(w.im) - double(a.im) * double(w.re);
 }
 
-// All threads of the block visit the nodes of a level.
-template <typename F>
-__device__ __forceinline__ void blk_nodes(const Grid& g, F&& f) {
-    const int m = g.n + 1;
-    const int N = m * m;
-    for (int q = thread_linear(); q < N; q += kTailThreads) {
-        const int i = q % m, j = q / m;
-        f(i, j, g.at(i, j));
-    }
-}
-
-// The level's Galerkin stencil as an operator object.
-template <typename T, typename F>
-__device__ __forceinline__ void with_stencil(const TailLevel<T>& L, F&& f) {
-    if (L.radius == 1) f(StencilOp<T, 1>{L.g, L.coef});
-    else if (L.radius == 2) f(StencilOp<T, 2>{L.g, L.coef});
-    else f(StencilOp<T, 3>{L.g, L.coef});
-}
-
-// Per-right-hand-side pointers of one level, with the Jacobi ping-pong
-// (u and t exchange roles after every sweep).
+// One level of the tail: its stencil in global memory and its LDS planes.
+// LDS planes have a zero frame of kTailGhost nodes: node (i, j) sits at
+// (j + kTailGhost) * lp + i + kTailGhost.
 template <typename T>
-struct Lv {
-    TailLevel<T> d;
-    cplx<T>* u;
-    cplx<T>* t;
+struct TLv {
+    Grid g;  // global layout (coefficient planes)
+    int radius;
+    const cplx<T>* coef;
+    int m, lp;
+    cplx<T>* pl;  // planes: u, f, then z0, z1, z2, wa, wb on smoothed levels
+    __device__ __forceinline__ cplx<T>* u() const { return pl; }
+    __device__ __forceinline__ cplx<T>* f() const { return pl + lp * lp; }
+    __device__ __forceinline__ cplx<T>* s(int k) const { return pl + (2 + k) * lp * lp; }
+    __device__ __forceinline__ int li(int i, int j) const { return (j + kTailGhost) * lp + i + kTailGhost; }
 };
 
 template <typename T>
-__device__ __forceinline__ Lv<T> level_view(const TailArgs<T>& a, int l, int b, unsigned swapped) {
-    Lv<T> v;
-    v.d = a.lv[l];
-    const long long pl = v.d.g.plane;
-    v.d.u += b * pl;
-    v.d.f += b * pl;
-    v.d.t += b * pl;
-    v.d.w += b * pl;
-    v.d.Z += 4 * b * pl;
-    const bool sw = (swapped >> l) & 1u;
-    v.u = sw ? v.d.t : v.d.u;
-    v.t = sw ? v.d.u : v.d.t;
+__device__ __forceinline__ TLv<T> tail_level(const TailArgs<T>& a, int q, cplx<T>* lds) {
+    TLv<T> v;
+    v.g = a.lv[q].g;
+    v.radius = a.lv[q].radius;
+    v.coef = a.lv[q].coef;
+    v.m = v.g.n + 1;
+    v.lp = tail_pitch(v.g.n);
+    long long off = 0;
+    for (int r = 0; r < q; ++r) off += tail_plane_values(a.lv[r].g.n, r, a.nlev);
+    v.pl = lds + off;
     return v;
 }
 
+// All threads visit the nodes of a level: f(i, j, LDS index, global index).
+template <typename T, typename F>
+__device__ __forceinline__ void tnodes(const TLv<T>& L, F&& f) {
+    const int N = L.m * L.m;
+    for (int q = thread_linear(); q < N; q += kTailThreads) {
+        const int i = q % L.m, j = q / L.m;
+        f(i, j, L.li(i, j), L.g.at(i, j));
+    }
+}
+
+// Stencil of radius R at one node; x from LDS. The coefficients are loaded
+// in batches of stencil rows that are all issued before the first product
+// (the empty asm keeps the compiler from interleaving each load with its
+// use, which would leave one load in flight per wave).
+template <typename T, int R>
+__device__ __forceinline__ cplx<T> tapply(const TLv<T>& L, const cplx<T>* x, int li, long long gp) {
+    constexpr int D = 2 * R + 1;
+    constexpr int RB = sizeof(T) == 4 ? 7 : 4;  // stencil rows per batch
+    const cplx<T>* cp = L.coef + gp;
+    const long long pl = L.g.plane;
+    cplx<T> y{T(0), T(0)};
+#pragma unroll
+    for (int r0 = 0; r0 < D; r0 += RB) {
+        cplx<T> c[RB][D];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (r0 + r < D)
+#pragma unroll
+                for (int dx = 0; dx < D; ++dx) c[r][dx] = cp[((r0 + r) * D + dx) * pl];
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+            if (r0 + r < D)
+#pragma unroll
+                for (int dx = 0; dx < D; ++dx) y = cfma(y, c[r][dx], x[li + (r0 + r - R) * L.lp + dx - R]);
+    }
+    return y;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ cplx<T> tdiag(const TLv<T>& L, long long gp) {
+    constexpr int D = 2 * R + 1;
+    return L.coef[(R * D + R) * L.g.plane + gp];
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ void with_radius(const TLv<T>& L, F&& f) {
+    if (L.radius == 1) f(std::integral_constant<int, 1>{});
+    else if (L.radius == 2) f(std::integral_constant<int, 2>{});
+    else f(std::integral_constant<int, 3>{});
+}
+
 template <typename T>
-__device__ void tail_jacobi(const Lv<T>& L, double inv_omega) {
+__device__ void tail_jacobi(const TLv<T>& L, double inv_omega) {
     const T w = T(inv_omega);
-    with_stencil(L.d, [&](auto op) {
-        blk_nodes(L.d.g, [&](int i, int j, long long p) {
-            const cplx<T> r = L.d.f[p] - op.apply(L.u, i, j, p);
-            L.t[p] = L.u[p] + w * cdiv(r, op.diag(i, j, p));
+    cplx<T>* u = L.u();
+    cplx<T>* t = L.s(3);
+    with_radius(L, [&](auto Rc) {
+        constexpr int R = decltype(Rc)::value;
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> r = L.f()[li] - tapply<T, R>(L, u, li, gp);
+            t[li] = u[li] + w * cdiv(r, tdiag<T, R>(L, gp));
         });
     });
     __syncthreads();
+    tnodes(L, [&](int, int, int li, long long) { u[li] = t[li]; });
+    __syncthreads();
 }
 
-// One GMRES(3) smoothing step (§5.3): classical Gram-Schmidt Arnoldi with the
-// same recurrences as the multi-kernel path, reductions inside the block.
+// One GMRES(3) smoothing step (§5.3): classical Gram-Schmidt Arnoldi on
+// unnormalised vectors z_j with scale s_j = 1 / ||z_j||, the same recurrences
+// as the multi-kernel path, reductions inside the block.
 template <typename T>
-__device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork& ls) {
-    const Grid& g = L.d.g;
-    cplx<T>* z0 = L.d.Z;
-    cplx<T>* z1 = z0 + g.plane;
-    cplx<T>* z2 = z1 + g.plane;
-    cplx<T>* wa = L.d.w;
-    cplx<T>* wb = L.t;
-    double hr[4][3], hi[4][3], s[3];
+__device__ void tail_gmres(const TLv<T>& L, double breakdown) {
+    cplx<T>* u = L.u();
+    const cplx<T>* f = L.f();
+    cplx<T>* z0 = L.s(0);
+    cplx<T>* z1 = L.s(1);
+    cplx<T>* z2 = L.s(2);
+    cplx<T>* wa = L.s(3);
+    cplx<T>* wb = L.s(4);
+    double hr[4][3] = {}, hi[4][3] = {}, s[3] = {};
     int k = 3;
     double beta;
-    with_stencil(L.d, [&](auto op) {
+    with_radius(L, [&](auto Rc) {
+        constexpr int R = decltype(Rc)::value;
         double a1[1] = {0.0}, t1[1];
-        blk_nodes(g, [&](int i, int j, long long p) {
-            const cplx<T> z = L.d.f[p] - op.apply(L.u, i, j, p);
-            z0[p] = z;
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> z = f[li] - tapply<T, R>(L, u, li, gp);
+            z0[li] = z;
             a1[0] += tn2(z);
         });
         block_sum<1>(a1, t1);
@@ -107,31 +154,31 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
             return;
         }
         s[0] = 1.0 / beta;
-        // column 0
+        // column 0: w = A z0, H00 = s0^2 <z0, w>
         double a2[2] = {0.0, 0.0}, t2[2];
-        blk_nodes(g, [&](int i, int j, long long p) {
-            const cplx<T> w = op.apply(z0, i, j, p);
-            wa[p] = w;
-            tdot(a2[0], a2[1], z0[p], w);
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z0, li, gp);
+            wa[li] = w;
+            tdot(a2[0], a2[1], z0[li], w);
         });
         block_sum<2>(a2, t2);
         hr[0][0] = s[0] * s[0] * t2[0];
         hi[0][0] = s[0] * s[0] * t2[1];
-        // z1 = s0 w0 - H00 s0 z0
+        // z1 = s0 w - H00 s0 z0
         {
             const cplx<T> c0 = {T(hr[0][0] * s[0]), T(hi[0][0] * s[0])};
             const T sc = T(s[0]);
-            blk_nodes(g, [&](int, int, long long p) {
-                const cplx<T> zq = z0[p];
-                cplx<T> v = sc * wa[p];
+            a1[0] = 0.0;
+            tnodes(L, [&](int, int, int li, long long) {
+                const cplx<T> zq = z0[li];
+                cplx<T> v = sc * wa[li];
                 v.re -= c0.re * zq.re - c0.im * zq.im;
                 v.im -= c0.re * zq.im + c0.im * zq.re;
-                z1[p] = v;
+                z1[li] = v;
+                a1[0] += tn2(v);
             });
+            block_sum<1>(a1, t1);
         }
-        a1[0] = 0.0;
-        blk_nodes(g, [&](int, int, long long p) { a1[0] += tn2(z1[p]); });
-        block_sum<1>(a1, t1);
         hr[1][0] = sqrt(t1[0]);
         hi[1][0] = 0.0;
         if (!(hr[1][0] > breakdown * beta)) {
@@ -141,11 +188,11 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
         s[1] = 1.0 / hr[1][0];
         // column 1
         double a4[4] = {0.0, 0.0, 0.0, 0.0}, t4[4];
-        blk_nodes(g, [&](int i, int j, long long p) {
-            const cplx<T> w = op.apply(z1, i, j, p);
-            wb[p] = w;
-            tdot(a4[0], a4[1], z0[p], w);
-            tdot(a4[2], a4[3], z1[p], w);
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z1, li, gp);
+            wb[li] = w;
+            tdot(a4[0], a4[1], z0[li], w);
+            tdot(a4[2], a4[3], z1[li], w);
         });
         block_sum<4>(a4, t4);
         for (int q = 0; q < 2; ++q) {
@@ -157,12 +204,12 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
             const cplx<T> c1 = {T(hr[1][1] * s[1]), T(hi[1][1] * s[1])};
             const T sc = T(s[1]);
             a1[0] = 0.0;
-            blk_nodes(g, [&](int, int, long long p) {
-                const cplx<T> q0 = z0[p], q1 = z1[p];
-                cplx<T> v = sc * wb[p];
+            tnodes(L, [&](int, int, int li, long long) {
+                const cplx<T> q0 = z0[li], q1 = z1[li];
+                cplx<T> v = sc * wb[li];
                 v.re -= c0.re * q0.re - c0.im * q0.im + c1.re * q1.re - c1.im * q1.im;
                 v.im -= c0.re * q0.im + c0.im * q0.re + c1.re * q1.im + c1.im * q1.re;
-                z2[p] = v;
+                z2[li] = v;
                 a1[0] += tn2(v);
             });
             block_sum<1>(a1, t1);
@@ -176,12 +223,12 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
         s[2] = 1.0 / hr[2][1];
         // column 2
         double a6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t6[6];
-        blk_nodes(g, [&](int i, int j, long long p) {
-            const cplx<T> w = op.apply(z2, i, j, p);
-            wa[p] = w;
-            tdot(a6[0], a6[1], z0[p], w);
-            tdot(a6[2], a6[3], z1[p], w);
-            tdot(a6[4], a6[5], z2[p], w);
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z2, li, gp);
+            wa[li] = w;
+            tdot(a6[0], a6[1], z0[li], w);
+            tdot(a6[2], a6[3], z1[li], w);
+            tdot(a6[4], a6[5], z2[li], w);
         });
         block_sum<6>(a6, t6);
         for (int q = 0; q < 3; ++q) {
@@ -193,9 +240,9 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
             for (int q = 0; q < 3; ++q) c[q] = {T(hr[q][2] * s[q]), T(hi[q][2] * s[q])};
             const T sc = T(s[2]);
             a1[0] = 0.0;
-            blk_nodes(g, [&](int, int, long long p) {
-                cplx<T> v = sc * wa[p];
-                const cplx<T> q0 = z0[p], q1 = z1[p], q2 = z2[p];
+            tnodes(L, [&](int, int, int li, long long) {
+                cplx<T> v = sc * wa[li];
+                const cplx<T> q0 = z0[li], q1 = z1[li], q2 = z2[li];
                 v.re -= c[0].re * q0.re - c[0].im * q0.im + c[1].re * q1.re - c[1].im * q1.im + c[2].re * q2.re -
                         c[2].im * q2.im;
                 v.im -= c[0].re * q0.im + c[0].im * q0.re + c[1].re * q1.im + c[1].im * q1.re + c[2].re * q2.im +
@@ -208,66 +255,61 @@ __device__ void tail_gmres(const Lv<T>& L, double breakdown, GmState& S, LsWork&
         hi[3][2] = 0.0;
     });
     if (k == 0) return;
-    if (thread_linear() == 0) {
-        S.beta = beta;
-        S.k = k;
-        for (int q = 0; q < 3; ++q) S.s[q] = (q < k) ? s[q] : 0.0;
-        for (int a = 0; a < 4; ++a)
-            for (int c = 0; c < 3; ++c) {
-                const bool used = (c < k) && (a <= c + 1);
-                S.hr[a][c] = used ? hr[a][c] : 0.0;
-                S.hi[a][c] = used ? hi[a][c] : 0.0;
-            }
-        gm_least_squares(S, ls);
-    }
-    __syncthreads();
+    // every thread holds the same H (block sums are identical in all
+    // threads) and solves the least-squares problem in registers
+    double yr[3], yi[3];
+    gm_least_squares_regs(hr, hi, s, beta, k, yr, yi);
     cplx<T> c[3];
-    for (int q = 0; q < 3; ++q) c[q] = {T(S.yr[q]), T(S.yi[q])};
-    blk_nodes(g, [&](int, int, long long p) {
-        cplx<T> x = L.u[p];
-        x = cfma(x, c[0], z0[p]);
-        if (k > 1) x = cfma(x, c[1], z1[p]);
-        if (k > 2) x = cfma(x, c[2], z2[p]);
-        L.u[p] = x;
+    for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
+    tnodes(L, [&](int, int, int li, long long) {
+        cplx<T> x = u[li];
+        x = cfma(x, c[0], z0[li]);
+        if (k > 1) x = cfma(x, c[1], z1[li]);
+        if (k > 2) x = cfma(x, c[2], z2[li]);
+        u[li] = x;
     });
     __syncthreads();
 }
 
-// f_c = R (f - A u) (§4 transfers, R = P^T / 4) and u_c = 0.
+// f_c = R (f - A u) (§4 transfers, R = P^T / 4) and u_c = 0. The residual
+// goes to scratch plane wa of the fine level; the LDS frame supplies the zero
+// ghosts that truncate the mask at the boundary.
 template <typename T>
-__device__ void tail_residual_restrict(const Lv<T>& L, const Lv<T>& C, bool bez) {
-    with_stencil(L.d, [&](auto op) {
-        blk_nodes(L.d.g, [&](int i, int j, long long p) { L.d.w[p] = L.d.f[p] - op.apply(L.u, i, j, p); });
+__device__ void tail_residual_restrict(const TLv<T>& L, const TLv<T>& C, bool bez) {
+    cplx<T>* w = L.s(3);
+    with_radius(L, [&](auto Rc) {
+        constexpr int R = decltype(Rc)::value;
+        tnodes(L, [&](int, int, int li, long long gp) { w[li] = L.f()[li] - tapply<T, R>(L, L.u(), li, gp); });
     });
     __syncthreads();
-    const Grid& gf = L.d.g;
-    blk_nodes(C.d.g, [&](int I, int J, long long pc) {
-        const long long pf = gf.at(2 * I, 2 * J);
-        const T w5[5] = {T(1), T(4), T(6), T(4), T(1)};
-        const T w3[5] = {T(0), T(1), T(2), T(1), T(0)};
-        const T* w = bez ? w5 : w3;
+    const T w5[5] = {T(1), T(4), T(6), T(4), T(1)};
+    const T w3[5] = {T(0), T(1), T(2), T(1), T(0)};
+    const T* mw = bez ? w5 : w3;
+    const T scale = T(bez ? 1.0 / 256.0 : 1.0 / 16.0);
+    tnodes(C, [&](int I, int J, int lc, long long) {
+        const int pf = L.li(2 * I, 2 * J);
         cplx<T> acc{T(0), T(0)};
         for (int dy = -2; dy <= 2; ++dy) {
             cplx<T> row{T(0), T(0)};
             for (int dx = -2; dx <= 2; ++dx) {
-                const cplx<T> v = L.d.w[pf + (long long)dy * gf.pitch + dx];
-                row.re += w[dx + 2] * v.re;
-                row.im += w[dx + 2] * v.im;
+                const cplx<T> v = w[pf + dy * L.lp + dx];
+                row.re += mw[dx + 2] * v.re;
+                row.im += mw[dx + 2] * v.im;
             }
-            acc.re += w[dy + 2] * row.re;
-            acc.im += w[dy + 2] * row.im;
+            acc.re += mw[dy + 2] * row.re;
+            acc.im += mw[dy + 2] * row.im;
         }
-        C.d.f[pc] = T(bez ? 1.0 / 256.0 : 1.0 / 16.0) * acc;
-        C.u[pc] = cplx<T>{T(0), T(0)};
+        C.f()[lc] = scale * acc;
+        C.u()[lc] = cplx<T>{T(0), T(0)};
     });
     __syncthreads();
 }
 
-// u += P e (§4 prolongation; coarse ghosts are zero, which truncates).
+// u += P e (§4 prolongation; the zero frame of the coarse plane truncates).
 template <typename T>
-__device__ void tail_prolong(const Lv<T>& C, const Lv<T>& L, bool bez) {
-    const Grid& gc = C.d.g;
-    blk_nodes(L.d.g, [&](int i, int j, long long pf) {
+__device__ void tail_prolong(const TLv<T>& C, const TLv<T>& L, bool bez) {
+    const cplx<T>* e = C.u();
+    tnodes(L, [&](int i, int j, int li, long long) {
         T wx[3], wy[3];
         const bool ox = i & 1, oy = j & 1;
         wx[0] = ox ? T(0) : (bez ? T(0.125) : T(0));
@@ -276,20 +318,35 @@ __device__ void tail_prolong(const Lv<T>& C, const Lv<T>& L, bool bez) {
         wy[0] = oy ? T(0) : (bez ? T(0.125) : T(0));
         wy[1] = oy ? T(0.5) : (bez ? T(0.75) : T(1));
         wy[2] = oy ? T(0.5) : (bez ? T(0.125) : T(0));
-        const long long pc = gc.at((i >> 1) - 1, (j >> 1) - 1);
+        const int pc = C.li((i >> 1) - 1, (j >> 1) - 1);
         cplx<T> acc{T(0), T(0)};
         for (int ty = 0; ty < 3; ++ty) {
             cplx<T> row{T(0), T(0)};
             for (int tx = 0; tx < 3; ++tx) {
-                const cplx<T> v = C.u[pc + (long long)ty * gc.pitch + tx];
+                const cplx<T> v = e[pc + ty * C.lp + tx];
                 row.re += wx[tx] * v.re;
                 row.im += wx[tx] * v.im;
             }
             acc.re += wy[ty] * row.re;
             acc.im += wy[ty] * row.im;
         }
-        L.u[pf] = L.u[pf] + acc;
+        L.u()[li] = L.u()[li] + acc;
     });
+    __syncthreads();
+}
+
+// u = A_c^{-1} f on the coarsest level with the explicit FP64 inverse
+// (complex64 data is widened): one row per thread.
+template <typename T>
+__device__ void tail_coarse(const TLv<T>& C, const cplx<double>* inv) {
+    const int N = C.m * C.m;
+    const cplx<T>* f = C.f();
+    for (int r = thread_linear(); r < N; r += kTailThreads) {
+        const cplx<double>* row = inv + (long long)r * N;
+        cplx<double> acc{0.0, 0.0};
+        for (int P = 0; P < N; ++P) acc = cfma(acc, row[P], cast<double>(f[C.li(P % C.m, P / C.m)]));
+        C.u()[C.li(r % C.m, r / C.m)] = cast<T>(acc);
+    }
     __syncthreads();
 }
 
@@ -297,89 +354,146 @@ template <typename T>
 __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int* active) {
     const int b = blockIdx.x;
     if (!rhs_active(active, b)) return;
-    __shared__ cplx<double> x[kTailMaxCoarse];
-    __shared__ cplx<double> lu_s[kTailMaxLdsLU];
-    __shared__ int piv_s[kTailMaxCoarse];
-    __shared__ GmState S;
-    __shared__ LsWork ls;
-    const int tid = thread_linear();
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
     const int last = a.nlev - 1;
-    const Grid gcst = a.lv[last].g;
-    const int mc = gcst.n + 1;
-    const int Nc = mc * mc;
-    const bool staged = Nc * Nc <= kTailMaxLdsLU;
-    for (int q = tid; q < Nc; q += kTailThreads) piv_s[q] = a.piv[q];
-    if (staged)
-        for (int q = tid; q < Nc * Nc; q += kTailThreads) lu_s[q] = a.lu[q];
-    __syncthreads();
-    const cplx<double>* LU = staged ? lu_s : a.lu;
-    const double inv_omega = 1.0 / a.omega;
-    const bool bez = a.bez != 0;
-
-    unsigned swapped = 0u;  // bit l: level l's iterate lives in its t buffer
-    unsigned visits = 0u;   // 2 bits per level: coarse visits left
-    auto smooth = [&](int l, int nu) {
-        for (int s = 0; s < nu; ++s) {
-            const Lv<T> L = level_view(a, l, b, swapped);
-            if (a.smoother == 0) {
-                tail_jacobi(L, inv_omega);
-                swapped ^= 1u << l;
-            } else {
-                tail_gmres(L, a.breakdown, S, ls);
-            }
-        }
-    };
-    int l = 0;
-    bool up = false;
-    for (;;) {
-        if (!up) {
-            if (l == last) {
-                const Lv<T> L = level_view(a, l, b, swapped);
-                for (int P = tid; P < Nc; P += kTailThreads) x[P] = cast<double>(L.d.f[gcst.at(P % mc, P / mc)]);
-                __syncthreads();
-                lu_substitute(LU, piv_s, x, Nc, tid, kTailThreads);
-                for (int P = tid; P < Nc; P += kTailThreads) L.u[gcst.at(P % mc, P / mc)] = cast<T>(x[P]);
-                __syncthreads();
-                if (l == 0) break;
-                l -= 1;
-                up = true;
-                continue;
-            }
-            smooth(l, a.nu1);
-            swapped &= ~(1u << (l + 1));  // the child starts from zero in its u buffer
-            tail_residual_restrict(level_view(a, l, b, swapped), level_view(a, l + 1, b, swapped), bez);
-            visits = (visits & ~(3u << (2 * l))) | (unsigned(a.gamma) << (2 * l));
-            l += 1;
-            continue;
-        }
-        // back from one visit of level l + 1
-        const unsigned left = ((visits >> (2 * l)) & 3u) - 1u;
-        visits = (visits & ~(3u << (2 * l))) | (left << (2 * l));
-        if (left > 0) {
-            l += 1;
-            up = false;
-            continue;
-        }
-        tail_prolong(level_view(a, l + 1, b, swapped), level_view(a, l, b, swapped), bez);
-        smooth(l, a.nu2);
-        if (l == 0) break;
-        l -= 1;
-    }
-    // the caller reads the top level's iterate from its u buffer
-    if (swapped & 1u) {
-        const Lv<T> L = level_view(a, 0, b, 0u);
-        blk_nodes(L.d.g, [&](int, int, long long p) { L.u[p] = L.t[p]; });
+    // zero every plane (the frames must read zero), then load the top level
+    {
+        const long long total = a.lds_bytes / (long long)sizeof(cplx<T>);
+        for (long long q = thread_linear(); q < total; q += kTailThreads) lds[q] = cplx<T>{T(0), T(0)};
+        __syncthreads();
+        const TLv<T> L = tail_level(a, 0, lds);
+        const long long off = (long long)b * L.g.plane;
+        tnodes(L, [&](int, int, int li, long long gp) {
+            L.u()[li] = a.u_top[off + gp];
+            L.f()[li] = a.f_top[off + gp];
+        });
         __syncthreads();
     }
+    const double inv_omega = 1.0 / a.omega;
+    const bool bez = a.bez != 0;
+    // Cycle state machine with a single smoothing site (keeps the GMRES
+    // passes inlined once): going down, level q is pre-smoothed and its
+    // residual restricted; coming back up after its last coarse visit, the
+    // correction is prolongated and q is post-smoothed.
+    unsigned visits = 0u;  // 2 bits per level: coarse visits left
+    int q = 0;
+    bool up = false;
+    if (last == 0) {
+        tail_coarse(tail_level(a, 0, lds), a.inv);
+    } else {
+        for (;;) {
+            int nu;
+            if (!up) {
+                if (q == last) {
+                    tail_coarse(tail_level(a, q, lds), a.inv);
+                    q -= 1;
+                    up = true;
+                    continue;
+                }
+                nu = a.nu1;
+            } else {
+                // back from one visit of level q + 1
+                const unsigned left = ((visits >> (2 * q)) & 3u) - 1u;
+                visits = (visits & ~(3u << (2 * q))) | (left << (2 * q));
+                if (left > 0) {
+                    q += 1;
+                    up = false;
+                    continue;
+                }
+                tail_prolong(tail_level(a, q + 1, lds), tail_level(a, q, lds), bez);
+                nu = a.nu2;
+            }
+            {
+                const TLv<T> L = tail_level(a, q, lds);
+                for (int s = 0; s < nu; ++s) {
+                    if (a.smoother == 0) tail_jacobi(L, inv_omega);
+                    else tail_gmres(L, a.breakdown);
+                }
+            }
+            if (!up) {
+                tail_residual_restrict(tail_level(a, q, lds), tail_level(a, q + 1, lds), bez);
+                visits = (visits & ~(3u << (2 * q))) | (unsigned(a.gamma) << (2 * q));
+                q += 1;
+            } else {
+                if (q == 0) break;
+                q -= 1;
+            }
+        }
+    }
+    const TLv<T> L = tail_level(a, 0, lds);
+    const long long off = (long long)b * L.g.plane;
+    tnodes(L, [&](int, int, int li, long long gp) { a.u_top[off + gp] = L.u()[li]; });
+}
+
+// X = A^{-1} from the row-major LU factor with row swaps piv (X = U^{-1} L^{-1} P),
+// N <= kTailMaxCoarseNodes, X staged in LDS.
+constexpr int kInvThreads = 1024;
+__global__ __launch_bounds__(kInvThreads) void k_lu_inverse(int N, const cplx<double>* LU, const int* piv,
+                                                           cplx<double>* inv) {
+    cplx<double>* X = reinterpret_cast<cplx<double>*>(hm_dyn_lds);
+    __shared__ int perm[kTailMaxCoarseNodes];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        for (int r = 0; r < N; ++r) perm[r] = r;
+        for (int k = 0; k < N; ++k) {
+            const int p = piv[k];
+            const int t = perm[k];
+            perm[k] = perm[p];
+            perm[p] = t;
+        }
+    }
+    __syncthreads();
+    // (P I)[r][c] = 1 where perm[r] == c
+    for (int t = tid; t < N * N; t += kInvThreads) X[t] = cplx<double>{perm[t / N] == t % N ? 1.0 : 0.0, 0.0};
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {  // unit lower
+        const int rem = N - k - 1;
+        for (int t = tid; t < rem * N; t += kInvThreads) {
+            const int r = k + 1 + t / N, c = t % N;
+            X[r * N + c] = X[r * N + c] - LU[(long long)r * N + k] * X[k * N + c];
+        }
+        __syncthreads();
+    }
+    for (int k = N - 1; k >= 0; --k) {  // upper
+        const cplx<double> d = LU[(long long)k * N + k];
+        for (int c = tid; c < N; c += kInvThreads) X[k * N + c] = cdiv(X[k * N + c], d);
+        __syncthreads();
+        for (int t = tid; t < k * N; t += kInvThreads) {
+            const int r = t / N, c = t % N;
+            X[r * N + c] = X[r * N + c] - LU[(long long)r * N + k] * X[k * N + c];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < N * N; t += kInvThreads) inv[t] = X[t];
 }
 
 }  // namespace
 
+void tail_init() {
+    static const bool done = [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kTailMaxLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(kTailMaxLdsBytes));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lu_inverse),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(kTailMaxCoarseNodes * kTailMaxCoarseNodes * sizeof(cplx<double>)));
+        return true;
+    }();
+    (void)done;
+}
+
 template <typename T>
 void launch_tail(const LaunchCtx& ctx, const TailArgs<T>& args) {
-    hipLaunchKernelGGL((k_tail<T>), dim3(ctx.nrhs), dim3(kBX, kTailBY), 0, ctx.stream, args, ctx.active);
+    hipLaunchKernelGGL((k_tail<T>), dim3(ctx.nrhs), dim3(kBX, kTailBY), size_t(args.lds_bytes), ctx.stream, args,
+                       ctx.active);
 }
 template void launch_tail<double>(const LaunchCtx&, const TailArgs<double>&);
 template void launch_tail<float>(const LaunchCtx&, const TailArgs<float>&);
+
+void launch_lu_inverse(hipStream_t s, int N, const cplx<double>* lu, const int* piv, cplx<double>* inv) {
+    hipLaunchKernelGGL(k_lu_inverse, dim3(1), dim3(kInvThreads), size_t(N) * N * sizeof(cplx<double>), s, N, lu, piv,
+                       inv);
+}
 
 }  // namespace hm

@@ -208,10 +208,12 @@ class Solver:
         return u
 
     def cycle(self, u: torch.Tensor, f_s: torch.Tensor, cycle="V", smoother="gmres", nu_pre=1, nu_post=1,
-              omega=4.5) -> torch.Tensor:
-        uv = _batched(u, self.n, torch.complex128).clone()
-        fv = _batched(f_s, self.n, torch.complex128)
-        opts = self.solve_options(nu_pre, nu_post, omega, 1, "fp64")
+              omega=4.5, precision="fp64") -> torch.Tensor:
+        """mg_cycle: one cycle; complex128 data, or complex64 with precision="fp32_refined"."""
+        dt = torch.complex64 if precision == "fp32_refined" else torch.complex128
+        uv = _batched(u, self.n, dt).clone()
+        fv = _batched(f_s, self.n, dt)
+        opts = self.solve_options(nu_pre, nu_post, omega, 1, precision)
         _check(B.lib().mg_cycle(self.handle, _ptr(uv), _ptr(fv), uv.shape[0], _CYCLE[cycle], _SMOOTHER[smoother],
                                 ctypes.byref(opts), _stream()), self.handle)
         return uv

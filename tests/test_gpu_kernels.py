@@ -175,17 +175,19 @@ def test_full_size_level_operations_on_sampled_rows():
             assert diff <= 1e-13 * abs(H.A[l]).max(), l
 
 
+@pytest.mark.parametrize("tail_n", ["0", "16"])
 @pytest.mark.parametrize("cyc,smoother", [("V", "gmres"), ("W", "gmres"), ("W", "jacobi")])
-def test_one_cycle_with_single_workgroup_tail(monkeypatch, cyc, smoother):
-    """The coarse tail (levels of at most 16 intervals in one workgroup per right-hand
-    side) gives the same cycle as the oracle."""
+def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
+    """Levels of at most 32 intervals normally run in the single-workgroup LDS
+    tail; with the tail off (every level launched kernel by kernel) or starting
+    at 16 intervals the cycle is the oracle's as well, in FP64 and FP32."""
     require_gpu()
     from paper_2308_13476_amd.solver import Solver
-    monkeypatch.setenv("HELMG_TAIL_N", "16")
+    monkeypatch.setenv("HELMG_TAIL_N", tail_n)
     n = 64
     k2 = W.random_k2(n, 9, 8.0, 18.0)
     H = O.build_hierarchy(k2, 1.0 / n, 0.3)
-    S = Solver(to_gpu(k2), 1.0 / n, 0.3, max_batch=2)
+    S = Solver(to_gpu(k2), 1.0 / n, 0.3, max_batch=2, precision="fp32_refined")
     u = _rand(n, 2, 120)
     f = _rand(n, 2, 121)
     got = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, smoother=smoother, nu_pre=2, nu_post=1))
@@ -193,3 +195,7 @@ def test_one_cycle_with_single_workgroup_tail(monkeypatch, cyc, smoother):
     for b in range(2):
         ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
         assert rel(got[b], ref) <= 1e-10, (b, rel(got[b], ref))
+    got32 = to_np(S.cycle(to_gpu(u.astype(np.complex64)), to_gpu(f.astype(np.complex64)), cycle=cyc,
+                          smoother=smoother, nu_pre=2, nu_post=1, precision="fp32_refined"))
+    ref = O.cycle(H, 0, u[0].ravel(), f[0].ravel(), opts)
+    assert rel(got32[0], ref) <= 1e-4, rel(got32[0], ref)
