@@ -64,8 +64,8 @@ void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
-// One GMRES(3) smoothing step (§5.3) on A u = f: six passes (residual; apply;
-// two fused orthogonalise + apply passes; last norm; least squares + update).
+// One GMRES(3) smoothing step (§5.3) on A u = f: five passes (residual; apply;
+// two fused orthogonalise + apply passes; last column + least squares + update).
 // Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
 // products A z. `between(arg, i)` (may be null) is called on the host after
 // the i-th launch of the Arnoldi passes (timing hook).

@@ -328,7 +328,8 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
 // Passes 3 and 4 (J = 1, 2): finish Arnoldi column J-1 from the previous
 // pass's sums, then build z_J = s_{J-1} w_{J-1} - sum_i H[i][J-1] s_i z_i,
 // w_J = A z_J (z_J recomputed at the stencil neighbours), partials
-// ||z_J||^2 and <z_i, w_J> for i <= J.
+// ||z_J||^2 and <z_i, w_J> for i <= J, and for J = 2 also ||w_2||^2 (the last
+// Arnoldi norm then follows without another pass over the vectors).
 template <typename Op, typename T, int J, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
@@ -396,9 +397,10 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
         }
         return v;
     };
-    double acc[1 + 2 * (J + 1)];
+    constexpr int KOUT = 1 + 2 * (J + 1) + (J == 2 ? 1 : 0);
+    double acc[KOUT];
 #pragma unroll
-    for (int q = 0; q < 1 + 2 * (J + 1); ++q) acc[q] = 0.0;
+    for (int q = 0; q < KOUT; ++q) acc[q] = 0.0;
     for_nodes_applied<Op, T>(op, rpt, znew, [&](int, int, long long p, cplx<T> zp, cplx<T> w) {
         zJ[p] = zp;
         wo[p] = w;
@@ -406,95 +408,63 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
 #pragma unroll
         for (int q = 0; q < J; ++q) acc_dot(acc[1 + 2 * q], acc[2 + 2 * q], z[q][p], w);
         acc_dot(acc[1 + 2 * J], acc[2 + 2 * J], zp, w);
+        if constexpr (J == 2) acc[KOUT - 1] += dnorm2(w);
     });
-    block_partials<1 + 2 * (J + 1)>(acc, pout + b * kPartStride);
+    block_partials<KOUT>(acc, pout + b * kPartStride);
 }
 
-// Pass 5: finish column 2 from pass 4, and the norm of z_3 = s_2 w_2 - sum H[i][2] s_i z_i.
+// Pass 5: column 2 of H from pass 4's sums (unless the Arnoldi process
+// stopped early), the least-squares problem and u += sum y_i s_i z_i.
+// H[3][2] = ||z_3|| for z_3 = s_2 w_2 - sum_i H[i][2] s_i z_i comes from
+// ||z_3||^2 = s_2^2 ||w_2||^2 - sum_i |H[i][2]|^2 (the s_i z_i are orthonormal),
+// clamped at zero. Every thread reduces the sums and solves the small problem
+// in registers.
 template <typename T, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_gm_o3(Grid g, Vec<T> Z, Vec<T> Win, GmState* st, double breakdown,
-                                                    const double* pin, int nblk_in, double* pout, const int* active,
-                                                    int rpt) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
-    double t[7];
-    reduce_partials<7>(pin + b * kPartStride, nblk_in, t);
-    const GmState& S0 = st[b];
-    const double hn = sqrt(t[0]);
-    const bool broke = !(hn > breakdown * S0.beta);
-    const double s2 = broke ? 0.0 : 1.0 / hn;
-    const double sv[3] = {S0.s[0], S0.s[1], s2};
-    double hr[3], hi[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        hr[q] = sv[q] * s2 * t[1 + 2 * q];
-        hi[q] = sv[q] * s2 * t[2 + 2 * q];
-    }
-    if (lead_thread()) {
-        GmState& S = st[b];
-        S.hr[2][1] = hn;
-        S.hi[2][1] = 0.0;
-        if (broke) {
-            S.k = 2;
-            S.arnoldi_done = 1;
-        } else {
-            S.s[2] = s2;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                S.hr[q][2] = hr[q];
-                S.hi[q][2] = hi[q];
-            }
-        }
-    }
-    if (broke) return;
-    cplx<T> c[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = {T(hr[q] * sv[q]), T(hi[q] * sv[q])};
-    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
-    const cplx<T>* wi = Win.rhs(b);
-    const T sT = T(s2);
-    double acc[1] = {0.0};
-    for_nodes(g, rpt, [&](int, int, long long p) {
-        cplx<T> v = sT * wi[p];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const cplx<T> zq = z0[p + (long long)a * Z.plane];
-            v.re -= c[a].re * zq.re - c[a].im * zq.im;
-            v.im -= c[a].re * zq.im + c[a].im * zq.re;
-        }
-        acc[0] += dnorm2(v);
-    });
-    block_partials<1>(acc, pout + b * kPartStride);
-}
-
-// Pass 6: H[3][2] from pass 5 (unless the Arnoldi process stopped early), the
-// small least-squares problem (one thread, shared memory), u += sum y_i s_i z_i.
-template <typename T, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, GmState* st, const double* pin,
-                                                   int nblk_in, const int* active, int rpt) {
+__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, const GmState* st, double breakdown,
+                                                   const double* pin, int nblk_in, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
-    const int k0 = st[b].k;
-    if (k0 == 0) return;
-    const bool full = !st[b].arnoldi_done;
-    double t[1] = {0.0};
-    if (full) reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
-    __shared__ GmState S;
-    __shared__ LsWork ls;
-    if (thread_linear() == 0) {
-        S = st[b];
-        if (full) {
-            S.hr[3][2] = sqrt(t[0]);
-            S.hi[3][2] = 0.0;
-            S.k = 3;
+    const GmState S = st[b];
+    if (S.k == 0) return;
+    double t[8];
+    reduce_partials<8>(pin + b * kPartStride, nblk_in, t);  // read in any case; used after a full Arnoldi pass
+    double hr[4][3], hi[4][3], s[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hr[a][c] = S.hr[a][c];
+            hi[a][c] = S.hi[a][c];
         }
-        gm_least_squares(S, ls);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[q] = S.s[q];
+    int k = S.k;
+    if (!S.arnoldi_done) {
+        const double hn = sqrt(t[0]);
+        if (!(hn > breakdown * S.beta)) {
+            k = 2;
+        } else {
+            const double s2 = 1.0 / hn;
+            s[2] = s2;
+            hr[2][1] = hn;
+            hi[2][1] = 0.0;
+            double sq = s2 * s2 * t[7];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                hr[q][2] = s[q] * s2 * t[1 + 2 * q];
+                hi[q][2] = s[q] * s2 * t[2 + 2 * q];
+                sq -= hr[q][2] * hr[q][2] + hi[q][2] * hi[q][2];
+            }
+            hr[3][2] = sqrt(fmax(sq, 0.0));
+            hi[3][2] = 0.0;
+            k = 3;
+        }
     }
-    __syncthreads();
-    const int k = S.k;
+    double yr[3], yi[3];
+    gm_least_squares_regs(hr, hi, s, S.beta, k, yr, yi);
     cplx<T> c[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = {T(S.yr[q]), T(S.yi[q])};
+    for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     cplx<T>* ub = u.rhs(b);
     for_nodes(g, rpt, [&](int, int, long long p) {
@@ -730,8 +700,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 3);
     });
-    HM_LAUNCH(qv, (k_gm_o3<T, BY>), lop.g, Z, Wa, st, breakdown, B, nb_op, A, HM_ACTIVE, qv.rpt);
-    HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, A, qv.nblk, HM_ACTIVE, qv.rpt);
+    HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
 }
 
 void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
