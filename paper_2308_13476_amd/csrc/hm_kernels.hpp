@@ -68,10 +68,13 @@ void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, 
 // two fused orthogonalise + apply passes; last column + least squares + update).
 // Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
 // products A z. `between(arg, i)` (may be null) is called on the host after
-// the i-th launch of the Arnoldi passes (timing hook).
+// the i-th launch of the Arnoldi passes (timing hook). With res.p set, the
+// last pass writes the updated iterate to unew (u is left as it was) and the
+// residual f - A unew to res; unew and res may be Wb and Wa.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
-                       GmState* st, double breakdown, void (*between)(void*, int), void* between_arg);
+                       GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
+                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0});
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

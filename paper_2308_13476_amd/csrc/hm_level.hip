@@ -96,35 +96,28 @@ __device__ __forceinline__ double dnorm2(cplx<T> z) {
     return double(z.re) * double(z.re) + double(z.im) * double(z.im);
 }
 
-// Runs f(i, j, p, A x at p) over the thread's nodes, where x is given by the
-// element getter xget. Galerkin levels first stage x for the block tile plus
-// halo in LDS (one global read per tile node instead of one per stencil
-// entry); the level-0 five-point operator reads x directly.
+// Runs f(i, j, p, x at p, A x at p) over the thread's nodes, where x is given
+// by the element getter xget: x for the block tile plus halo is staged in LDS
+// first (one evaluation of the getter per tile node instead of one per
+// stencil entry), then the operator reads LDS only.
 template <typename Op, typename T, typename XGet, typename F>
 __device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& xget, F&& f) {
-    if constexpr (is_stencil<Op>::value) {
-        constexpr int R = is_stencil<Op>::radius;
-        cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
-        const Tile<R> tl = block_tile<R>(rpt);
-        fill_tile<T, R>(lds, tl, op.g, xget);
-        for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-            const int li = tl.at(i, j);
-            f(i, j, p, lds[li], apply_tile(op, lds, li, p));
-        });
-    } else {
-        for_nodes(op.g, rpt, [&](int i, int j, long long p) { f(i, j, p, xget(p), op.apply_at(xget, i, j, p)); });
-    }
+    constexpr int R = op_radius<Op>::value;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<R> tl = block_tile<R>(rpt);
+    fill_tile<T, R>(lds, tl, op.g, xget);
+    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
+        const int li = tl.at(i, j);
+        if constexpr (is_stencil<Op>::value) f(i, j, p, lds[li], apply_tile(op, lds, li, p));
+        else f(i, j, p, lds[li], apply_tile(op, lds, li, i, j, p));
+    });
 }
 
 // Dynamic LDS bytes of an operator kernel launched with geometry (by, rpt).
 template <typename Op, typename T>
 size_t tile_bytes(int by, int rpt) {
-    if constexpr (is_stencil<Op>::value) {
-        constexpr int R = is_stencil<Op>::radius;
-        return size_t(Tile<R>::TW) * size_t(by * rpt + 2 * R) * sizeof(cplx<T>);
-    } else {
-        return 0;
-    }
+    constexpr int R = op_radius<Op>::value;
+    return size_t(Tile<R>::TW) * size_t(by * rpt + 2 * R) * sizeof(cplx<T>);
 }
 
 // ---------------------------------------------------------------- operator
@@ -413,32 +406,33 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     block_partials<KOUT>(acc, pout + b * kPartStride);
 }
 
-// Pass 5: column 2 of H from pass 4's sums (unless the Arnoldi process
-// stopped early), the least-squares problem and u += sum y_i s_i z_i.
-// H[3][2] = ||z_3|| for z_3 = s_2 w_2 - sum_i H[i][2] s_i z_i comes from
+// Pass 5 prologue: column 2 of H from pass 4's sums (unless the Arnoldi
+// process stopped early), the least-squares problem, and the update weights
+// c_i = y_i s_i (k = 0: nothing to add). H[3][2] = ||z_3|| for
+// z_3 = s_2 w_2 - sum_i H[i][2] s_i z_i comes from
 // ||z_3||^2 = s_2^2 ||w_2||^2 - sum_i |H[i][2]|^2 (the s_i z_i are orthonormal),
 // clamped at zero. Every thread reduces the sums and solves the small problem
 // in registers.
-template <typename T, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, const GmState* st, double breakdown,
-                                                   const double* pin, int nblk_in, const int* active, int rpt) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
+template <typename T>
+__device__ __forceinline__ int gm_update_weights(const GmState* st, int b, double breakdown, const double* pin,
+                                                 int nblk_in, cplx<T> (&c)[3]) {
     const GmState S = st[b];
-    if (S.k == 0) return;
     double t[8];
     reduce_partials<8>(pin + b * kPartStride, nblk_in, t);  // read in any case; used after a full Arnoldi pass
+    int k = S.k;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[q] = {T(0), T(0)};
+    if (k == 0) return 0;
     double hr[4][3], hi[4][3], s[3];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            hr[a][c] = S.hr[a][c];
-            hi[a][c] = S.hi[a][c];
+        for (int cc = 0; cc < 3; ++cc) {
+            hr[a][cc] = S.hr[a][cc];
+            hi[a][cc] = S.hi[a][cc];
         }
 #pragma unroll
     for (int q = 0; q < 3; ++q) s[q] = S.s[q];
-    int k = S.k;
     if (!S.arnoldi_done) {
         const double hn = sqrt(t[0]);
         if (!(hn > breakdown * S.beta)) {
@@ -462,9 +456,20 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, c
     }
     double yr[3], yi[3];
     gm_least_squares_regs(hr, hi, s, S.beta, k, yr, yi);
-    cplx<T> c[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
+    return k;
+}
+
+// Pass 5: u += sum y_i s_i z_i.
+template <typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, const GmState* st, double breakdown,
+                                                   const double* pin, int nblk_in, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    cplx<T> c[3];
+    const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
+    if (k == 0) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     cplx<T>* ub = u.rhs(b);
     for_nodes(g, rpt, [&](int, int, long long p) {
@@ -473,6 +478,37 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, c
         if (k > 1) x = cfma(x, c[1], z0[p + Z.plane]);
         if (k > 2) x = cfma(x, c[2], z0[p + 2 * Z.plane]);
         ub[p] = x;
+    });
+}
+
+// Pass 5 fused with the residual that follows the last pre-smoothing step:
+// u_new = u + sum y_i s_i z_i goes to unew (a different buffer: neighbouring
+// blocks still read u), r = f - A u_new to r.
+template <typename Op, typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u, Vec<T> f, Vec<T> unew, Vec<T> r,
+                                                       const GmState* st, double breakdown, const double* pin,
+                                                       int nblk_in, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    cplx<T> c[3];
+    const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
+    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    const cplx<T>* z1 = z0 + Z.plane;
+    const cplx<T>* z2 = z1 + Z.plane;
+    const cplx<T>* ub = u.rhs(b);
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* nb = unew.rhs(b);
+    cplx<T>* rb = r.rhs(b);
+    auto getu = [&](long long q) {
+        cplx<T> x = ub[q];
+        if (k > 0) x = cfma(x, c[0], z0[q]);
+        if (k > 1) x = cfma(x, c[1], z1[q]);
+        if (k > 2) x = cfma(x, c[2], z2[q]);
+        return x;
+    };
+    for_nodes_applied<Op, T>(op, rpt, getu, [&](int, int, long long p, cplx<T> up, cplx<T> au) {
+        nb[p] = up;
+        rb[p] = fb[p] - au;
     });
 }
 
@@ -525,11 +561,12 @@ __global__ __launch_bounds__(kBX * BY) void k_refine_residual(FineOp<double> op,
     const cplx<double>* fb = f.rhs(b);
     cplx<float>* rb = r32.rhs(b);
     double acc[1] = {0.0};
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const cplx<double> r = fb[p] - op.apply(xb, i, j, p);
-        rb[p] = cast<float>(r);
-        acc[0] += dnorm2(r);
-    });
+    for_nodes_applied<FineOp<double>, double>(op, rpt, [xb](long long q) { return xb[q]; },
+                                              [&](int, int, long long p, cplx<double>, cplx<double> ax) {
+                                                  const cplx<double> r = fb[p] - ax;
+                                                  rb[p] = cast<float>(r);
+                                                  acc[0] += dnorm2(r);
+                                              });
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
@@ -546,12 +583,13 @@ __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op
     cplx<float>* rb = r32.rhs(b);
     double acc[1] = {0.0};
     auto xnew = [xb, eb](long long q) { return xb[q] + cast<double>(eb[q]); };
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        ob[p] = xnew(p);
-        const cplx<double> r = fb[p] - op.apply_at(xnew, i, j, p);
-        rb[p] = cast<float>(r);
-        acc[0] += dnorm2(r);
-    });
+    for_nodes_applied<FineOp<double>, double>(op, rpt, xnew,
+                                              [&](int, int, long long p, cplx<double> xp, cplx<double> ax) {
+                                                  ob[p] = xp;
+                                                  const cplx<double> r = fb[p] - ax;
+                                                  rb[p] = cast<float>(r);
+                                                  acc[0] += dnorm2(r);
+                                              });
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
@@ -681,7 +719,8 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
-                       Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg) {
+                       Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
+                       Vec<T> unew, Vec<T> res) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx.nrhs);  // vector-only passes
@@ -699,8 +738,11 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         if (between) between(between_arg, 2);
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 3);
+        if (res.p)
+            HM_LAUNCH_OP(q, (k_gm_u_res<Op, T, BY>), op, Z, u, f, unew, res, st, breakdown, B, nb, HM_ACTIVE,
+                         q.rpt);
     });
-    HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
+    if (!res.p) HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
 }
 
 void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
@@ -730,17 +772,21 @@ void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
 
 void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
                             Vec<float> r32, RhsNorms* norms) {
+    using Op = FineOp<double>;
+    using T = double;
     const Geom q = geom(lop.g, false, ctx.nrhs);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    HM_LAUNCH(q, (k_refine_residual<BY>), op, x, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
+    HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 1);
 }
 
 void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
                              Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms) {
+    using Op = FineOp<double>;
+    using T = double;
     const Geom q = geom(lop.g, false, ctx.nrhs);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    HM_LAUNCH(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
+    HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 1);
 }
 
@@ -798,7 +844,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>);                \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
-                                       Vec<T>, GmState*, double, void (*)(void*, int), void*);                  \
+                                       Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>);  \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

@@ -31,17 +31,20 @@ struct FineOp {
         if (s) im = -two_h * T(s) * sqrt(kk);
         return {W * (T(4) * ih2 - kk), W * im};
     }
-    template <typename X>
-    __device__ __forceinline__ cplx<T> apply_at(const X& x, int i, int j, long long p) const {
+    // (A_s x)_p from the centre value and the west, east, south, north neighbours
+    __device__ __forceinline__ cplx<T> apply5(int i, int j, long long p, cplx<T> c, cplx<T> xw, cplx<T> xe,
+                                              cplx<T> xs, cplx<T> xn) const {
         const int n = g.n;
         const cplx<T> d = diag(i, j, p);
-        const cplx<T> c = x(p);
-        const cplx<T> xw = x(p - 1), xe = x(p + 1), xs = x(p - g.pitch), xn = x(p + g.pitch);
         const T cx = ih2 * line_w<T>(j, n), cy = ih2 * line_w<T>(i, n);
         cplx<T> y = d * c;
         y.re -= cx * (xw.re + xe.re) + cy * (xs.re + xn.re);
         y.im -= cx * (xw.im + xe.im) + cy * (xs.im + xn.im);
         return y;
+    }
+    template <typename X>
+    __device__ __forceinline__ cplx<T> apply_at(const X& x, int i, int j, long long p) const {
+        return apply5(i, j, p, x(p), x(p - 1), x(p + 1), x(p - g.pitch), x(p + g.pitch));
     }
     __device__ __forceinline__ cplx<T> apply(const cplx<T>* __restrict__ x, int i, int j, long long p) const {
         return apply_at([x](long long q) { return x[q]; }, i, j, p);
@@ -107,17 +110,28 @@ __device__ __forceinline__ Tile<R> block_tile(int rpt) {
 
 // lds[t.at(i, j)] = get(g.at(i, j)) for every tile node inside the padded
 // frame (ghosts read as stored, zero); nodes beyond it hold zero and are
-// never used by an in-domain stencil.
+// never used by an in-domain stencil. Each thread gathers up to kFillBatch
+// values before storing any, so that their loads are in flight together.
+constexpr int kFillBatch = 8;
 template <typename T, int R, typename Get>
 __device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const Grid& g, Get&& get) {
     const int total = t.count();
     const int nt = blockDim.x * blockDim.y;
-    for (int q = threadIdx.y * kBX + threadIdx.x; q < total; q += nt) {
-        const int i = t.c0 - R + q % Tile<R>::TW;
-        const int j = t.r0 - R + q / Tile<R>::TW;
-        cplx<T> v{T(0), T(0)};
-        if (i >= -R && j >= -R && i <= g.n + R && j <= g.n + R) v = get(g.at(i, j));
-        lds[q] = v;
+    for (int q0 = threadIdx.y * kBX + threadIdx.x; q0 < total; q0 += kFillBatch * nt) {
+        cplx<T> v[kFillBatch];
+#pragma unroll
+        for (int u = 0; u < kFillBatch; ++u) {
+            const int q = q0 + u * nt;
+            const int i = t.c0 - R + q % Tile<R>::TW;
+            const int j = t.r0 - R + q / Tile<R>::TW;
+            v[u] = cplx<T>{T(0), T(0)};
+            if (q < total && i >= -R && j >= -R && i <= g.n + R && j <= g.n + R) v[u] = get(g.at(i, j));
+        }
+#pragma unroll
+        for (int u = 0; u < kFillBatch; ++u) {
+            const int q = q0 + u * nt;
+            if (q < total) lds[q] = v[u];
+        }
     }
     __syncthreads();
 }
@@ -136,6 +150,14 @@ __device__ __forceinline__ cplx<T> apply_tile(const StencilOp<T, R>& op, const c
     return y;
 }
 
+// Level-0 operator applied at tile index li from LDS.
+template <typename T>
+__device__ __forceinline__ cplx<T> apply_tile(const FineOp<T>& op, const cplx<T>* lds, int li, int i, int j,
+                                              long long p) {
+    constexpr int TW = Tile<1>::TW;
+    return op.apply5(i, j, p, lds[li], lds[li - 1], lds[li + 1], lds[li - TW], lds[li + TW]);
+}
+
 template <typename Op>
 struct is_stencil {
     static constexpr bool value = false;
@@ -144,6 +166,16 @@ template <typename T, int R>
 struct is_stencil<StencilOp<T, R>> {
     static constexpr bool value = true;
     static constexpr int radius = R;
+};
+
+// Halo width of an operator's LDS tile.
+template <typename Op>
+struct op_radius {
+    static constexpr int value = 1;  // level-0 five-point operator
+};
+template <typename T, int R>
+struct op_radius<StencilOp<T, R>> {
+    static constexpr int value = R;
 };
 
 __device__ __forceinline__ bool rhs_active(const int* active, int b) { return active == nullptr || active[b] != 0; }

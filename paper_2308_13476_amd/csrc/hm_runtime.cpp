@@ -400,8 +400,11 @@ struct CycleParams {
     double omega;
 };
 
+// One smoothing step on level l. With then_residual (GMRES only), the step's
+// last pass also forms the residual f - A u into the level's w buffer; the
+// updated iterate then lands in t and the u / t buffers exchange roles.
 template <typename T>
-void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
+void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -441,9 +444,14 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
         }
     } hook{c, lc.stream, nodes};
     const bool timed = c->timing_class == (l == 0 ? 1 : (l == 1 ? 4 : -1));
+    const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
-                         vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::t_ref(lb), lb), c->gm, Prec<T>::breakdown,
-                         timed ? &Hook::cb : nullptr, &hook);
+                         w, t, c->gm, Prec<T>::breakdown, timed ? &Hook::cb : nullptr, &hook,
+                         then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0});
+    if (then_residual) {
+        std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
+        if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
+    }
 }
 
 template <typename T>
@@ -482,9 +490,13 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
         return;
     }
     LevelBuf& cb = c->lv[l + 1];
-    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp);
-    launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
-                       vec<T>(Prec<T>::w(lb), lb));
+    // on Galerkin levels the last GMRES pre-smoothing step also forms the
+    // residual to restrict
+    const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && l > 0;
+    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1);
+    if (!fused)
+        launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
+                           vec<T>(Prec<T>::w(lb), lb));
     launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::f(cb), cb),
                        vec<T>(Prec<T>::u(cb), cb));
     for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp);

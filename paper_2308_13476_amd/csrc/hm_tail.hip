@@ -221,37 +221,23 @@ __device__ void tail_gmres(const TLv<T>& L, double breakdown) {
             return;
         }
         s[2] = 1.0 / hr[2][1];
-        // column 2
-        double a6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t6[6];
+        // column 2; ||z_3||^2 = s_2^2 ||w||^2 - sum |H[i][2]|^2 (orthonormal s_i z_i)
+        double a7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t7[7];
         tnodes(L, [&](int, int, int li, long long gp) {
             const cplx<T> w = tapply<T, R>(L, z2, li, gp);
-            wa[li] = w;
-            tdot(a6[0], a6[1], z0[li], w);
-            tdot(a6[2], a6[3], z1[li], w);
-            tdot(a6[4], a6[5], z2[li], w);
+            tdot(a7[0], a7[1], z0[li], w);
+            tdot(a7[2], a7[3], z1[li], w);
+            tdot(a7[4], a7[5], z2[li], w);
+            a7[6] += tn2(w);
         });
-        block_sum<6>(a6, t6);
+        block_sum<7>(a7, t7);
+        double sq = s[2] * s[2] * t7[6];
         for (int q = 0; q < 3; ++q) {
-            hr[q][2] = s[q] * s[2] * t6[2 * q];
-            hi[q][2] = s[q] * s[2] * t6[2 * q + 1];
+            hr[q][2] = s[q] * s[2] * t7[2 * q];
+            hi[q][2] = s[q] * s[2] * t7[2 * q + 1];
+            sq -= hr[q][2] * hr[q][2] + hi[q][2] * hi[q][2];
         }
-        {
-            cplx<T> c[3];
-            for (int q = 0; q < 3; ++q) c[q] = {T(hr[q][2] * s[q]), T(hi[q][2] * s[q])};
-            const T sc = T(s[2]);
-            a1[0] = 0.0;
-            tnodes(L, [&](int, int, int li, long long) {
-                cplx<T> v = sc * wa[li];
-                const cplx<T> q0 = z0[li], q1 = z1[li], q2 = z2[li];
-                v.re -= c[0].re * q0.re - c[0].im * q0.im + c[1].re * q1.re - c[1].im * q1.im + c[2].re * q2.re -
-                        c[2].im * q2.im;
-                v.im -= c[0].re * q0.im + c[0].im * q0.re + c[1].re * q1.im + c[1].im * q1.re + c[2].re * q2.im +
-                        c[2].im * q2.re;
-                a1[0] += tn2(v);
-            });
-            block_sum<1>(a1, t1);
-        }
-        hr[3][2] = sqrt(t1[0]);
+        hr[3][2] = sqrt(fmax(sq, 0.0));
         hi[3][2] = 0.0;
     });
     if (k == 0) return;
