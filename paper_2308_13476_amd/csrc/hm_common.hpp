@@ -67,9 +67,10 @@ constexpr int kBY = 4;      // short blocks (register-heavy stencils, small grid
 constexpr int kMaxBY = 16;  // tall blocks (light kernels on large grids)
 
 // A level kernel launches at most kMaxPartialBlocks blocks per right-hand
-// side (the launch cap itself is a runtime setting <= this capacity);
-// reductions keep up to 8 partial sums per block in each of two regions.
-constexpr int kMaxPartialBlocks = 2560;
+// side; reductions keep up to 8 partial sums per block in each of two
+// regions. Consumers reduce the partials themselves up to the runtime block
+// cap; above it a one-block pass pre-reduces them first.
+constexpr int kMaxPartialBlocks = 8192;
 constexpr long long kPartStride = (long long)kMaxPartialBlocks * 8;  // doubles per (region, right-hand side)
 
 // Boundary weight w of a grid line position (1/2 at both ends).

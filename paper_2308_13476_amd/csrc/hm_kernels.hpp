@@ -31,7 +31,7 @@ struct LaunchCtx {
     const int* active;  // [nrhs] device flags; 0 skips that right-hand side
     double* partials;   // per-block partial sums: 2 regions x nrhs_cap x kPartStride doubles
     int nrhs_cap;       // right-hand sides the partials were sized for
-    int rpt;            // unused: rows per thread follow from the level size
+    int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
 };
 
 // The operator of one level: analytic on level 0 (from k^2), stored Galerkin
@@ -43,7 +43,13 @@ struct LevelOp {
     int radius;
     const cplx<T>* coef;  // [(2r+1)^2][plane], levels >= 1
     const T* k2;          // padded k^2 plane, level 0
-    double h;
+    double h;             // level-0 mesh width
+    // Level 1 applied as the product R C_s P from level-0 data (product != 0):
+    // level-0 grid, shift beta2 of C_s, transfer (0 Bezier, 1 linear).
+    int product;
+    Grid g0;
+    double shift;
+    int transfer;
 };
 
 // Vectors of one level in the padded layout: `count` consecutive planes.

@@ -24,23 +24,12 @@ int tall_rows() {
 }
 int block_rows(const Grid& g, bool heavy) { return (!heavy && g.n >= 256) ? tall_rows() : kBY; }
 
-// Block cap of a level grid: every consumer of a reduction reads all partial
-// sums of its producer, so more blocks cost more of those reads.
-// HELMG_MAX_BLOCKS overrides the default (at most kMaxPartialBlocks).
-int block_cap() {
-    static const int cap = [] {
-        int v = 640;
-        if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) v = std::atoi(e);
-        return v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
-    }();
-    return cap;
-}
-
-// Rows per thread: enough that a level grid has at most block_cap() blocks.
-int level_rpt(const Grid& g, int by) {
+// Rows per thread: enough that a level grid has at most `cap` blocks (the
+// block cap of the context: every consumer of a reduction reads all partial
+// sums of its producer, so more blocks cost more of those reads).
+int level_rpt(const Grid& g, int by, int cap) {
     const long long m = g.n + 1;
     const long long bx = (m + kBX - 1) / kBX;
-    const long long cap = block_cap();
     const long long r = (m * bx + (long long)by * cap - 1) / ((long long)by * cap);
     return int(r < 1 ? 1 : r);
 }
@@ -54,13 +43,29 @@ struct Geom {
     dim3 grid, block;
 };
 
-Geom geom(const Grid& g, bool heavy, int nrhs) {
+Geom geom(const Grid& g, bool heavy, int nrhs, int cap) {
     Geom q;
     q.by = block_rows(g, heavy);
-    q.rpt = level_rpt(g, q.by);
+    q.rpt = level_rpt(g, q.by, cap);
     q.grid = level_grid(g, q.rpt, nrhs, q.by);
     q.block = dim3(kBX, q.by);
     q.nblk = int(q.grid.x * q.grid.y);
+    return q;
+}
+
+// Geometry of an operator kernel: the level geometry with rows per thread
+// lowered until the block's LDS stages fit kMaxTileBytes.
+constexpr size_t kMaxTileBytes = 64 * 1024;
+template <typename Op, typename T>
+size_t tile_bytes(int by, int rpt);
+template <typename Op, typename T>
+Geom geom_op(const Grid& g, int nrhs, int cap) {
+    Geom q = geom(g, Op::kHeavy, nrhs, cap);
+    if (tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) {
+        while (q.rpt > 1 && tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) --q.rpt;
+        q.grid = level_grid(g, q.rpt, nrhs, q.by);
+        q.nblk = int(q.grid.x * q.grid.y);
+    }
     return q;
 }
 
@@ -84,6 +89,14 @@ void with_op(const LevelOp<T>& lop, F&& f) {
         f(FineOp<T>{lop.g, lop.k2, T(1.0 / (lop.h * lop.h)), T(2.0 / lop.h)});
         return;
     }
+    if (lop.level == 1 && lop.product) {
+        const FineOp<T> fine{lop.g0, lop.k2, T(1.0 / (lop.h * lop.h)), T(2.0 / lop.h)};
+        const int D = 2 * lop.radius + 1;
+        const cplx<T>* diagc = lop.coef + (long long)(lop.radius * D + lop.radius) * lop.g.plane;
+        if (lop.transfer == 0) f(ProductOp<T, true>{lop.g, fine, T(lop.shift), diagc});
+        else f(ProductOp<T, false>{lop.g, fine, T(lop.shift), diagc});
+        return;
+    }
     switch (lop.radius) {
         case 1: f(StencilOp<T, 1>{lop.g, lop.coef}); break;
         case 2: f(StencilOp<T, 2>{lop.g, lop.coef}); break;
@@ -96,6 +109,95 @@ __device__ __forceinline__ double dnorm2(cplx<T> z) {
     return double(z.re) * double(z.re) + double(z.im) * double(z.im);
 }
 
+// Stages 2-4 of a ProductOp apply, after the coarse tile (halo 3) is in LDS:
+// y = P x and v = C_s y on the block's fine region, then the restriction of v
+// at each coarse node, handed to f(i, j, p, x at p, A_1 x at p).
+template <typename T, bool kBez, typename F>
+__device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, const Tile<3>& tl, cplx<T>* lds,
+                                               F&& f) {
+    using PS = ProductStages<T>;
+    const int rows = tl.rows;
+    cplx<T>* y = lds + Tile<3>::TW * (rows + 6);
+    cplx<T>* v = y + PS::YW * PS::yrows(rows);
+    const int nt = blockDim.x * blockDim.y;
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    const int nf = op.fine.g.n;
+    const int fx0 = 2 * tl.c0 - 3, fy0 = 2 * tl.r0 - 3;  // fine origin of y
+    // y = P x: even fine index 2K takes (1/8, 3/4, 1/8) of K-1, K, K+1 (Bezier)
+    // or x_K (linear); odd 2K+1 takes (x_K + x_{K+1}) / 2. Zero off the fine grid.
+    const int ny = PS::YW * PS::yrows(rows);
+    for (int q = tid; q < ny; q += nt) {
+        const int fi = fx0 + q % PS::YW, fj = fy0 + q / PS::YW;
+        cplx<T> acc{T(0), T(0)};
+        if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
+            T wx[3], wy[3];
+            const bool ox = fi & 1, oy = fj & 1;
+            wx[0] = ox ? T(0) : (kBez ? T(0.125) : T(0));
+            wx[1] = ox ? T(0.5) : (kBez ? T(0.75) : T(1));
+            wx[2] = ox ? T(0.5) : (kBez ? T(0.125) : T(0));
+            wy[0] = oy ? T(0) : (kBez ? T(0.125) : T(0));
+            wy[1] = oy ? T(0.5) : (kBez ? T(0.75) : T(1));
+            wy[2] = oy ? T(0.5) : (kBez ? T(0.125) : T(0));
+            const int base = tl.at((fi >> 1) - 1, (fj >> 1) - 1);
+#pragma unroll
+            for (int ty = 0; ty < 3; ++ty) {
+                cplx<T> row{T(0), T(0)};
+#pragma unroll
+                for (int tx = 0; tx < 3; ++tx) {
+                    const cplx<T> xv = lds[base + ty * Tile<3>::TW + tx];
+                    row.re += wx[tx] * xv.re;
+                    row.im += wx[tx] * xv.im;
+                }
+                acc.re += wy[ty] * row.re;
+                acc.im += wy[ty] * row.im;
+            }
+        }
+        y[q] = acc;
+    }
+    __syncthreads();
+    // v = C_s y = A_s y - i beta2 W k^2 y on fine nodes of the grid, zero elsewhere
+    const int nv = PS::VW * PS::vrows(rows);
+    for (int q = tid; q < nv; q += nt) {
+        const int a = q % PS::VW, bb = q / PS::VW;
+        const int fi = fx0 + 1 + a, fj = fy0 + 1 + bb;
+        cplx<T> r{T(0), T(0)};
+        if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
+            const int yi = (bb + 1) * PS::YW + a + 1;
+            const long long p = op.fine.g.at(fi, fj);
+            const cplx<T> yc = y[yi];
+            r = op.fine.apply5(fi, fj, p, yc, y[yi - 1], y[yi + 1], y[yi - PS::YW], y[yi + PS::YW]);
+            const T sw = op.shift * line_w<T>(fi, nf) * line_w<T>(fj, nf) * op.fine.k2[p];
+            r.re += sw * yc.im;
+            r.im -= sw * yc.re;
+        }
+        v[q] = r;
+    }
+    __syncthreads();
+    // (R v)_I = (1/4) sum of the prolongation weights of I times v
+    const T m5[5] = {T(1), T(4), T(6), T(4), T(1)};
+    const T m3[5] = {T(0), T(1), T(2), T(1), T(0)};
+    const T scale = kBez ? T(1.0 / 256.0) : T(1.0 / 16.0);
+    for_nodes(op.g, (rows + blockDim.y - 1) / blockDim.y, [&](int i, int j, long long p) {
+        const int vc = (2 * (j - tl.r0) + 2) * PS::VW + 2 * (i - tl.c0) + 2;
+        cplx<T> acc{T(0), T(0)};
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            cplx<T> row{T(0), T(0)};
+#pragma unroll
+            for (int dx = -2; dx <= 2; ++dx) {
+                const T w = kBez ? m5[dx + 2] : m3[dx + 2];
+                const cplx<T> vv = v[vc + dy * PS::VW + dx];
+                row.re += w * vv.re;
+                row.im += w * vv.im;
+            }
+            const T w = kBez ? m5[dy + 2] : m3[dy + 2];
+            acc.re += w * row.re;
+            acc.im += w * row.im;
+        }
+        f(i, j, p, lds[tl.at(i, j)], scale * acc);
+    });
+}
+
 // Runs f(i, j, p, x at p, A x at p) over the thread's nodes, where x is given
 // by the element getter xget: x for the block tile plus halo is staged in LDS
 // first (one evaluation of the getter per tile node instead of one per
@@ -106,17 +208,22 @@ __device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& 
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
     const Tile<R> tl = block_tile<R>(rpt);
     fill_tile<T, R>(lds, tl, op.g, xget);
-    for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-        const int li = tl.at(i, j);
-        if constexpr (is_stencil<Op>::value) f(i, j, p, lds[li], apply_tile(op, lds, li, p));
-        else f(i, j, p, lds[li], apply_tile(op, lds, li, i, j, p));
-    });
+    if constexpr (is_product<Op>::value) {
+        product_stages(op, tl, lds, f);
+    } else {
+        for_nodes(op.g, rpt, [&](int i, int j, long long p) {
+            const int li = tl.at(i, j);
+            if constexpr (is_stencil<Op>::value) f(i, j, p, lds[li], apply_tile(op, lds, li, p));
+            else f(i, j, p, lds[li], apply_tile(op, lds, li, i, j, p));
+        });
+    }
 }
 
 // Dynamic LDS bytes of an operator kernel launched with geometry (by, rpt).
 template <typename Op, typename T>
 size_t tile_bytes(int by, int rpt) {
     constexpr int R = op_radius<Op>::value;
+    if constexpr (is_product<Op>::value) return ProductStages<T>::values(by * rpt) * sizeof(cplx<T>);
     return size_t(Tile<R>::TW) * size_t(by * rpt + 2 * R) * sizeof(cplx<T>);
 }
 
@@ -471,14 +578,42 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, c
     const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
     if (k == 0) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    const cplx<T>* z1 = z0 + Z.plane;
+    const cplx<T>* z2 = z1 + Z.plane;
     cplx<T>* ub = u.rhs(b);
-    for_nodes(g, rpt, [&](int, int, long long p) {
-        cplx<T> x = ub[p];
-        x = cfma(x, c[0], z0[p]);
-        if (k > 1) x = cfma(x, c[1], z0[p + Z.plane]);
-        if (k > 2) x = cfma(x, c[2], z0[p + 2 * Z.plane]);
+    // rows software-pipelined: the loads of row rr + 1 are issued before the
+    // store of row rr
+    const int i = blockIdx.x * kBX + threadIdx.x;
+    if (i > g.n) return;
+    const int by = blockDim.y;
+    int j = blockIdx.y * rpt * by + threadIdx.y;
+    const int jend = min(g.n + 1, (blockIdx.y + 1) * rpt * by);
+    if (j >= jend) return;
+    long long p = g.at(i, j);
+    const long long step = (long long)by * g.pitch;
+    cplx<T> xu = ub[p], x0 = z0[p], x1 = z1[p], x2 = z2[p];
+    for (;;) {
+        const int jn = j + by;
+        const bool more = jn < jend;
+        cplx<T> nu{}, n0{}, n1{}, n2{};
+        if (more) {
+            nu = ub[p + step];
+            n0 = z0[p + step];
+            n1 = z1[p + step];
+            n2 = z2[p + step];
+        }
+        cplx<T> x = cfma(xu, c[0], x0);
+        if (k > 1) x = cfma(x, c[1], x1);
+        if (k > 2) x = cfma(x, c[2], x2);
         ub[p] = x;
-    });
+        if (!more) break;
+        j = jn;
+        p += step;
+        xu = nu;
+        x0 = n0;
+        x1 = n1;
+        x2 = n2;
+    }
 }
 
 // Pass 5 fused with the residual that follows the last pre-smoothing step:
@@ -510,6 +645,20 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u
         nb[p] = up;
         rb[p] = fb[p] - au;
     });
+}
+
+// Sums the nblk partial rows of a region into row 0 (same thread count and
+// order as a consumer-side reduction, hence the same totals), so that the
+// consumers of a large producer grid read one row.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_prereduce(double* part, int nblk, const int* active) {
+    const int b = blockIdx.x;
+    if (!rhs_active(active, b)) return;
+    double t[K];
+    reduce_partials<K>(part + b * kPartStride, nblk, t);  // ends with barriers after every read
+    if (thread_linear() == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[b * kPartStride + k] = t[k];
 }
 
 // ---------------------------------------------------------------- norms
@@ -678,7 +827,7 @@ template <typename T>
 void launch_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> y) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
         HM_LAUNCH_OP(q, (k_apply<Op, T, BY>), op, x, y, HM_ACTIVE, q.rpt);
     });
 }
@@ -687,7 +836,7 @@ template <typename T>
 void launch_residual(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> r) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
         HM_LAUNCH_OP(q, (k_residual<Op, T, BY>), op, x, f, r, HM_ACTIVE, q.rpt);
     });
 }
@@ -696,21 +845,21 @@ template <typename T>
 void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
         HM_LAUNCH_OP(q, (k_jacobi<Op, T, BY>), op, x, f, y, T(inv_omega), HM_ACTIVE, q.rpt);
     });
 }
 
 template <typename T>
 void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc) {
-    const Geom q = geom(coarse, false, ctx.nrhs);
+    const Geom q = geom(coarse, false, ctx.nrhs, ctx.block_cap);
     if (transfer == 0) HM_LAUNCH(q, (k_restrict<T, true, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
     else HM_LAUNCH(q, (k_restrict<T, false, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
 }
 
 template <typename T>
 void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u) {
-    const Geom q = geom(fine, false, ctx.nrhs);
+    const Geom q = geom(fine, false, ctx.nrhs, ctx.block_cap);
     if (transfer == 0) HM_LAUNCH(q, (k_prolong_add<T, true, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
     else HM_LAUNCH(q, (k_prolong_add<T, false, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
 }
@@ -723,21 +872,33 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
                        Vec<T> unew, Vec<T> res) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
-    const Geom qv = geom(lop.g, false, ctx.nrhs);  // vector-only passes
+    const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
     int nb_op = 0;
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
         nb_op = q.nblk;
-        const int nb = q.nblk;
+        // consumers read the producer's partials directly, or one pre-reduced row
+        const bool pre = q.nblk > ctx.block_cap;
+        const int nb = pre ? 1 : q.nblk;
+        auto prereduce = [&](double* part, auto kc) {
+            if (pre)
+                hipLaunchKernelGGL((k_prereduce<decltype(kc)::value>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream,
+                                   part, q.nblk, HM_ACTIVE);
+        };
         HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
+        prereduce(A, std::integral_constant<int, 1>{});
         if (between) between(between_arg, 0);
         HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb, B, HM_ACTIVE, q.rpt);
+        prereduce(B, std::integral_constant<int, 2>{});
         if (between) between(between_arg, 1);
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
+        prereduce(A, std::integral_constant<int, 5>{});
         if (between) between(between_arg, 2);
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         if (between) between(between_arg, 3);
+        prereduce(B, std::integral_constant<int, 8>{});
+        nb_op = nb;
         if (res.p)
             HM_LAUNCH_OP(q, (k_gm_u_res<Op, T, BY>), op, Z, u, f, unew, res, st, breakdown, B, nb, HM_ACTIVE,
                          q.rpt);
@@ -756,7 +917,7 @@ void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T
     int nb = 0;
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom(lop.g, Op::kHeavy, ctx.nrhs);
+        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
         nb = q.nblk;
         HM_LAUNCH_OP(q, (k_resnorm<Op, T, BY>), op, x, f, region(ctx, 0), HM_ACTIVE, q.rpt);
     });
@@ -765,7 +926,7 @@ void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T
 
 template <typename T>
 void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
-    const Geom q = geom(g, false, ctx.nrhs);
+    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
     HM_LAUNCH(q, (k_norm<T, BY>), g, f, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 0);
 }
@@ -774,7 +935,7 @@ void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Ve
                             Vec<float> r32, RhsNorms* norms) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx.nrhs);
+    const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 1);
@@ -784,7 +945,7 @@ void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, V
                              Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx.nrhs);
+    const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 1);
@@ -793,7 +954,7 @@ void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, V
 template <typename T>
 void launch_copy_in(const LaunchCtx& ctx, Grid g, const void* src, bool src_is_f32, Vec<T> dst, bool scale_w,
                     bool conj) {
-    const Geom q = geom(g, false, ctx.nrhs);
+    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
     if (src_is_f32)
         HM_LAUNCH(q, (k_copy_in<T, float, BY>), g, static_cast<const cplx<float>*>(src), dst, int(scale_w),
                   int(conj), q.rpt);
@@ -804,7 +965,7 @@ void launch_copy_in(const LaunchCtx& ctx, Grid g, const void* src, bool src_is_f
 
 template <typename T>
 void launch_copy_out(const LaunchCtx& ctx, Grid g, Vec<T> src, void* dst, bool dst_is_f32, bool scale_w, bool conj) {
-    const Geom q = geom(g, false, ctx.nrhs);
+    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
     if (dst_is_f32)
         HM_LAUNCH(q, (k_copy_out<T, float, BY>), g, src, static_cast<cplx<float>*>(dst), int(scale_w), int(conj),
                   q.rpt);
@@ -832,7 +993,7 @@ void launch_fill_words(hipStream_t s, void* p, long long bytes, unsigned value) 
 
 void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Vec<double> u, Vec<double> mu,
                     double* grad_k2_dense) {
-    const int rpt = level_rpt(g, kBY);
+    const int rpt = level_rpt(g, kBY, ctx.block_cap);
     hipLaunchKernelGGL(k_grad_k2, level_grid(g, rpt, 1, kBY), dim3(kBX, kBY), 0, ctx.stream, g, h, k2, u, mu,
                        grad_k2_dense, ctx.nrhs, rpt);
 }

@@ -75,6 +75,23 @@ struct StencilOp {
     }
 };
 
+// Level 1 without its stored stencil: A_1 = R C_s P (§3 Galerkin product, §4
+// transfers) applied in three steps from level-0 data, y = P x on the fine
+// grid, v = C_s y with the shifted Laplacian C_s = A_s - i beta2 W K^2 of
+// level 0, then the restriction R = P^T / 4 of v. Equal to the stored
+// Galerkin stencil up to rounding; reads x and level-0 k^2 instead of
+// (2r+1)^2 complex coefficients per node. The Jacobi diagonal comes from the
+// centre plane of the stored stencil.
+template <typename T, bool kBez>
+struct ProductOp {
+    static constexpr bool kHeavy = true;  // short blocks: three LDS stages
+    Grid g;                 // level 1
+    FineOp<T> fine;         // level-0 operator A_s (grid, k^2, 1/h^2, 2/h)
+    T shift;                // beta2
+    const cplx<T>* diagc;   // centre plane of the stored level-1 stencil
+    __device__ __forceinline__ cplx<T> diag(int, int, long long p) const { return diagc[p]; }
+};
+
 // Calls f(i, j, p) for the nodes of this thread: column blockIdx.x * 64 + lane,
 // rows interleaved by 4 over rows_per_thread consecutive row groups.
 template <typename F>
@@ -177,6 +194,32 @@ template <typename T, int R>
 struct op_radius<StencilOp<T, R>> {
     static constexpr int value = R;
 };
+template <typename T, bool B>
+struct op_radius<ProductOp<T, B>> {
+    static constexpr int value = 3;  // coarse halo that the fine stages need
+};
+template <typename Op>
+struct is_product {
+    static constexpr bool value = false;
+};
+template <typename T, bool B>
+struct is_product<ProductOp<T, B>> {
+    static constexpr bool value = true;
+};
+
+// Fine-grid stages of a ProductOp block. The block's coarse tile covers
+// columns [c0, c0 + 64) and rows [r0, r0 + rows); the restriction reads fine
+// nodes 2I - 2 .. 2I + 2, C_s one more on each side.
+template <typename T>
+struct ProductStages {
+    static constexpr int YW = 2 * kBX + 5;  // fine columns 2 c0 - 3 .. 2 c0 + 129 (y = P x)
+    static constexpr int VW = 2 * kBX + 3;  // fine columns 2 c0 - 2 .. 2 c0 + 128 (v = C_s y)
+    __host__ __device__ static int yrows(int rows) { return 2 * rows + 5; }
+    __host__ __device__ static int vrows(int rows) { return 2 * rows + 3; }
+    __host__ __device__ static size_t values(int rows) {
+        return size_t(Tile<3>::TW) * (rows + 6) + size_t(YW) * yrows(rows) + size_t(VW) * vrows(rows);
+    }
+};
 
 __device__ __forceinline__ bool rhs_active(const int* active, int b) { return active == nullptr || active[b] != 0; }
 
@@ -230,15 +273,27 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* out) {
 }
 
 // Sums the K partials of nblk producer blocks; every thread gets the totals.
+// Each thread sums partials q = tid, tid + nt, ... in that order; loads are
+// gathered kReduceBatch strides at a time so that they are in flight together.
+constexpr int kReduceBatch = 4;
 template <int K>
 __device__ __forceinline__ void reduce_partials(const double* in, int nblk, double (&tot)[K]) {
     double acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     const int nt = blockDim.x * blockDim.y;
-    for (int q = thread_linear(); q < nblk; q += nt) {
+    for (int q0 = thread_linear(); q0 < nblk; q0 += kReduceBatch * nt) {
+        double v[kReduceBatch][K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += in[q * K + k];
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int q = q0 + u * nt;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = (q < nblk) ? in[q * K + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += v[u][k];
     }
     block_sum<K>(acc, tot);
 }

@@ -23,6 +23,7 @@ thread_local std::string g_setup_error;
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxCoarseNodes = 1089;
+constexpr int kMaxN = 4096;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -36,15 +37,6 @@ Grid make_grid(int n) {
 }
 
 int next_radius(int r, int transfer) { return transfer == MG_TRANSFER_BEZIER ? (r + 4) / 2 : (r + 2) / 2; }
-
-int default_rpt(int n) {
-    if (const char* e = std::getenv("HELMG_RPT")) {
-        const int v = std::atoi(e);
-        if (v >= 1 && v <= 64) return v;
-    }
-    return n >= 2048 ? 4 : n >= 512 ? 2 : 1;
-}
-
 
 struct LevelBuf {
     Grid g;
@@ -74,7 +66,7 @@ struct Carver {
 }  // namespace
 
 struct mg_ctx {
-    int n = 0, L = 0, transfer = 0, max_batch = 1, has32 = 0, coarsest_n = 4, rpt = 1;
+    int n = 0, L = 0, transfer = 0, max_batch = 1, has32 = 0, coarsest_n = 4;
     double h = 0.0, shift = 0.0;
     std::vector<LevelBuf> lv;
     double* k2_64 = nullptr;
@@ -113,6 +105,12 @@ struct mg_ctx {
     // first level run by the single-workgroup coarse tail (-1: none), per
     // precision (index 0: FP64 cycles, 1: FP32 cycles)
     int tail_level[2] = {-1, -1};
+    // level 1 applied as R C_s P from level-0 data instead of its stored
+    // stencil (HELMG_L1_PRODUCT=0 selects the stored stencil)
+    int product_l1 = 1;
+    // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
+    // beyond it reductions are pre-reduced in a one-block pass
+    int block_cap = 640;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -123,6 +121,8 @@ namespace {
 // ---------------------------------------------------------------- layout plan
 bool levels_for(int n, int levels, int coarsest_n, int* L_out, std::string* why) {
     if (n < 2) { *why = "n must be >= 2"; return false; }
+    // level kernels launch at most kMaxPartialBlocks blocks per right-hand side
+    if (n > kMaxN) { *why = "n must be <= 4096"; return false; }
     int L = levels;
     if (L <= 0) {
         if (coarsest_n < 1) { *why = "coarsest_n must be >= 1"; return false; }
@@ -147,7 +147,6 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     Carver cv{base};
     if (c) c->lv.assign(L, LevelBuf());
     int r = 1;
-    const int rpt = default_rpt(n);
     const size_t B = size_t(max_batch);
     for (int l = 0; l < L; ++l) {
         const Grid g = make_grid(n >> l);
@@ -197,7 +196,6 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
         c->norms = norms;
         c->active = active;
         c->partials = partials;
-        c->rpt = rpt;
     }
     return align_up(cv.off, kAlign);
 }
@@ -248,14 +246,15 @@ template <> struct Prec<float> {
 template <typename T>
 LevelOp<T> level_op(const mg_ctx* c, int l) {
     const LevelBuf& lb = c->lv[l];
-    return LevelOp<T>{l, lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::k2(c), c->h};
+    return LevelOp<T>{l, lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::k2(c), c->h,
+                      c->product_l1, c->lv[0].g, c->shift, c->transfer};
 }
 
 template <typename T>
 Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
-    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->rpt};
+    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap};
 }
 
 // Timing hook: events around the launches of one kernel class.
@@ -783,6 +782,11 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
+        const int v = std::atoi(e);
+        c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
+    }
     pick_tail_levels(c);
     tail_init();
     carve(c, c->ws, n, L, transfer, max_batch, has32);

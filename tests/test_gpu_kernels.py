@@ -199,3 +199,34 @@ def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
                           smoother=smoother, nu_pre=2, nu_post=1, precision="fp32_refined"))
     ref = O.cycle(H, 0, u[0].ravel(), f[0].ravel(), opts)
     assert rel(got32[0], ref) <= 1e-4, rel(got32[0], ref)
+
+
+@pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"}],
+                         ids=["block_cap_64", "stored_level1"])
+def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
+    """With a block cap of 64 every GMRES reduction goes through the one-block
+    pre-reduction pass; with HELMG_L1_PRODUCT=0 level 1 applies its stored
+    Galerkin stencil instead of R C_s P. Both give the oracle's level-1 apply
+    and cycle (FP64) and stay close to it in FP32."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
+    n = 128
+    k2 = W.random_k2(n, 11, 10.0, 30.0)
+    H = O.build_hierarchy(k2, 1.0 / n, 0.2)
+    S = Solver(to_gpu(k2), 1.0 / n, 0.2, max_batch=2, precision="fp32_refined")
+    x = _rand(n // 2, 2, 130)
+    y = to_np(S.apply(1, to_gpu(x)))
+    for b in range(2):
+        assert rel(y[b], H.A[1] @ x[b].ravel()) <= 1e-13
+    u = _rand(n, 2, 131)
+    f = _rand(n, 2, 132)
+    opts = O.CycleOptions(gamma=1, smoother="gmres")
+    got = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle="V", smoother="gmres"))
+    got32 = to_np(S.cycle(to_gpu(u.astype(np.complex64)), to_gpu(f.astype(np.complex64)), cycle="V",
+                          smoother="gmres", precision="fp32_refined"))
+    for b in range(2):
+        ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
+        assert rel(got[b], ref) <= 1e-10, (b, rel(got[b], ref))
+        assert rel(got32[b], ref) <= 1e-4, (b, rel(got32[b], ref))
