@@ -120,6 +120,25 @@ mg_status mg_update_k2(mg_handle h, const double* k2, void* stream);
 mg_status mg_solve(mg_handle h, const void* rhs, void* x, int nrhs, double tol, int cycle, int smoother,
                    const mg_solve_opts* opts, mg_solve_stats* stats, void* stream);
 
+/* Mixed-size batch: several independent problems, each with its own handle
+ * (any n, k^2 field, shift, levels; set up separately with mg_setup), solved
+ * together. Every cycle of the problems still running is launched as one
+ * HIP graph with one branch per problem, so the level kernels of different
+ * problems run concurrently and one stream synchronisation per cycle serves
+ * all of them (batching of the cycle in §5 across problems; not in the paper).
+ *  handles[p]  distinct handles, p < nprob.
+ *  rhs[p], x[p], nrhs[p]  as rhs, x, nrhs of mg_solve for problem p.
+ *  stats       NULL or an array of nprob mg_solve_stats, each as in mg_solve.
+ *  tol, cycle, smoother, opts as in mg_solve, shared by all problems.
+ * Each problem stops like mg_solve; the result is that of mg_solve for each
+ * problem alone, bit for bit. Returns the worst status over the problems
+ * (an error, else MG_E_DIVERGED, else MG_NOT_CONVERGED, else MG_OK); the
+ * detail is in mg_last_error of the first failing handle, or of NULL for an
+ * argument error that names no handle. */
+mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, void* const* x, const int* nrhs,
+                         double tol, int cycle, int smoother, const mg_solve_opts* opts, mg_solve_stats* stats,
+                         void* stream);
+
 /* Adjoint-state gradient for a real loss L(u) of solutions u = A_s^{-1} W f.
  *  u       [dev] complex128 [nsrc][n+1][n+1], forward solutions.
  *  grad_u  [dev] complex128 [nsrc][n+1][n+1], dL/du in PyTorch's convention

@@ -106,7 +106,9 @@ struct mg_ctx {
     // precision (index 0: FP64 cycles, 1: FP32 cycles)
     int tail_level[2] = {-1, -1};
     // level 1 applied as R C_s P from level-0 data instead of its stored
-    // stencil (HELMG_L1_PRODUCT=0 selects the stored stencil)
+    // stencil: 1 in FP32 cycles (default; measured faster there, while FP64
+    // cycles are faster with the stored stencil), 2 in both, 0 never
+    // (HELMG_L1_PRODUCT)
     int product_l1 = 1;
     // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
     // beyond it reductions are pre-reduced in a one-block pass
@@ -246,8 +248,9 @@ template <> struct Prec<float> {
 template <typename T>
 LevelOp<T> level_op(const mg_ctx* c, int l) {
     const LevelBuf& lb = c->lv[l];
+    const int product = c->product_l1 == 2 || (c->product_l1 == 1 && sizeof(T) == 4);
     return LevelOp<T>{l, lb.g, lb.radius, Prec<T>::coef(lb), Prec<T>::k2(c), c->h,
-                      c->product_l1, c->lv[0].g, c->shift, c->transfer};
+                      product, c->lv[0].g, c->shift, c->transfer};
 }
 
 template <typename T>
@@ -586,59 +589,88 @@ mg_status check_solve_args(mg_ctx* c, int nrhs, double tol, int cyc, int smoothe
 
 // Core solve of A_s x = f_s on level-0 buffers: f_s already in lv[0].f64, the
 // initial guess in lv[0].u64. Leaves every solution in lv[0].u64.
-mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, int smoother, const mg_solve_opts& o,
-                     mg_solve_stats* stats) {
-    const auto t0 = std::chrono::steady_clock::now();
-    LevelBuf& l0 = c->lv[0];
-    const CycleParams cp{cyc, smoother, o.nu_pre, o.nu_post, o.omega};
-    const bool fp32 = (o.precision == MG_FP32_REFINED);
-    const LevelOp<double> op0 = level_op<double>(c, 0);
-    c->cur_buf = 0;
-    c->final_buf.assign(nrhs, -1);
-    for (int b = 0; b < nrhs; ++b) c->h_active[b] = 1;
-    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    LaunchCtx lc = launch_ctx(c, s, nrhs);
-    launch_norm<double>(lc, l0.g, vec<double>(l0.f64, l0), c->norms);
-    if (fp32)
-        launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), vec<float>(l0.f32, l0),
-                               c->norms);
-    else
-        launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
-    if (mg_status st = check_launch(c)) return st;
-    HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
-    HM_HIP(hipStreamSynchronize(s));
-    std::vector<double> rel0(nrhs), rel(nrhs);
-    std::vector<int> cycles(nrhs, 0), state(nrhs, 0);  // state: 0 running, 1 converged, 2 diverged
+// One solve on one handle, driven cycle by cycle (a9 stop test): start()
+// enqueues the initial norms; after the stream has synchronised, begin()
+// reads them. enqueue_cycle() enqueues one cycle plus the residual norms on a
+// stream (captured or eager), and after_cycle() reads the norms after the
+// next synchronisation. finish() gathers every right-hand side's last iterate.
+struct SolveRun {
+    mg_ctx* c = nullptr;
+    int nrhs = 0;
+    double tol = 0.0;
+    CycleParams cp{};
+    mg_solve_opts o{};
+    bool fp32 = false;
+    std::vector<double> rel0, rel;
+    std::vector<int> cycles, state;  // state: 0 running, 1 converged, 2 diverged
     int running = 0;
-    for (int b = 0; b < nrhs; ++b) {
-        const double f2 = c->h_norms[b].f2;
-        if (f2 == 0.0) {
-            // zero right-hand side: the solution is zero
-            launch_zero<double>(s, l0.u64 + (long long)b * l0.g.plane, l0.g.plane);
-            rel0[b] = rel[b] = 0.0;
-            state[b] = 1;
-        } else {
-            rel0[b] = rel[b] = std::sqrt(c->h_norms[b].r2 / f2);
-            if (!std::isfinite(rel0[b])) state[b] = 2;
-            else if (rel0[b] <= tol) state[b] = 1;
-        }
-        if (state[b] != 0) {
-            c->h_active[b] = 0;
-            c->final_buf[b] = 0;
-        } else {
-            ++running;
-        }
+    std::vector<uintptr_t> key;
+    std::chrono::steady_clock::time_point t0;
+
+    SolveRun(mg_ctx* ctx, int nr, double tl, int cyc, int smoother, const mg_solve_opts& opts)
+        : c(ctx), nrhs(nr), tol(tl), cp{cyc, smoother, opts.nu_pre, opts.nu_post, opts.omega}, o(opts),
+          fp32(opts.precision == MG_FP32_REFINED) {
+        uint64_t omega_bits;
+        std::memcpy(&omega_bits, &o.omega, sizeof(omega_bits));
+        key = {uintptr_t(fp32), uintptr_t(cyc), uintptr_t(smoother), uintptr_t(o.nu_pre), uintptr_t(o.nu_post),
+               uintptr_t(omega_bits), uintptr_t(nrhs), uintptr_t(c->timing_class)};
     }
-    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
-    int it = 0;
-    uint64_t omega_bits;
-    std::memcpy(&omega_bits, &o.omega, sizeof(omega_bits));
-    const std::vector<uintptr_t> key{uintptr_t(fp32), uintptr_t(cyc), uintptr_t(smoother), uintptr_t(o.nu_pre),
-                                     uintptr_t(o.nu_post), uintptr_t(omega_bits), uintptr_t(nrhs),
-                                     uintptr_t(c->timing_class)};
-    auto body = [&](hipStream_t st) {
-        LaunchCtx l2 = lc;
-        l2.stream = st;
+    LaunchCtx ctx(hipStream_t s) const { return launch_ctx(c, s, nrhs); }
+
+    mg_status start(hipStream_t s) {
+        t0 = std::chrono::steady_clock::now();
+        LevelBuf& l0 = c->lv[0];
+        const LevelOp<double> op0 = level_op<double>(c, 0);
+        c->cur_buf = 0;
+        c->final_buf.assign(nrhs, -1);
+        for (int b = 0; b < nrhs; ++b) c->h_active[b] = 1;
+        HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        LaunchCtx lc = ctx(s);
+        launch_norm<double>(lc, l0.g, vec<double>(l0.f64, l0), c->norms);
+        if (fp32)
+            launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0),
+                                   vec<float>(l0.f32, l0), c->norms);
+        else
+            launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
+        if (mg_status st = check_launch(c)) return st;
+        HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+        return MG_OK;
+    }
+
+    mg_status begin(hipStream_t s) {
+        LevelBuf& l0 = c->lv[0];
+        rel0.assign(nrhs, 0.0);
+        rel.assign(nrhs, 0.0);
+        cycles.assign(nrhs, 0);
+        state.assign(nrhs, 0);
+        running = 0;
+        for (int b = 0; b < nrhs; ++b) {
+            const double f2 = c->h_norms[b].f2;
+            if (f2 == 0.0) {
+                // zero right-hand side: the solution is zero
+                launch_zero<double>(s, l0.u64 + (long long)b * l0.g.plane, l0.g.plane);
+                rel0[b] = rel[b] = 0.0;
+                state[b] = 1;
+            } else {
+                rel0[b] = rel[b] = std::sqrt(c->h_norms[b].r2 / f2);
+                if (!std::isfinite(rel0[b])) state[b] = 2;
+                else if (rel0[b] <= tol) state[b] = 1;
+            }
+            if (state[b] != 0) {
+                c->h_active[b] = 0;
+                c->final_buf[b] = 0;
+            } else {
+                ++running;
+            }
+        }
+        HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        return MG_OK;
+    }
+
+    void enqueue_cycle(hipStream_t st) {
+        LevelBuf& l0 = c->lv[0];
+        const LevelOp<double> op0 = level_op<double>(c, 0);
+        LaunchCtx l2 = ctx(st);
         if (fp32) {
             launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
             cycle<float>(c, l2, 0, cp);
@@ -651,13 +683,15 @@ mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, in
             cycle<double>(c, l2, 0, cp);
             launch_resnorm<double>(l2, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
         }
-    };
-    while (running > 0 && it < o.max_cycles) {
-        ++it;
-        if (mg_status st = run_cycle_graph(c, s, key, body)) return st;
-        if (mg_status st = check_launch(c)) return st;
+    }
+
+    mg_status read_norms(hipStream_t s) {
         HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
-        HM_HIP(hipStreamSynchronize(s));
+        return MG_OK;
+    }
+
+    // after cycle `it` (1-based) and a synchronisation of the stream
+    mg_status after_cycle(int it, hipStream_t s, mg_solve_stats* stats) {
         harvest_timing(c);
         bool changed = false;
         for (int b = 0; b < nrhs; ++b) {
@@ -682,39 +716,70 @@ mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, in
         }
         if (changed && running > 0)
             HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        return MG_OK;
     }
-    for (int b = 0; b < nrhs; ++b)
-        if (c->final_buf[b] < 0) c->final_buf[b] = c->cur_buf;
-    if (fp32) {
-        // buffer 0 = u64, buffer 1 = t64 (pointers never swapped in this path)
+
+    // enqueues the gather of the final iterates (no synchronisation)
+    mg_status gather(hipStream_t s) {
+        LevelBuf& l0 = c->lv[0];
         for (int b = 0; b < nrhs; ++b)
-            if (c->final_buf[b] == 1)
-                HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
-                                      size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
-    } else {
-        // Jacobi on level 0 swaps the u64 / t64 pointers (cur_buf counts the
-        // parity); a right-hand side that stopped at another parity than the
-        // current one has its iterate in t64 now.
-        for (int b = 0; b < nrhs; ++b)
-            if (c->final_buf[b] != c->cur_buf)
-                HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
-                                      size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
-    }
-    HM_HIP(hipStreamSynchronize(s));
-    mg_status result = MG_OK;
-    for (int b = 0; b < nrhs; ++b) {
-        if (state[b] == 2) result = MG_E_DIVERGED;
-        else if (state[b] == 0 && result == MG_OK) result = MG_NOT_CONVERGED;
-    }
-    if (stats) {
-        for (int b = 0; b < nrhs; ++b) {
-            if (stats->cycles) stats->cycles[b] = cycles[b];
-            if (stats->relres) stats->relres[b] = rel[b];
+            if (c->final_buf[b] < 0) c->final_buf[b] = c->cur_buf;
+        if (fp32) {
+            // buffer 0 = u64, buffer 1 = t64 (pointers never swapped in this path)
+            for (int b = 0; b < nrhs; ++b)
+                if (c->final_buf[b] == 1)
+                    HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
+                                          size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
+        } else {
+            // Jacobi on level 0 swaps the u64 / t64 pointers (cur_buf counts the
+            // parity); a right-hand side that stopped at another parity than the
+            // current one has its iterate in t64 now.
+            for (int b = 0; b < nrhs; ++b)
+                if (c->final_buf[b] != c->cur_buf)
+                    HM_HIP(hipMemcpyAsync(l0.u64 + (long long)b * l0.g.plane, l0.t64 + (long long)b * l0.g.plane,
+                                          size_t(l0.g.plane) * 16, hipMemcpyDeviceToDevice, s));
         }
-        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return MG_OK;
     }
-    if (result == MG_E_DIVERGED) c->err = "residual diverged";
-    return result;
+
+    // after gather() and a synchronisation
+    mg_status result(mg_solve_stats* stats) {
+        mg_status res = MG_OK;
+        for (int b = 0; b < nrhs; ++b) {
+            if (state[b] == 2) res = MG_E_DIVERGED;
+            else if (state[b] == 0 && res == MG_OK) res = MG_NOT_CONVERGED;
+        }
+        if (stats) {
+            for (int b = 0; b < nrhs; ++b) {
+                if (stats->cycles) stats->cycles[b] = cycles[b];
+                if (stats->relres) stats->relres[b] = rel[b];
+            }
+            stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (res == MG_E_DIVERGED) c->err = "residual diverged";
+        return res;
+    }
+};
+
+mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, int smoother, const mg_solve_opts& o,
+                     mg_solve_stats* stats) {
+    SolveRun run(c, nrhs, tol, cyc, smoother, o);
+    if (mg_status st = run.start(s)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    if (mg_status st = run.begin(s)) return st;
+    auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
+    int it = 0;
+    while (run.running > 0 && it < o.max_cycles) {
+        ++it;
+        if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
+        if (mg_status st = check_launch(c)) return st;
+        if (mg_status st = run.read_norms(s)) return st;
+        HM_HIP(hipStreamSynchronize(s));
+        if (mg_status st = run.after_cycle(it, s, stats)) return st;
+    }
+    if (mg_status st = run.gather(s)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    return run.result(stats);
 }
 
 mg_status check_level(mg_ctx* c, int level, int precision, bool allow_last) {
@@ -782,7 +847,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
-    if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
         const int v = std::atoi(e);
         c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
@@ -842,6 +907,186 @@ mg_status mg_solve(mg_handle c, const void* rhs, void* x, int nrhs, double tol, 
     if (mg_status st = check_launch(c)) return st;
     HM_HIP(hipStreamSynchronize(s));
     return res;
+}
+
+namespace {
+
+// Graphs of mg_solve_multi: one per set of running problems and their buffer
+// assignment, alive for one call.
+struct MultiGraphs {
+    struct Entry {
+        std::vector<uintptr_t> key;
+        hipGraphExec_t exec = nullptr;
+        std::vector<std::vector<void*>> after_ptrs;
+        std::vector<int> after_cur;
+    };
+    std::vector<Entry> entries;
+    std::vector<hipStream_t> branch;
+    std::vector<hipEvent_t> join;
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
+    ~MultiGraphs() {
+        for (Entry& e : entries)
+            if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        for (hipStream_t b : branch) (void)hipStreamDestroy(b);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (fork) (void)hipEventDestroy(fork);
+    }
+    bool ready(size_t nbranch) {
+        if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return false;
+        if (!fork && hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return false;
+        while (branch.size() < nbranch) {
+            hipStream_t b;
+            hipEvent_t e;
+            if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess) return false;
+            branch.push_back(b);
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+            join.push_back(e);
+        }
+        return true;
+    }
+};
+
+}  // namespace
+
+mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, void* const* x, const int* nrhs,
+                         double tol, int cyc, int smoother, const mg_solve_opts* opts, mg_solve_stats* stats,
+                         void* stream) {
+    if (!handles || nprob < 1 || !rhs || !x || !nrhs) {
+        g_setup_error = "handles, rhs, x and nrhs must be non-NULL and nprob >= 1";
+        return MG_E_ARG;
+    }
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    for (int p = 0; p < nprob; ++p) {
+        mg_ctx* c = handles[p];
+        if (!c) { g_setup_error = "NULL handle"; return MG_E_ARG; }
+        for (int q = 0; q < p; ++q)
+            if (handles[q] == c) { g_setup_error = "handles must be distinct"; return MG_E_ARG; }
+        if (mg_status st = check_solve_args(c, nrhs[p], tol, cyc, smoother, o)) return st;
+        if (!is_dev_ptr_ok(rhs[p]) || !is_dev_ptr_ok(x[p])) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mg_ctx* c = handles[0];  // carries the message of a stream-level HIP error
+    std::vector<SolveRun> runs;
+    runs.reserve(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        mg_ctx* cp = handles[p];
+        LevelBuf& l0 = cp->lv[0];
+        LaunchCtx lc = launch_ctx(cp, s, nrhs[p]);
+        lc.active = nullptr;
+        launch_copy_in<double>(lc, l0.g, rhs[p], false, vec<double>(l0.f64, l0), true, false);
+        launch_copy_in<double>(lc, l0.g, x[p], false, vec<double>(l0.u64, l0), false, false);
+        if (mg_status st = check_launch(cp)) return st;
+        runs.emplace_back(cp, nrhs[p], tol, cyc, smoother, o);
+        if (mg_status st = runs.back().start(s)) return st;
+    }
+    HM_HIP(hipStreamSynchronize(s));
+    for (SolveRun& r : runs)
+        if (mg_status st = r.begin(s)) return st;
+    bool use_graph = true;
+    for (SolveRun& r : runs) use_graph = use_graph && r.c->use_graph && r.c->timing_class == 0;
+    MultiGraphs mg;
+    int it = 0;
+    for (;;) {
+        std::vector<int> R;
+        for (int p = 0; p < nprob; ++p)
+            if (runs[p].running > 0) R.push_back(p);
+        if (R.empty() || it >= o.max_cycles) break;
+        ++it;
+        bool launched = false;
+        if (use_graph) {
+            std::vector<uintptr_t> key;
+            for (int p : R) {
+                mg_ctx* cp = runs[p].c;
+                key.push_back(uintptr_t(p));
+                key.insert(key.end(), runs[p].key.begin(), runs[p].key.end());
+                for (void* q : pointer_state(cp)) key.push_back(reinterpret_cast<uintptr_t>(q));
+                key.push_back(uintptr_t(cp->cur_buf));
+            }
+            for (MultiGraphs::Entry& e : mg.entries) {
+                if (e.key != key) continue;
+                for (size_t k = 0; k < R.size(); ++k) {
+                    restore_pointer_state(runs[R[k]].c, e.after_ptrs[k]);
+                    runs[R[k]].c->cur_buf = e.after_cur[k];
+                }
+                HM_HIP(hipGraphLaunch(e.exec, s));
+                launched = true;
+                break;
+            }
+            if (!launched) {
+                std::vector<std::vector<void*>> before;
+                std::vector<int> cur_before;
+                for (int p : R) {
+                    before.push_back(pointer_state(runs[p].c));
+                    cur_before.push_back(runs[p].c->cur_buf);
+                }
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                bool ok = mg.ready(R.size()) &&
+                          hipStreamBeginCapture(mg.cap, hipStreamCaptureModeRelaxed) == hipSuccess;
+                if (ok) {
+                    ok = hipEventRecord(mg.fork, mg.cap) == hipSuccess;
+                    for (size_t k = 0; ok && k < R.size(); ++k) {
+                        ok = hipStreamWaitEvent(mg.branch[k], mg.fork, 0) == hipSuccess;
+                        if (ok) runs[R[k]].enqueue_cycle(mg.branch[k]);
+                        ok = ok && hipEventRecord(mg.join[k], mg.branch[k]) == hipSuccess &&
+                             hipStreamWaitEvent(mg.cap, mg.join[k], 0) == hipSuccess;
+                    }
+                    const bool ended = hipStreamEndCapture(mg.cap, &graph) == hipSuccess && graph != nullptr;
+                    ok = ok && ended;
+                }
+                if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                if (ok) {
+                    MultiGraphs::Entry e;
+                    e.key = std::move(key);
+                    e.exec = exec;
+                    for (int p : R) {
+                        e.after_ptrs.push_back(pointer_state(runs[p].c));
+                        e.after_cur.push_back(runs[p].c->cur_buf);
+                    }
+                    mg.entries.push_back(std::move(e));
+                    HM_HIP(hipGraphLaunch(mg.entries.back().exec, s));
+                    launched = true;
+                } else {
+                    // capture failed: eager launches from here on
+                    use_graph = false;
+                    for (size_t k = 0; k < R.size(); ++k) {
+                        restore_pointer_state(runs[R[k]].c, before[k]);
+                        runs[R[k]].c->cur_buf = cur_before[k];
+                    }
+                }
+            }
+        }
+        if (!launched)
+            for (int p : R) runs[p].enqueue_cycle(s);
+        for (int p : R) {
+            if (mg_status st = check_launch(runs[p].c)) return st;
+            if (mg_status st = runs[p].read_norms(s)) return st;
+        }
+        HM_HIP(hipStreamSynchronize(s));
+        for (int p : R)
+            if (mg_status st = runs[p].after_cycle(it, s, stats ? stats + p : nullptr)) return st;
+    }
+    for (SolveRun& r : runs)
+        if (mg_status st = r.gather(s)) return st;
+    HM_HIP(hipStreamSynchronize(s));
+    mg_status worst = MG_OK;
+    auto rank = [](mg_status st) { return st == MG_OK ? 0 : st == MG_NOT_CONVERGED ? 1 : st == MG_E_DIVERGED ? 2 : 3; };
+    for (int p = 0; p < nprob; ++p) {
+        const mg_status st = runs[p].result(stats ? stats + p : nullptr);
+        if (rank(st) > rank(worst)) worst = st;
+        mg_ctx* cp = handles[p];
+        LevelBuf& l0 = cp->lv[0];
+        LaunchCtx lc = launch_ctx(cp, s, nrhs[p]);
+        lc.active = nullptr;
+        launch_copy_out<double>(lc, l0.g, vec<double>(l0.u64, l0), x[p], false, false, false);
+        if (mg_status st2 = check_launch(cp)) return st2;
+    }
+    HM_HIP(hipStreamSynchronize(s));
+    return worst;
 }
 
 mg_status mg_grad(mg_handle c, const void* u, const void* grad_u, int nsrc, double tol, int cyc, int smoother,

@@ -129,6 +129,42 @@ class Solver:
             raise B.MGError(st, B.last_error(self.handle))
         return x, info
 
+    @staticmethod
+    def solve_multi(solvers, rhs_list, x0_list=None, tol: float = 1e-6, cycle="V", smoother="gmres", nu_pre=1,
+                    nu_post=1, omega=4.5, max_cycles=500, precision="fp64", divergence=1e8, raise_on_error=True):
+        """mg_solve_multi: independent problems (one Solver each, any sizes) solved
+        together. Returns a list of (x, info) in the order of `solvers`."""
+        npb = len(solvers)
+        if npb == 0 or len(rhs_list) != npb:
+            raise ValueError("need one right-hand side tensor per solver")
+        fs = [_batched(r, S.n, torch.complex128) for S, r in zip(solvers, rhs_list)]
+        if x0_list is None:
+            xs = [torch.zeros_like(f) for f in fs]
+        else:
+            xs = [_batched(x0, S.n, torch.complex128).clone() for S, x0 in zip(solvers, x0_list)]
+        nbs = [f.shape[0] for f in fs]
+        opts = Solver.solve_options(nu_pre, nu_post, omega, max_cycles, precision, divergence)
+        cyc = [(ctypes.c_int * nb)() for nb in nbs]
+        rel = [(ctypes.c_double * nb)() for nb in nbs]
+        stats = (B.SolveStats * npb)(*[B.SolveStats(ctypes.cast(c, ctypes.POINTER(ctypes.c_int)),
+                                                    ctypes.cast(r, ctypes.POINTER(ctypes.c_double)), None, 0.0)
+                                       for c, r in zip(cyc, rel)])
+        handles = (ctypes.c_void_p * npb)(*[S.handle for S in solvers])
+        rp = (ctypes.c_void_p * npb)(*[_ptr(f) for f in fs])
+        xp = (ctypes.c_void_p * npb)(*[_ptr(x) for x in xs])
+        nr = (ctypes.c_int * npb)(*nbs)
+        st = B.lib().mg_solve_multi(handles, npb, rp, xp, nr, float(tol), _CYCLE[cycle], _SMOOTHER[smoother],
+                                    ctypes.byref(opts), stats, _stream())
+        if raise_on_error and st < 0:
+            failing = next((S.handle for S in solvers if B.last_error(S.handle)), None)
+            raise B.MGError(st, B.last_error(failing))
+        out = []
+        for p in range(npb):
+            info = {"status": st, "status_name": B.status_string(st), "cycles": list(cyc[p]),
+                    "relres": list(rel[p]), "seconds": stats[p].seconds}
+            out.append((xs[p], info))
+        return out
+
     def grad(self, u: torch.Tensor, grad_u: torch.Tensor, tol: float = 1e-10, cycle="V", smoother="gmres",
              nu_pre=1, nu_post=1, omega=4.5, max_cycles=500, precision="fp64", want_rhs=True):
         """mg_grad: returns (grad_k2 float64 (n+1, n+1), grad_rhs complex128 or None, info)."""

@@ -1,0 +1,59 @@
+"""Writes tests/golden/oracle_config3.json from the CPU oracle only.
+
+Heterogeneous MP 2-B-type media at n = 2048 intervals (4,198,401 unknowns):
+a three-layer wedge and a smooth Gaussian random velocity (generators in
+paper_2308_13476_amd/workloads.py, seed 3), k = 2 pi f / c with the
+frequency chosen so that max(k) h = 0.3, point source 1/h^2 at
+(n/2, round(0.9 n)), shift beta2 = 1 / max(k) (§5.3.1), GMRES(3) V(1,1)
+cycles (§5.3), Bézier transfers (§4), coarsening to 4 x 4 intervals.
+Stores the FP64 cycle count to relative residual 1e-6 and the residual
+history of every cycle.
+
+Run: python tests/golden/make_config3_golden.py   (tens of minutes, one core)
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle as O  # noqa: E402
+from paper_2308_13476_amd import workloads as W  # noqa: E402
+
+N = 2048
+SEED = 3
+KH_MAX = 0.3
+TOL = 1e-6
+
+
+def medium(name):
+    c = W.wedge_velocity(N, SEED) if name == "wedge" else W.grf_velocity(N, SEED)
+    return W.k2_from_velocity(c, KH_MAX)
+
+
+def main():
+    out = {"workload": f"n={N}, seed {SEED}, max kh {KH_MAX}, source (n/2, round(0.9 n)), shift 1/k_max, "
+                       "GMRES(3) V(1,1), Bezier, coarsest 4x4 intervals, FP64", "tol": TOL, "runs": {}}
+    src = (N // 2, int(round(0.9 * N)))
+    fs = O.scaled_rhs(W.point_source_rhs(N, [src])[0]).ravel()
+    for name in ["wedge", "grf"]:
+        k2 = medium(name)
+        kmax = float(np.sqrt(k2.max()))
+        t = time.time()
+        H = O.build_hierarchy(k2, 1.0 / N, 1.0 / kmax)
+        setup = time.time() - t
+        t = time.time()
+        res = O.solve(H, fs, O.CycleOptions(gamma=1, smoother="gmres"), tol=TOL, max_cycles=600)
+        out["runs"][name] = {"cycles": res.cycles, "status": res.status, "history": res.history,
+                             "k_max": kmax, "setup_seconds": setup, "seconds": time.time() - t}
+        print(name, res.cycles, res.status, round(setup, 1), round(time.time() - t, 1), flush=True)
+        with open(os.path.join(HERE, "oracle_config3.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,97 @@
+"""Batching on the GPU: many right-hand sides on one hierarchy (config 4 (i))
+and independent problems of mixed sizes solved together (config 4 (ii),
+mg_solve_multi). Members of a batch are compared with the same problems
+solved alone (bit for bit: every right-hand side and every problem runs the
+same arithmetic in the same order) and with the oracle's operator."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_13476_amd import workloads as W
+from tests.gpu_common import require_gpu, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _relres(k2, f, x):
+    n = k2.shape[0] - 1
+    A = O.helmholtz_matrix(k2, 1.0 / n)
+    fs = O.scaled_rhs(f).ravel()
+    return float(np.linalg.norm(fs - A @ x.ravel()) / np.linalg.norm(fs))
+
+
+def _problem(n, k, seed=None):
+    k2 = W.constant_k2(n, k) if seed is None else W.random_k2(n, seed, 0.7 * k, k)
+    return k2, W.point_source_rhs(n, [W.center_node(n)])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_multi_equals_solo_small(precision):
+    """Five problems of three sizes (one with two right-hand sides, one with a
+    varying wavenumber): each result and cycle count equals its solo solve."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    specs = [(64, 20.0, None, 1), (128, 30.0, 4, 2), (64, 12.0, None, 1), (256, 60.0, None, 1), (128, 40.0, None, 1)]
+    solvers, rhs = [], []
+    for n, k, seed, nb in specs:
+        k2, f = _problem(n, k, seed)
+        if nb == 2:
+            f = np.concatenate([f, W.point_source_rhs(n, [(n // 4, n // 3)])])
+        solvers.append(Solver(to_gpu(k2), 1.0 / n, 1.0 / k, max_batch=nb, precision=precision))
+        rhs.append(to_gpu(f))
+    multi = Solver.solve_multi(solvers, rhs, tol=1e-6, precision=precision, max_cycles=300)
+    for S, f, (x, info) in zip(solvers, rhs, multi):
+        assert info["status"] == 0, info
+        xs, info_s = S.solve(f, tol=1e-6, precision=precision, max_cycles=300)
+        assert info["cycles"] == info_s["cycles"]
+        assert torch.equal(x, xs)
+
+
+def test_config4_mixed_sizes_32_problems():
+    """Config 4 (ii): 32 problems, n in {128, 256, 512, 1024} x 8 in seeded order,
+    k = 0.3 n, centre source, shift 1/k, GMRES(3) V(1,1), FP32-refined, solved
+    together. One problem per size is re-solved alone (bit-for-bit equal) and
+    its residual checked with the oracle's operator."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    sizes = np.random.default_rng(4).permutation(np.repeat([128, 256, 512, 1024], 8))
+    solvers, rhs, k2s = [], [], []
+    for n in sizes:
+        n = int(n)
+        k = 0.3 * n
+        k2, f = _problem(n, k)
+        solvers.append(Solver(to_gpu(k2), 1.0 / n, 1.0 / k, precision="fp32_refined"))
+        rhs.append(to_gpu(f))
+        k2s.append((k2, f))
+    multi = Solver.solve_multi(solvers, rhs, tol=1e-6, precision="fp32_refined", max_cycles=400)
+    assert all(info["status"] == 0 for _, info in multi)
+    for n in [128, 256, 512, 1024]:
+        p = int(np.nonzero(sizes == n)[0][0])
+        x, info = multi[p]
+        xs, info_s = solvers[p].solve(rhs[p], tol=1e-6, precision="fp32_refined", max_cycles=400)
+        assert info["cycles"] == info_s["cycles"], (n, info["cycles"], info_s["cycles"])
+        assert torch.equal(x, xs)
+        k2, f = k2s[p]
+        assert _relres(k2, f[0], to_np(x)[0]) <= 1e-6
+
+
+def test_config4_64_sources_one_launch_per_kernel():
+    """Config 4 (i): 64 sources at seeded distinct interior nodes on n = 512,
+    k = 100, shift 1/k, GMRES(3) V(1,1), FP32-refined, all in one batched solve
+    (grid z = source in every level kernel). Every member converges; three
+    members equal their solo solves and pass the oracle residual check."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    n, k = 512, 100.0
+    k2 = W.constant_k2(n, k)
+    nodes = W.seeded_interior_nodes(n, 64, 4)
+    f = W.point_source_rhs(n, nodes)
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, max_batch=64, precision="fp32_refined")
+    x, info = S.solve(to_gpu(f), tol=1e-6, precision="fp32_refined", max_cycles=300)
+    assert info["status"] == 0 and max(info["relres"]) <= 1e-6
+    for b in [0, 31, 63]:
+        xs, info_s = S.solve(to_gpu(f[b:b + 1]), tol=1e-6, precision="fp32_refined", max_cycles=300)
+        assert info_s["cycles"][0] == info["cycles"][b]
+        assert torch.equal(xs[0], x[b])
+        assert _relres(k2, f[b], to_np(x)[b]) <= 1e-6

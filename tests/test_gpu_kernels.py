@@ -201,13 +201,16 @@ def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
     assert rel(got32[0], ref) <= 1e-4, rel(got32[0], ref)
 
 
-@pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"}],
-                         ids=["block_cap_64", "stored_level1"])
+@pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"},
+                                 {"HELMG_L1_PRODUCT": "2", "HELMG_MAX_BLOCKS": "200"}],
+                         ids=["block_cap_64", "stored_level1", "product_level1_fp64"])
 def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
     """With a block cap of 64 every GMRES reduction goes through the one-block
-    pre-reduction pass; with HELMG_L1_PRODUCT=0 level 1 applies its stored
-    Galerkin stencil instead of R C_s P. Both give the oracle's level-1 apply
-    and cycle (FP64) and stay close to it in FP32."""
+    pre-reduction pass; HELMG_L1_PRODUCT=0 makes level 1 apply its stored
+    Galerkin stencil in both precisions, =2 the product R C_s P in both (FP32
+    cycles use the product by default, FP64 cycles the stored stencil). Each
+    gives the oracle's level-1 apply and cycle (FP64) and stays close to it in
+    FP32."""
     require_gpu()
     from paper_2308_13476_amd.solver import Solver
     for key, val in env.items():
