@@ -50,7 +50,76 @@ def parse():
     ap.add_argument("--kernel-class", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner (mg_tune) on the FP32-refined cycle before timing")
+    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32"], default="mp2a",
+                    help="mp2a: the headline n=1024 solve (default); batch64: 64 sources on n=512 in one "
+                         "batched solve; mixed32: 32 problems n=128..1024 solved together")
     return ap.parse_args()
+
+
+def batch_workloads(args):
+    """Secondary workloads (batched right-hand sides, mixed-size problems): one
+    step is one FP32-refined GMRES(3) V(1,1) solve of the whole batch to 1e-6
+    with the hierarchies set up beforehand; value = sum over right-hand sides of
+    unknowns x cycles per second. mixed32 also times the same problems solved
+    one after another."""
+    import numpy as np
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    kw = dict(tol=1e-6, cycle="V", smoother="gmres", precision="fp32_refined", max_cycles=400)
+    if args.workload == "batch64":
+        n, k = 512, 100.0
+        nodes = W.seeded_interior_nodes(n, 64, 4)
+        f = torch.from_numpy(W.point_source_rhs(n, nodes)).to(dev)
+        S = Solver(torch.from_numpy(W.constant_k2(n, k)).to(dev), 1.0 / n, 1.0 / k, max_batch=64,
+                   precision="fp32_refined")
+        run = lambda: [S.solve(f, **kw)[1]]  # noqa: E731
+        sizes = [n]
+        config = {"workload": "64 point sources at seeded interior nodes, n=512, k=100, shift 1/k, GMRES(3) V(1,1), "
+                              "FP32-refined, tol 1e-6, one batched solve", "n": n, "k": k, "batch": 64}
+    else:
+        order = np.random.default_rng(4).permutation(np.repeat([128, 256, 512, 1024], 8))
+        solvers, rhs = [], []
+        for n in order:
+            n = int(n)
+            k = 0.3 * n
+            solvers.append(Solver(torch.from_numpy(W.constant_k2(n, k)).to(dev), 1.0 / n, 1.0 / k,
+                                  precision="fp32_refined"))
+            rhs.append(torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev))
+        run = lambda: [info for _, info in Solver.solve_multi(solvers, rhs, **kw)]  # noqa: E731
+        sizes = [int(n) for n in order]
+        config = {"workload": "32 problems, n in {128,256,512,1024} x 8 (seeded order), k=0.3n, centre source, "
+                              "shift 1/k, GMRES(3) V(1,1), FP32-refined, tol 1e-6, solved together",
+                  "problems": 32}
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    dof = sum((n + 1) ** 2 * sum(info["cycles"]) for n, info in zip(sizes, infos))
+    out = {"metric": "batched V-cycle DOF/s (sum over right-hand sides), FP32-refined", "value": dof / dt,
+           "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64 cycle in c128 refinement",
+           "data": "synthetic", "config": config,
+           "cycles": [c for info in infos for c in info["cycles"]], "roofline": None, "cpu_baseline": None}
+    if args.workload == "mixed32":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for S, f in zip(solvers, rhs):
+            S.solve(f, **kw)
+        torch.cuda.synchronize()
+        seq = time.perf_counter() - t0
+        out["sequential_ms"] = seq * 1e3
+        out["speedup_vs_sequential"] = seq / dt
+    print(json.dumps(out))
 
 
 def cpu_baseline(n, k, cycles):
@@ -82,6 +151,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "mp2a":
+        batch_workloads(args)
+        return
     import numpy as np
     import torch
 
@@ -105,6 +177,7 @@ def main():
     f = torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev)
     S = Solver(k2, 1.0 / n, beta, precision="fp32_refined")
     solve_kw = dict(tol=1e-6, cycle="V", smoother="gmres", nu_pre=1, nu_post=1, max_cycles=500)
+    tuned = S.tune(f, precision="fp32_refined") if args.tune else None
     print(f"bench: n={n} k={k:g} levels={S.levels} warmup={args.warmup} steps={args.steps}", file=sys.stderr,
           flush=True)
 
@@ -168,6 +241,8 @@ def main():
                              "fp64": nodes * r64["cycles_per_solve"] / (r64["ms_per_step"] * 1e-3)},
         "fp32_refined_speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
     }
+    if tuned is not None:
+        out["tuned_settings"] = tuned
     # error of both GPU results against the stored FP64 oracle iterate and exact solution
     gold = os.path.join(ROOT, "tests", "golden", "oracle_full_size.json")
     if n == 1024 and k == 200.0 and os.path.exists(gold):

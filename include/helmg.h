@@ -139,6 +139,27 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
                          double tol, int cycle, int smoother, const mg_solve_opts* opts, mg_solve_stats* stats,
                          void* stream);
 
+/* Launch settings chosen by mg_tune. */
+typedef struct {
+    int block_cap;       /* blocks per right-hand side a level grid aims at     */
+    int tail_n;          /* levels of at most this many intervals run in the
+                            single-workgroup LDS tail (0: none)                 */
+    int level1_product;  /* level 1 as R C_s P: 0 never, 1 in FP32 cycles, 2 both */
+    double ms_per_cycle; /* measured time of one cycle with these settings      */
+    int candidates;      /* settings timed                                      */
+} mg_tune_result;
+
+/* Autotuner (a launch-setting search; the method is unchanged): times three
+ * captured cycles of the given problem (rhs [dev] complex128 [nrhs][n+1][n+1]
+ * as in mg_solve, zero initial guess) for each combination of block cap
+ * {320, 640, 1280}, tail size {0, 16, 32} and level-1 operator {stored,
+ * product}, keeps the fastest on the handle for later solves and reports it
+ * in *out (may be NULL). Overwrites the handle's iterates; results of later
+ * solves are those of the chosen settings (equal to any other setting up to
+ * rounding). MG_E_STATE while the timing hook is on. */
+mg_status mg_tune(mg_handle h, const void* rhs, int nrhs, int cycle, int smoother, const mg_solve_opts* opts,
+                  mg_tune_result* out, void* stream);
+
 /* Adjoint-state gradient for a real loss L(u) of solutions u = A_s^{-1} W f.
  *  u       [dev] complex128 [nsrc][n+1][n+1], forward solutions.
  *  grad_u  [dev] complex128 [nsrc][n+1][n+1], dL/du in PyTorch's convention

@@ -103,8 +103,10 @@ struct mg_ctx {
     hipStream_t cap_stream = nullptr;
     bool use_graph = true;
     // first level run by the single-workgroup coarse tail (-1: none), per
-    // precision (index 0: FP64 cycles, 1: FP32 cycles)
+    // precision (index 0: FP64 cycles, 1: FP32 cycles), for tail levels of at
+    // most tail_n intervals
     int tail_level[2] = {-1, -1};
+    int tail_n = 16;
     // level 1 applied as R C_s P from level-0 data instead of its stored
     // stencil: 1 in FP32 cycles (default; measured faster there, while FP64
     // cycles are faster with the stored stencil), 2 in both, 0 never
@@ -397,6 +399,16 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
 }
 
 // ---------------------------------------------------------------- cycle
+// Drops every captured cycle (after a change of launch settings).
+void clear_graphs(mg_ctx* c) {
+    for (auto& g : c->graphs) {
+        destroy_pairs(g.timed);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    }
+    c->graphs.clear();
+    c->last_graph = -1;
+}
+
 struct CycleParams {
     int gamma, smoother, nu1, nu2;
     double omega;
@@ -531,13 +543,11 @@ mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s) {
     return check_launch(c);
 }
 
-// Levels of at most HELMG_TAIL_N intervals (default 32) run in the
+// Levels of at most tail_n intervals (HELMG_TAIL_N, default 16) run in the
 // single-workgroup tail when all of them fit its LDS budget at the cycle's
 // precision and the coarsest grid is small enough for the explicit inverse;
 // HELMG_TAIL_N = 0 turns the tail off.
-void pick_tail_levels(mg_ctx* c) {
-    int tail_n = 32;
-    if (const char* e = std::getenv("HELMG_TAIL_N")) tail_n = std::atoi(e);
+void pick_tail_levels(mg_ctx* c, int tail_n) {
     const int L = c->L;
     const int nc = c->n >> (L - 1);
     const bool small_coarse = (nc + 1) * (nc + 1) <= kTailMaxCoarseNodes;
@@ -852,7 +862,14 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
         const int v = std::atoi(e);
         c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
     }
-    pick_tail_levels(c);
+    {
+        // default tail: levels of at most 16 intervals (the autotuner's choice on
+        // the n = 1024 benchmark; 32 was 0.5 ms per solve slower there)
+        int tail_n = 16;
+        if (const char* e = std::getenv("HELMG_TAIL_N")) tail_n = std::atoi(e);
+        c->tail_n = tail_n;
+        pick_tail_levels(c, tail_n);
+    }
     tail_init();
     carve(c, c->ws, n, L, transfer, max_batch, has32);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1087,6 +1104,87 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
     }
     HM_HIP(hipStreamSynchronize(s));
     return worst;
+}
+
+mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother, const mg_solve_opts* opts,
+                  mg_tune_result* out, void* stream) {
+    if (!c) return MG_E_ARG;
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    if (mg_status st = check_solve_args(c, nrhs, 1.0, cyc, smoother, o)) return st;
+    if (!is_dev_ptr_ok(rhs)) { c->err = "rhs NULL or misaligned"; return MG_E_ARG; }
+    if (c->timing_class != 0) { c->err = "mg_tune needs the timing hook off"; return MG_E_STATE; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LevelBuf& l0 = c->lv[0];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HM_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        c->err = "hipEventCreate failed";
+        return MG_E_HIP;
+    }
+    struct Guard {
+        hipEvent_t a, b;
+        ~Guard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } guard{e0, e1};
+    const int caps[] = {320, 640, 1280};
+    const int tails[] = {0, 16, 32};
+    const int prods[] = {0, 1};
+    const int keep_cap = c->block_cap, keep_tail = c->tail_n, keep_prod = c->product_l1;
+    double best = 1e300;
+    int best_cap = keep_cap, best_tail = keep_tail, best_prod = keep_prod, tried = 0;
+    constexpr int kTimed = 3;
+    for (int cap : caps)
+        for (int tail : tails)
+            for (int prod : prods) {
+                c->block_cap = cap;
+                c->tail_n = tail;
+                pick_tail_levels(c, tail);
+                c->product_l1 = prod;
+                clear_graphs(c);
+                LaunchCtx lc = launch_ctx(c, s, nrhs);
+                lc.active = nullptr;
+                launch_copy_in<double>(lc, l0.g, rhs, false, vec<double>(l0.f64, l0), true, false);
+                launch_zero<double>(s, l0.u64, l0.g.plane * nrhs);
+                if (mg_status st = check_launch(c)) return st;
+                SolveRun run(c, nrhs, 1e-300, cyc, smoother, o);
+                if (mg_status st = run.start(s)) return st;
+                HM_HIP(hipStreamSynchronize(s));
+                if (mg_status st = run.begin(s)) return st;
+                auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
+                if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;  // warm-up and capture
+                HM_HIP(hipEventRecord(e0, s));
+                for (int k = 0; k < kTimed; ++k)
+                    if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
+                HM_HIP(hipEventRecord(e1, s));
+                HM_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                HM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ++tried;
+                const double per = double(ms) / kTimed;
+                if (per < best) {
+                    best = per;
+                    best_cap = cap;
+                    best_tail = tail;
+                    best_prod = prod;
+                }
+            }
+    c->block_cap = best_cap;
+    c->tail_n = best_tail;
+    pick_tail_levels(c, best_tail);
+    c->product_l1 = best_prod;
+    clear_graphs(c);
+    HM_HIP(hipStreamSynchronize(s));
+    if (out) {
+        out->block_cap = best_cap;
+        out->tail_n = best_tail;
+        out->level1_product = best_prod;
+        out->ms_per_cycle = best;
+        out->candidates = tried;
+    }
+    return MG_OK;
 }
 
 mg_status mg_grad(mg_handle c, const void* u, const void* grad_u, int nsrc, double tol, int cyc, int smoother,

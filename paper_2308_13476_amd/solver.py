@@ -129,6 +129,18 @@ class Solver:
             raise B.MGError(st, B.last_error(self.handle))
         return x, info
 
+    def tune(self, rhs: torch.Tensor, cycle="V", smoother="gmres", nu_pre=1, nu_post=1, omega=4.5,
+             precision="fp64") -> dict:
+        """mg_tune: times cycles of this problem under each candidate launch setting
+        and keeps the fastest for later solves."""
+        f = _batched(rhs, self.n, torch.complex128)
+        opts = self.solve_options(nu_pre, nu_post, omega, 1, precision)
+        res = B.TuneResult()
+        _check(B.lib().mg_tune(self.handle, _ptr(f), f.shape[0], _CYCLE[cycle], _SMOOTHER[smoother],
+                               ctypes.byref(opts), ctypes.byref(res), _stream()), self.handle)
+        return {"block_cap": res.block_cap, "tail_n": res.tail_n, "level1_product": res.level1_product,
+                "ms_per_cycle": res.ms_per_cycle, "candidates": res.candidates}
+
     @staticmethod
     def solve_multi(solvers, rhs_list, x0_list=None, tol: float = 1e-6, cycle="V", smoother="gmres", nu_pre=1,
                     nu_post=1, omega=4.5, max_cycles=500, precision="fp64", divergence=1e8, raise_on_error=True):

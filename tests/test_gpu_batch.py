@@ -95,3 +95,29 @@ def test_config4_64_sources_one_launch_per_kernel():
         assert info_s["cycles"][0] == info["cycles"][b]
         assert torch.equal(xs[0], x[b])
         assert _relres(k2, f[b], to_np(x)[b]) <= 1e-6
+
+
+def test_autotuner_choice_keeps_oracle_results():
+    """mg_tune times all 18 launch settings on the caller's problem and keeps the
+    fastest; a solve afterwards still matches the oracle (cycle count within
+    one, iterate within 1e-10 after the same number of cycles)."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    n, k = 128, 30.0
+    k2 = W.random_k2(n, 6, 20.0, 30.0)
+    f = W.point_source_rhs(n, [W.center_node(n)])
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k)
+    choice = S.tune(to_gpu(f))
+    assert choice["candidates"] == 18
+    assert choice["block_cap"] in (320, 640, 1280) and choice["tail_n"] in (0, 16, 32)
+    assert choice["level1_product"] in (0, 1) and choice["ms_per_cycle"] > 0
+    x, info = S.solve(to_gpu(f), tol=1e-6)
+    assert info["status"] == 0
+    H = O.build_hierarchy(k2, 1.0 / n, 1.0 / k)
+    fs = O.scaled_rhs(f[0]).ravel()
+    opts = O.CycleOptions(smoother="gmres")
+    ref = O.solve(H, fs, opts, tol=1e-6, max_cycles=300)
+    assert abs(ref.cycles - info["cycles"][0]) <= 1
+    same = O.solve(H, fs, opts, tol=1e-30, max_cycles=info["cycles"][0])
+    x = to_np(x)[0].ravel()
+    assert np.linalg.norm(x - same.x) / np.linalg.norm(same.x) <= 1e-10
