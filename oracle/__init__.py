@@ -15,6 +15,7 @@ Modules
                FP32-in-FP64 refinement
   twogrid   -- the dense two-grid iteration matrix of §3 for tiny grids
   adjoint   -- misfit, adjoint-state gradient w.r.t. per-node k^2
+  krylov    -- flexible GMRES(m) with a multigrid cycle as right preconditioner
 
 Every function states the passage it follows; readings of silent or garbled
 passages are listed with the design notes of the repository.
@@ -41,3 +42,4 @@ from .multigrid import (  # noqa: F401
     solve_refined,
     SolveResult,
 )
+from .krylov import fgmres, mg_preconditioner, FgmresResult  # noqa: F401

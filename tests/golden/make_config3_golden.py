@@ -9,7 +9,9 @@ cycles (§5.3), Bézier transfers (§4), coarsening to 4 x 4 intervals.
 Stores the FP64 cycle count to relative residual 1e-6 and the residual
 history of every cycle.
 
-Run: python tests/golden/make_config3_golden.py   (tens of minutes, one core)
+Run: python tests/golden/make_config3_golden.py [wedge] [grf]   (tens of minutes per
+medium, one core; media given on the command line are (re)computed and merged into
+the existing file)
 """
 import json
 import os
@@ -35,12 +37,13 @@ def medium(name):
     return W.k2_from_velocity(c, KH_MAX)
 
 
-def main():
+def main(media):
+    path = os.path.join(HERE, "oracle_config3.json")
     out = {"workload": f"n={N}, seed {SEED}, max kh {KH_MAX}, source (n/2, round(0.9 n)), shift 1/k_max, "
                        "GMRES(3) V(1,1), Bezier, coarsest 4x4 intervals, FP64", "tol": TOL, "runs": {}}
     src = (N // 2, int(round(0.9 * N)))
     fs = O.scaled_rhs(W.point_source_rhs(N, [src])[0]).ravel()
-    for name in ["wedge", "grf"]:
+    for name in media:
         k2 = medium(name)
         kmax = float(np.sqrt(k2.max()))
         t = time.time()
@@ -51,9 +54,11 @@ def main():
         out["runs"][name] = {"cycles": res.cycles, "status": res.status, "history": res.history,
                              "k_max": kmax, "setup_seconds": setup, "seconds": time.time() - t}
         print(name, res.cycles, res.status, round(setup, 1), round(time.time() - t, 1), flush=True)
-        with open(os.path.join(HERE, "oracle_config3.json"), "w") as fh:
-            json.dump(out, fh, indent=1)
+        merged = json.load(open(path)) if os.path.exists(path) else {**out, "runs": {}}
+        merged["runs"][name] = out["runs"][name]
+        with open(path, "w") as fh:
+            json.dump(merged, fh, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:] or ["wedge", "grf"])
