@@ -52,7 +52,7 @@ def parse():
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (mg_tune) on the FP32-refined cycle before timing")
-    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32"], default="mp2a",
+    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres"], default="mp2a",
                     help="mp2a: the headline n=1024 solve (default); batch64: 64 sources on n=512 in one "
                          "batched solve; mixed32: 32 problems n=128..1024 solved together")
     return ap.parse_args()
@@ -146,11 +146,53 @@ def cpu_baseline(n, k, cycles):
                       f"(oracle setup excluded), {dt:.1f} s on one host thread"}
 
 
+def fgmres_workload(args):
+    """The headline problem solved by FP64 flexible GMRES(20) with one FP32
+    GMRES(3) V(1,1) cycle per iteration as preconditioner (multigrid as a
+    preconditioner, §1), to relative residual 1e-6, beside the stand-alone
+    FP32-refined solve; hierarchy set up beforehand."""
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    n, k = args.n, args.k
+    k2 = torch.from_numpy(W.constant_k2(n, k)).to(dev)
+    f = torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev)
+    S = Solver(k2, 1.0 / n, 1.0 / k, precision="fp32_refined")
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3, info
+
+    ms_k, info_k = timed(lambda: S.solve_fgmres(f, tol=1e-6, m=20, precision="fp32_refined")[1])
+    ms_a, info_a = timed(lambda: S.solve(f, tol=1e-6, precision="fp32_refined")[1])
+    out = {"metric": "time to rel.res 1e-6, FGMRES(20) + FP32 V-cycle preconditioner vs stand-alone FP32-refined",
+           "value": ms_k, "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_k, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c128 outer, c64 cycle", "data": "synthetic",
+           "config": {"workload": f"MP 2-A n={n}, k={k:g}, centre source, shift 1/k, GMRES(3) V(1,1) preconditioner, "
+                                  "FGMRES(20) in FP64, tol 1e-6, setup excluded", "n": n, "k": k},
+           "fgmres_iterations": info_k["cycles"][0], "fgmres_relres": info_k["relres"][0],
+           "standalone_ms": ms_a, "standalone_cycles": info_a["cycles"][0], "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "fgmres":
+        fgmres_workload(args)
+        return
     if args.workload != "mp2a":
         batch_workloads(args)
         return

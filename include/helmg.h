@@ -160,6 +160,30 @@ typedef struct {
 mg_status mg_tune(mg_handle h, const void* rhs, int nrhs, int cycle, int smoother, const mg_solve_opts* opts,
                   mg_tune_result* out, void* stream);
 
+/* Outer Krylov solver with the multigrid cycle as preconditioner (§1: multigrid
+ * on the CSL used as a preconditioner for GMRES). Restarted flexible GMRES(m)
+ * in FP64 on A_s x = W f with right preconditioning: every direction is
+ * z_j = one cycle (cycle, smoother, opts->nu_pre / nu_post / omega) on
+ * A_s z = v_j from z = 0, an FP64 cycle, or the FP32 cycle when
+ * opts->precision is MG_FP32_REFINED; modified Gram-Schmidt Arnoldi; the
+ * least-squares problem by Givens rotations on the host (one stream
+ * synchronisation per iteration).
+ *  rhs, x, nrhs as in mg_solve; m restart length in [1, 64].
+ *  krylov [dev] caller's buffer of at least mg_fgmres_workspace_bytes(h, m)
+ *         bytes, 256-byte aligned (basis V, directions Z, x, f, w, H, y);
+ *         zeroed and overwritten by every call, no contents need survive.
+ *  stats->cycles: iterations (= preconditioner cycles); relres: true
+ *         relative residual of the returned x; history[it * nrhs + b]: the
+ *         iteration's residual estimate (NaN after a right-hand side stopped).
+ * A right-hand side stops when the estimate reaches tol (at the end of that
+ * restart cycle's update) or after opts->max_cycles iterations. Returns
+ * MG_OK, MG_NOT_CONVERGED (x holds the last iterates), MG_E_WORKSPACE, or
+ * the errors of mg_solve. */
+size_t mg_fgmres_workspace_bytes(mg_handle h, int m);
+mg_status mg_solve_fgmres(mg_handle h, const void* rhs, void* x, int nrhs, double tol, int m, int cycle,
+                          int smoother, const mg_solve_opts* opts, void* krylov, size_t krylov_bytes,
+                          mg_solve_stats* stats, void* stream);
+
 /* Adjoint-state gradient for a real loss L(u) of solutions u = A_s^{-1} W f.
  *  u       [dev] complex128 [nsrc][n+1][n+1], forward solutions.
  *  grad_u  [dev] complex128 [nsrc][n+1][n+1], dL/du in PyTorch's convention

@@ -20,8 +20,8 @@ MG_JACOBI, MG_GMRES3 = 0, 1
 MG_FP64, MG_FP32_REFINED = 0, 1
 
 EXPORTED = [
-    "mg_workspace_bytes", "mg_setup", "mg_update_k2", "mg_solve", "mg_solve_multi", "mg_tune", "mg_grad",
-    "mg_destroy",
+    "mg_workspace_bytes", "mg_setup", "mg_update_k2", "mg_solve", "mg_solve_multi", "mg_tune",
+    "mg_fgmres_workspace_bytes", "mg_solve_fgmres", "mg_grad", "mg_destroy",
     "mg_status_string", "mg_last_error", "mg_level_info", "mg_get_stencil", "mg_apply", "mg_residual",
     "mg_smooth", "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_set_timing",
     "mg_get_timing",
@@ -74,6 +74,9 @@ def lib() -> ctypes.CDLL:
         "mg_solve_multi": (ci, [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ctypes.POINTER(vp), pi, cd, ci, ci,
                                 ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]),
         "mg_tune": (ci, [vp, vp, ci, ci, ci, ctypes.POINTER(SolveOpts), ctypes.POINTER(TuneResult), vp]),
+        "mg_fgmres_workspace_bytes": (sz, [vp, ci]),
+        "mg_solve_fgmres": (ci, [vp, vp, vp, ci, cd, ci, ci, ci, ctypes.POINTER(SolveOpts), vp, sz,
+                                 ctypes.POINTER(SolveStats), vp]),
         "mg_grad": (ci, [vp, vp, vp, ci, cd, ci, ci, ctypes.POINTER(SolveOpts), vp, vp,
                          ctypes.POINTER(SolveStats), vp]),
         "mg_destroy": (ci, [vp]),

@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libhelmg.so")
 ARCH = os.environ.get("HELMG_ARCH", "gfx950")
 
-SOURCES = ["hm_level.hip", "hm_setup.hip", "hm_tail.hip", "hm_runtime.cpp"]
+SOURCES = ["hm_level.hip", "hm_setup.hip", "hm_tail.hip", "hm_krylov.hip", "hm_runtime.cpp"]
 FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",

@@ -152,6 +152,20 @@ void tail_init();
 // inv = A^{-1} from the LU factor and pivots of launch_dense_lu, N <= kTailMaxCoarseNodes.
 void launch_lu_inverse(hipStream_t, int N, const cplx<double>* lu, const int* piv, cplx<double>* inv);
 
+// ---- outer flexible GMRES (level-0 FP64 vectors, [j][b][plane]) ----
+// w is orthogonalised against V_0..V_j by modified Gram-Schmidt; H[b * hstride + i]
+// receives column j (i = 0..j) and the subdiagonal ||w|| (i = j + 1); V_{j+1} = w / ||w||.
+void launch_kry_orthogonalise(const LaunchCtx&, Grid g, cplx<double>* V, long long vstride, int j,
+                              cplx<double>* w, cplx<double>* H, int hstride, long long plane);
+// v = r / ||r|| with ||r||^2 from norms[b].r2.
+void launch_kry_first(const LaunchCtx&, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
+                      const RhsNorms* norms);
+// x += sum_{i < nz} y[b * ystride + i] Z_i.
+void launch_kry_update(const LaunchCtx&, Grid g, const cplx<double>* Z, long long zstride, int nz,
+                       const cplx<double>* y, int ystride, cplx<double>* x, long long plane);
+void launch_kry_cast_down(const LaunchCtx&, Grid g, const cplx<double>* src, cplx<float>* dst, long long plane);
+void launch_kry_cast_up(const LaunchCtx&, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane);
+
 // ---- setup ----
 // Padded k^2 planes from the caller's dense array (FP64 and optionally FP32).
 void launch_k2_in(hipStream_t, Grid g, const double* k2_dense, double* k2_64, float* k2_32);

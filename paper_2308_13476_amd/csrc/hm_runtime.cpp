@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -1104,6 +1105,269 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
     }
     HM_HIP(hipStreamSynchronize(s));
     return worst;
+}
+
+namespace {
+
+constexpr int kMaxRestart = 64;
+
+// Carve of the caller's FGMRES buffer (base == nullptr only measures).
+struct KrylovBuf {
+    cplx<double>* V = nullptr;  // (m + 1) vectors
+    cplx<double>* Z = nullptr;  // m vectors
+    cplx<double>* X = nullptr;
+    cplx<double>* F = nullptr;
+    cplx<double>* Wv = nullptr;
+    cplx<double>* H = nullptr;  // [B][m + 1], one column at a time
+    cplx<double>* Y = nullptr;  // [B][m]
+    long long vstride = 0;      // values per vector (all right-hand sides)
+    size_t bytes = 0;
+};
+
+KrylovBuf krylov_carve(const mg_ctx* c, int m, char* base) {
+    KrylovBuf k;
+    Carver cv{base};
+    const size_t B = size_t(c->max_batch);
+    const size_t pl = size_t(c->lv[0].g.plane);
+    k.vstride = (long long)(B * pl);
+    k.V = cv.take<cplx<double>>(size_t(m + 1) * B * pl * 16);
+    k.Z = cv.take<cplx<double>>(size_t(m) * B * pl * 16);
+    k.X = cv.take<cplx<double>>(B * pl * 16);
+    k.F = cv.take<cplx<double>>(B * pl * 16);
+    k.Wv = cv.take<cplx<double>>(B * pl * 16);
+    k.H = cv.take<cplx<double>>(B * size_t(m + 1) * 16);
+    k.Y = cv.take<cplx<double>>(B * size_t(m) * 16);
+    k.bytes = align_up(cv.off, kAlign);
+    return k;
+}
+
+}  // namespace
+
+size_t mg_fgmres_workspace_bytes(mg_handle c, int m) {
+    if (!c || m < 1 || m > kMaxRestart) return 0;
+    return krylov_carve(c, m, nullptr).bytes;
+}
+
+mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, double tol, int m, int cyc, int smoother,
+                          const mg_solve_opts* opts, void* krylov, size_t krylov_bytes, mg_solve_stats* stats,
+                          void* stream) {
+    if (!c) return MG_E_ARG;
+    const mg_solve_opts o = opts ? *opts : default_solve_opts();
+    if (mg_status st = check_solve_args(c, nrhs, tol, cyc, smoother, o)) return st;
+    if (m < 1 || m > kMaxRestart) { c->err = "restart length m must be in [1, 64]"; return MG_E_ARG; }
+    if (!is_dev_ptr_ok(rhs) || !is_dev_ptr_ok(x)) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
+    if (!krylov || (reinterpret_cast<uintptr_t>(krylov) % kAlign) != 0) {
+        c->err = "krylov buffer NULL or not 256-byte aligned";
+        return MG_E_WORKSPACE;
+    }
+    const KrylovBuf K = krylov_carve(c, m, static_cast<char*>(krylov));
+    if (krylov_bytes < K.bytes) {
+        c->err = "krylov buffer too small: need " + std::to_string(K.bytes) + " bytes";
+        return MG_E_WORKSPACE;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LevelBuf& l0 = c->lv[0];
+    const Grid g0 = l0.g;
+    const long long pl = g0.plane;
+    const bool fp32 = o.precision == MG_FP32_REFINED;
+    const LevelOp<double> op0 = level_op<double>(c, 0);
+    const CycleParams cp{cyc, smoother, o.nu_pre, o.nu_post, o.omega};
+    LaunchCtx lc = launch_ctx(c, s, nrhs);
+    lc.active = nullptr;
+    // every plane of the buffer gets a zero ghost frame (the level-0 operator
+    // reads ghosts as zero; kernels here write interior nodes only)
+    launch_fill_words(s, krylov, (long long)(K.bytes / 4 * 4), 0u);
+    launch_copy_in<double>(lc, g0, rhs, false, vec<double>(K.F, l0), true, false);
+    launch_copy_in<double>(lc, g0, x, false, vec<double>(K.X, l0), false, false);
+    for (int b = 0; b < nrhs; ++b) c->h_active[b] = 1;
+    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    lc.active = c->active;
+    launch_norm<double>(lc, g0, vec<double>(K.F, l0), c->norms);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    std::vector<double> nf(nrhs), rel(nrhs, 0.0);
+    std::vector<int> its(nrhs, 0), state(nrhs, 0);  // 0 running, 1 converged, 3 out of iterations
+    for (int b = 0; b < nrhs; ++b) nf[b] = std::sqrt(c->h_norms[b].f2);
+    uint64_t omega_bits;
+    std::memcpy(&omega_bits, &o.omega, sizeof(omega_bits));
+    const std::vector<uintptr_t> key{0xF6E5u, uintptr_t(fp32), uintptr_t(cyc), uintptr_t(smoother),
+                                     uintptr_t(o.nu_pre), uintptr_t(o.nu_post), uintptr_t(omega_bits),
+                                     uintptr_t(nrhs)};
+    auto precond_body = [&](hipStream_t st) {
+        LaunchCtx l2 = lc;
+        l2.stream = st;
+        if (fp32) {
+            launch_zero<float>(st, l0.u32, pl * nrhs);
+            cycle<float>(c, l2, 0, cp);
+        } else {
+            launch_zero<double>(st, l0.u64, pl * nrhs);
+            cycle<double>(c, l2, 0, cp);
+        }
+    };
+    std::vector<cplx<double>> hcol(size_t(nrhs) * (m + 1)), yh(size_t(nrhs) * m);
+    // per right-hand side: Hessenberg columns rotated to upper triangular, rotations, g
+    std::vector<std::vector<std::complex<double>>> R(nrhs), gvec(nrhs), sn(nrhs);
+    std::vector<std::vector<double>> cs(nrhs);
+    std::vector<int> kdir(nrhs, 0);
+    auto set_active = [&](const std::vector<int>& act) -> mg_status {
+        // an earlier upload from h_active may still be pending on the stream
+        HM_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < nrhs; ++b) c->h_active[b] = act[b];
+        HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        return MG_OK;
+    };
+    for (;;) {
+        // true residual r = f - A x at the start of a restart cycle
+        std::vector<int> act(nrhs);
+        for (int b = 0; b < nrhs; ++b) act[b] = state[b] == 0;
+        if (mg_status st = set_active(act)) return st;
+        launch_residual<double>(lc, op0, vec<double>(K.X, l0), vec<double>(K.F, l0), vec<double>(K.Wv, l0));
+        launch_resnorm<double>(lc, op0, vec<double>(K.X, l0), vec<double>(K.F, l0), c->norms);
+        if (mg_status st = check_launch(c)) return st;
+        HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+        HM_HIP(hipStreamSynchronize(s));
+        int running = 0;
+        for (int b = 0; b < nrhs; ++b) {
+            if (state[b] != 0) continue;
+            const double beta = std::sqrt(c->h_norms[b].r2);
+            rel[b] = nf[b] > 0.0 ? beta / nf[b] : 0.0;
+            if (nf[b] == 0.0 || rel[b] <= tol) state[b] = 1;
+            else if (its[b] >= o.max_cycles) state[b] = 3;
+            if (state[b] != 0) {
+                act[b] = 0;
+                continue;
+            }
+            ++running;
+            R[b].assign(size_t(m + 1) * m, 0.0);
+            gvec[b].assign(m + 1, 0.0);
+            gvec[b][0] = beta;
+            cs[b].assign(m, 0.0);
+            sn[b].assign(m, 0.0);
+            kdir[b] = 0;
+        }
+        if (running == 0) break;
+        if (mg_status st = set_active(act)) return st;
+        launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms);
+        std::vector<int> in_cycle = act;  // right-hand sides updated at the end of this cycle
+        std::vector<int> stopped(nrhs, 0);
+        for (int j = 0; j < m; ++j) {
+            // z_j = M(v_j): one cycle from zero on A_s z = v_j
+            cplx<double>* vj = K.V + j * K.vstride;
+            cplx<double>* zj = K.Z + j * K.vstride;
+            if (fp32) launch_kry_cast_down(lc, g0, vj, l0.f32, pl);
+            else HM_HIP(hipMemcpyAsync(l0.f64, vj, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
+            if (mg_status st = run_cycle_graph(c, s, key, precond_body)) return st;
+            if (fp32) launch_kry_cast_up(lc, g0, l0.u32, zj, pl);
+            else HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
+            // w = A_s z_j, orthogonalised into column j of H and v_{j+1}
+            launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
+            launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl);
+            if (mg_status st = check_launch(c)) return st;
+            HM_HIP(hipMemcpyAsync(hcol.data(), K.H, sizeof(cplx<double>) * nrhs * (m + 1), hipMemcpyDeviceToHost,
+                                  s));
+            HM_HIP(hipStreamSynchronize(s));
+            bool any = false;
+            for (int b = 0; b < nrhs; ++b) {
+                if (!act[b]) continue;
+                std::vector<std::complex<double>> h(j + 2);
+                for (int i = 0; i <= j + 1; ++i) h[i] = {hcol[size_t(b) * (m + 1) + i].re, hcol[size_t(b) * (m + 1) + i].im};
+                // earlier rotations, then the one that zeroes h[j+1]
+                for (int i = 0; i < j; ++i) {
+                    const std::complex<double> a = h[i], bb = h[i + 1];
+                    h[i] = cs[b][i] * a + sn[b][i] * bb;
+                    h[i + 1] = -std::conj(sn[b][i]) * a + cs[b][i] * bb;
+                }
+                const std::complex<double> a = h[j], bb = h[j + 1];
+                const double na = std::abs(a), rho = std::sqrt(std::norm(a) + std::norm(bb));
+                double cj;
+                std::complex<double> sj;
+                if (rho == 0.0) {
+                    cj = 1.0;
+                    sj = 0.0;
+                } else if (na == 0.0) {
+                    cj = 0.0;
+                    sj = std::conj(bb) / rho;
+                } else {
+                    cj = na / rho;
+                    sj = (a / na) * std::conj(bb) / rho;
+                }
+                cs[b][j] = cj;
+                sn[b][j] = sj;
+                h[j] = cj * a + sj * bb;
+                for (int i = 0; i <= j; ++i) R[b][size_t(i) * m + j] = h[i];
+                const std::complex<double> g0v = gvec[b][j];
+                gvec[b][j] = cj * g0v;
+                gvec[b][j + 1] = -std::conj(sj) * g0v;
+                const double est = std::abs(gvec[b][j + 1]) / nf[b];
+                ++its[b];
+                kdir[b] = j + 1;
+                rel[b] = est;
+                if (stats && stats->history && its[b] <= o.max_cycles)
+                    stats->history[size_t(its[b] - 1) * nrhs + b] = est;
+                const bool subzero = hcol[size_t(b) * (m + 1) + j + 1].re == 0.0;
+                if (est <= tol || its[b] >= o.max_cycles || subzero) {
+                    act[b] = 0;
+                    if (est <= tol) stopped[b] = 1;
+                } else {
+                    any = true;
+                }
+            }
+            if (!any || j == m - 1) break;
+            if (mg_status st = set_active(act)) return st;
+        }
+        // x += Z y for every right-hand side of this cycle (R y = g by back substitution)
+        for (int b = 0; b < nrhs; ++b) {
+            for (int i = 0; i < m; ++i) yh[size_t(b) * m + i] = {0.0, 0.0};
+            if (!in_cycle[b]) continue;
+            const int k = kdir[b];
+            std::vector<std::complex<double>> y(k);
+            for (int i = k - 1; i >= 0; --i) {
+                std::complex<double> t = gvec[b][i];
+                for (int q = i + 1; q < k; ++q) t -= R[b][size_t(i) * m + q] * y[q];
+                y[i] = t / R[b][size_t(i) * m + i];
+            }
+            for (int i = 0; i < k; ++i) yh[size_t(b) * m + i] = {y[i].real(), y[i].imag()};
+        }
+        HM_HIP(hipMemcpyAsync(K.Y, yh.data(), sizeof(cplx<double>) * nrhs * m, hipMemcpyHostToDevice, s));
+        if (mg_status st = set_active(in_cycle)) return st;
+        int kmax = 0;
+        for (int b = 0; b < nrhs; ++b)
+            if (in_cycle[b]) kmax = std::max(kmax, kdir[b]);
+        launch_kry_update(lc, g0, K.Z, K.vstride, kmax, K.Y, m, K.X, pl);
+        if (mg_status st = check_launch(c)) return st;
+        for (int b = 0; b < nrhs; ++b)
+            if (stopped[b]) state[b] = 1;
+    }
+    // final true residuals of every right-hand side
+    for (int b = 0; b < nrhs; ++b) c->h_active[b] = 1;
+    HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+    launch_resnorm<double>(lc, op0, vec<double>(K.X, l0), vec<double>(K.F, l0), c->norms);
+    lc.active = nullptr;
+    launch_copy_out<double>(lc, g0, vec<double>(K.X, l0), x, false, false, false);
+    if (mg_status st = check_launch(c)) return st;
+    HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
+    HM_HIP(hipStreamSynchronize(s));
+    mg_status res = MG_OK;
+    for (int b = 0; b < nrhs; ++b) {
+        rel[b] = nf[b] > 0.0 ? std::sqrt(c->h_norms[b].r2) / nf[b] : 0.0;
+        if (state[b] != 1) res = MG_NOT_CONVERGED;
+    }
+    if (stats) {
+        for (int b = 0; b < nrhs; ++b) {
+            if (stats->cycles) stats->cycles[b] = its[b];
+            if (stats->relres) stats->relres[b] = rel[b];
+        }
+        if (stats->history) {
+            int itmax = 0;
+            for (int b = 0; b < nrhs; ++b) itmax = std::max(itmax, its[b]);
+            for (int b = 0; b < nrhs; ++b)
+                for (int it = its[b]; it < itmax && it < o.max_cycles; ++it) stats->history[size_t(it) * nrhs + b] = NAN;
+        }
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return res;
 }
 
 mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother, const mg_solve_opts* opts,

@@ -129,6 +129,37 @@ class Solver:
             raise B.MGError(st, B.last_error(self.handle))
         return x, info
 
+    def solve_fgmres(self, rhs: torch.Tensor, x0: torch.Tensor | None = None, tol: float = 1e-6, m: int = 20,
+                     cycle="V", smoother="gmres", nu_pre=1, nu_post=1, omega=4.5, max_iter=500, precision="fp64",
+                     history=False, raise_on_error=True):
+        """mg_solve_fgmres: FP64 flexible GMRES(m) preconditioned by one cycle per
+        iteration. Returns (x, info); info["cycles"] counts iterations."""
+        f = _batched(rhs, self.n, torch.complex128)
+        nb = f.shape[0]
+        x = torch.zeros_like(f) if x0 is None else _batched(x0, self.n, torch.complex128).clone()
+        nbytes = B.lib().mg_fgmres_workspace_bytes(self.handle, int(m))
+        if nbytes == 0:
+            raise ValueError("restart length m must be in [1, 64]")
+        kry = torch.empty(nbytes, dtype=torch.uint8, device=f.device)
+        opts = self.solve_options(nu_pre, nu_post, omega, max_iter, precision)
+        cycles = (ctypes.c_int * nb)()
+        rel = (ctypes.c_double * nb)()
+        hist = (ctypes.c_double * (nb * max_iter))() if history else None
+        stats = B.SolveStats(ctypes.cast(cycles, ctypes.POINTER(ctypes.c_int)),
+                             ctypes.cast(rel, ctypes.POINTER(ctypes.c_double)),
+                             ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None, 0.0)
+        st = B.lib().mg_solve_fgmres(self.handle, _ptr(f), _ptr(x), nb, float(tol), int(m), _CYCLE[cycle],
+                                     _SMOOTHER[smoother], ctypes.byref(opts), _ptr(kry), nbytes,
+                                     ctypes.byref(stats), _stream())
+        info = {"status": st, "status_name": B.status_string(st), "cycles": list(cycles), "relres": list(rel),
+                "seconds": stats.seconds}
+        if hist is not None:
+            h = list(hist)
+            info["history"] = [[h[it * nb + b] for it in range(max(info["cycles"]))] for b in range(nb)]
+        if raise_on_error and st < 0:
+            raise B.MGError(st, B.last_error(self.handle))
+        return x, info
+
     def tune(self, rhs: torch.Tensor, cycle="V", smoother="gmres", nu_pre=1, nu_post=1, omega=4.5,
              precision="fp64") -> dict:
         """mg_tune: times cycles of this problem under each candidate launch setting

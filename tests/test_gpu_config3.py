@@ -1,0 +1,50 @@
+"""Config 3 at full size: n = 2048 (4,198,401 unknowns) in a three-layer wedge
+and a Gaussian random velocity, max kh = 0.3, source near the top centre,
+shift 1 / max(k), GMRES(3) V(1,1). FP64 cycle counts and per-cycle residual
+histories against stored oracle runs (tests/golden/oracle_config3.json,
+written by make_config3_golden.py from the oracle only); FP32-refined solves
+within one cycle of them; both solutions pass the oracle operator's residual
+check."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_13476_amd import workloads as W
+from tests.gpu_common import require_gpu, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_config3.json")
+
+
+@pytest.mark.parametrize("medium", ["wedge", "grf"])
+def test_config3_n2048_against_stored_oracle_runs(medium):
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    g = json.load(open(GOLDEN))
+    ref = g["runs"][medium]
+    n = 2048
+    c = W.wedge_velocity(n, 3) if medium == "wedge" else W.grf_velocity(n, 3)
+    k2 = W.k2_from_velocity(c, 0.3)
+    kmax = float(np.sqrt(k2.max()))
+    assert abs(kmax - ref["k_max"]) <= 1e-9 * kmax
+    f = W.point_source_rhs(n, [(n // 2, int(round(0.9 * n)))])
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / kmax, precision="fp32_refined")
+    A_s = O.helmholtz_matrix(k2, 1.0 / n)
+    fs = O.scaled_rhs(f[0]).ravel()
+    x, info = S.solve(to_gpu(f), tol=g["tol"], history=True, max_cycles=800)
+    assert info["status"] == 0
+    assert abs(info["cycles"][0] - ref["cycles"]) <= 1, (info["cycles"], ref["cycles"])
+    m = min(len(ref["history"]), info["cycles"][0])
+    got = np.array(info["history"][0][:m])
+    want = np.array(ref["history"][:m])
+    assert np.max(np.abs(got - want) / want) <= 1e-6, np.max(np.abs(got - want) / want)
+    x64 = to_np(x)[0].ravel()
+    assert np.linalg.norm(fs - A_s @ x64) / np.linalg.norm(fs) <= g["tol"]
+    x32, info32 = S.solve(to_gpu(f), tol=g["tol"], precision="fp32_refined", max_cycles=800)
+    assert info32["status"] == 0
+    assert abs(info32["cycles"][0] - ref["cycles"]) <= 1, (info32["cycles"], ref["cycles"])
+    x32 = to_np(x32)[0].ravel()
+    assert np.linalg.norm(fs - A_s @ x32) / np.linalg.norm(fs) <= g["tol"]
