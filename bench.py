@@ -37,6 +37,24 @@ KERNEL_CLASSES = {
     1: {"name": "level-0 GMRES(3) orthogonalise + apply pass (complex64)", "bytes_per_node": 44.0},
 }
 
+# HBM traffic of the class-1 kernel per launch from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; profiles/ holds the summary and the commands), each
+# scaled by what the counter reads for a plain copy of known size. Valid only
+# for the kernel sources it was measured on: the hash below is of the files in
+# TRAFFIC_SOURCES, and a different hash reports traffic as null.
+TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
+                   "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
+MEASURED_TRAFFIC = None  # {"sources_sha256": ..., "fetch_bytes": ..., "write_bytes": ..., "profile": ...}
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel_path in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel_path), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -304,8 +322,11 @@ def main():
         kc = KERNEL_CLASSES[args.kernel_class]
         avg_ms = kms / launches
         achieved = kc["bytes_per_node"] * knodes / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_sha256():
+            traffic = MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]  # bytes per launch
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kc["name"],
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kc["name"],
                            "avg_launch_us": avg_ms * 1e3, "launches": launches,
                            "timed_in": "repeat of the timed steps with HIP events per launch (no graphs)"}
     if not args.no_cpu_baseline:
