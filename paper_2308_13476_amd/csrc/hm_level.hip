@@ -401,9 +401,12 @@ template <typename Op, typename T, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
                                                     int nblk_in, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
+    // flag and partial sums are loaded together; the block leaves after the
+    // reduction if its right-hand side is inactive (uniform in the block)
+    const bool act = rhs_active(active, b);
     double t[1];
     reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
+    if (!act) return;
     const double beta = sqrt(t[0]);
     const bool go = beta > 0.0;  // false for a zero or non-finite residual
     if (lead_thread()) {
@@ -435,18 +438,22 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
                                                     const int* active, int rpt) {
     const int b = blockIdx.z;
-    if (!rhs_active(active, b) || st[b].arnoldi_done) return;
+    // flag, state and partial sums are loaded together; the block leaves
+    // after the reduction if there is nothing to do (uniform in the block)
+    const bool act = rhs_active(active, b);
+    const int done = st[b].arnoldi_done;
+    const double s0 = st[b].s[0], beta0 = st[b].beta;
     constexpr int KIN = (J == 1) ? 2 : 5;  // previous pass: [||z_{J-1}||^2 (J > 1)], <z_i, w_{J-1}>
     double t[KIN];
     reduce_partials<KIN>(pin + b * kPartStride, nblk_in, t);
-    const GmState& S0 = st[b];
+    if (!act || done) return;
     double sv[J];  // s_0 .. s_{J-1}
-    sv[0] = S0.s[0];
+    sv[0] = s0;
     double hn = 0.0;
     bool broke = false;
     if (J > 1) {
         hn = sqrt(t[0]);
-        broke = !(hn > breakdown * S0.beta);
+        broke = !(hn > breakdown * beta0);
         sv[J - 1] = broke ? 0.0 : 1.0 / hn;
     }
     constexpr int D0 = (J > 1) ? 1 : 0;  // offset of the inner products in t
@@ -573,10 +580,10 @@ template <typename T, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, const GmState* st, double breakdown,
                                                    const double* pin, int nblk_in, const int* active, int rpt) {
     const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
+    const bool act = rhs_active(active, b);
     cplx<T> c[3];
     const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
-    if (k == 0) return;
+    if (!act || k == 0) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
@@ -624,9 +631,10 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u
                                                        const GmState* st, double breakdown, const double* pin,
                                                        int nblk_in, const int* active, int rpt) {
     const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
+    const bool act = rhs_active(active, b);
     cplx<T> c[3];
     const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
+    if (!act) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
