@@ -111,10 +111,10 @@ __device__ __forceinline__ double dnorm2(cplx<T> z) {
 
 // Stages 2-4 of a ProductOp apply, after the coarse tile (halo 3) is in LDS:
 // y = P x and v = C_s y on the block's fine region, then the restriction of v
-// at each coarse node, handed to f(i, j, p, x at p, A_1 x at p).
-template <typename T, bool kBez, typename F>
+// at each coarse node, handed to f(i, j, p, pget(p), x at p, A_1 x at p).
+template <typename T, bool kBez, typename PGet, typename F>
 __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, const Tile<3>& tl, cplx<T>* lds,
-                                               F&& f) {
+                                               PGet&& pget, F&& f) {
     using PS = ProductStages<T>;
     const int rows = tl.rows;
     cplx<T>* y = lds + Tile<3>::TW * (rows + 6);
@@ -156,28 +156,40 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
     }
     __syncthreads();
     // v = C_s y = A_s y - i beta2 W k^2 y on fine nodes of the grid, zero elsewhere
+    // k^2 of kVBatch fine nodes is loaded before their arithmetic (nodes off
+    // the fine grid read a clamped in-grid node and give zero)
+    constexpr int kVBatch = 8;
     const int nv = PS::VW * PS::vrows(rows);
-    for (int q = tid; q < nv; q += nt) {
-        const int a = q % PS::VW, bb = q / PS::VW;
-        const int fi = fx0 + 1 + a, fj = fy0 + 1 + bb;
-        cplx<T> r{T(0), T(0)};
-        if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
-            const int yi = (bb + 1) * PS::YW + a + 1;
-            const long long p = op.fine.g.at(fi, fj);
-            const cplx<T> yc = y[yi];
-            r = op.fine.apply5(fi, fj, p, yc, y[yi - 1], y[yi + 1], y[yi - PS::YW], y[yi + PS::YW]);
-            const T sw = op.shift * line_w<T>(fi, nf) * line_w<T>(fj, nf) * op.fine.k2[p];
-            r.re += sw * yc.im;
-            r.im -= sw * yc.re;
-        }
-        v[q] = r;
-    }
+    T kk[kVBatch];
+    for_strided_batched<kVBatch>(
+        nv,
+        [&](int u, int q) {
+            const int fi = fx0 + 1 + q % PS::VW, fj = fy0 + 1 + q / PS::VW;
+            kk[u] = op.fine.k2[op.fine.g.at(min(max(fi, 0), nf), min(max(fj, 0), nf))];
+        },
+        [&](int u, int q) {
+            const int a = q % PS::VW, bb = q / PS::VW;
+            const int fi = fx0 + 1 + a, fj = fy0 + 1 + bb;
+            cplx<T> r{T(0), T(0)};
+            if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
+                const int yi = (bb + 1) * PS::YW + a + 1;
+                const cplx<T> yc = y[yi];
+                r = op.fine.apply5k(fi, fj, kk[u], yc, y[yi - 1], y[yi + 1], y[yi - PS::YW], y[yi + PS::YW]);
+                const T sw = op.shift * line_w<T>(fi, nf) * line_w<T>(fj, nf) * kk[u];
+                r.re += sw * yc.im;
+                r.im -= sw * yc.re;
+            }
+            v[q] = r;
+        });
     __syncthreads();
     // (R v)_I = (1/4) sum of the prolongation weights of I times v
     const T m5[5] = {T(1), T(4), T(6), T(4), T(1)};
     const T m3[5] = {T(0), T(1), T(2), T(1), T(0)};
     const T scale = kBez ? T(1.0 / 256.0) : T(1.0 / 16.0);
-    for_nodes(op.g, (rows + blockDim.y - 1) / blockDim.y, [&](int i, int j, long long p) {
+    constexpr int NB = 2;
+    decltype(pget(0LL)) pv[NB];
+    for_nodes_batched<NB>(op.g, (rows + blockDim.y - 1) / blockDim.y, [&](int u, long long p) { pv[u] = pget(p); },
+                          [&](int u, int i, int j, long long p) {
         const int vc = (2 * (j - tl.r0) + 2) * PS::VW + 2 * (i - tl.c0) + 2;
         cplx<T> acc{T(0), T(0)};
 #pragma unroll
@@ -194,29 +206,48 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
             acc.re += w * row.re;
             acc.im += w * row.im;
         }
-        f(i, j, p, lds[tl.at(i, j)], scale * acc);
+        f(i, j, p, pv[u], lds[tl.at(i, j)], scale * acc);
     });
 }
 
-// Runs f(i, j, p, x at p, A x at p) over the thread's nodes, where x is given
-// by the element getter xget: x for the block tile plus halo is staged in LDS
-// first (one evaluation of the getter per tile node instead of one per
-// stencil entry), then the operator reads LDS only.
-template <typename Op, typename T, typename XGet, typename F>
-__device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& xget, F&& f) {
+// Runs f(i, j, p, pget(p), x at p, A x at p) over the thread's nodes, where
+// x = xmake(xload(p)) (xload only loads): x for the block tile plus halo is
+// staged in LDS first (one evaluation per tile node instead of one per
+// stencil entry), then the operator reads LDS only. pget loads the caller's
+// per-node operands; they and the operator's own (k^2 on level 0) are
+// loaded for a batch of rows before the batch's arithmetic.
+template <typename Op, typename T, typename XLoad, typename XMake, typename PGet, typename F>
+__device__ __forceinline__ void for_nodes_applied_pre(const Op& op, int rpt, XLoad&& xload, XMake&& xmake,
+                                                      PGet&& pget, F&& f) {
     constexpr int R = op_radius<Op>::value;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
     const Tile<R> tl = block_tile<R>(rpt);
-    fill_tile<T, R>(lds, tl, op.g, xget);
+    fill_tile<T, R>(lds, tl, op.g, xload, xmake);
     if constexpr (is_product<Op>::value) {
-        product_stages(op, tl, lds, f);
+        product_stages(op, tl, lds, pget, f);
     } else {
-        for_nodes(op.g, rpt, [&](int i, int j, long long p) {
-            const int li = tl.at(i, j);
-            if constexpr (is_stencil<Op>::value) f(i, j, p, lds[li], apply_tile(op, lds, li, p));
-            else f(i, j, p, lds[li], apply_tile(op, lds, li, i, j, p));
-        });
+        constexpr int NB = is_stencil<Op>::value ? 2 : (sizeof(T) == 4 ? 8 : 4);
+        decltype(pget(0LL)) pv[NB];
+        typename OpPre<Op>::type ov[NB];
+        for_nodes_batched<NB>(
+            op.g, rpt,
+            [&](int u, long long p) {
+                pv[u] = pget(p);
+                ov[u] = OpPre<Op>::load(op, p);
+            },
+            [&](int u, int i, int j, long long p) {
+                const int li = tl.at(i, j);
+                f(i, j, p, pv[u], lds[li], apply_tile_pre(op, lds, li, i, j, p, ov[u]));
+            });
     }
+}
+
+// for_nodes_applied_pre with x loaded as it is stored (xget(p) = x[p]) and
+// no per-node operands of the caller: f(i, j, p, x at p, A x at p).
+template <typename Op, typename T, typename XGet, typename F>
+__device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& xget, F&& f) {
+    for_nodes_applied_pre<Op, T>(op, rpt, xget, Ident{}, [](long long) { return NoVals{}; },
+                                 [&](int i, int j, long long p, NoVals, cplx<T> x, cplx<T> ax) { f(i, j, p, x, ax); });
 }
 
 // Dynamic LDS bytes of an operator kernel launched with geometry (by, rpt).
@@ -246,8 +277,9 @@ __global__ __launch_bounds__(kBX * BY) void k_residual(Op op, Vec<T> x, Vec<T> f
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* rb = r.rhs(b);
-    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
-                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { rb[p] = fb[p] - ax; });
+    for_nodes_applied_pre<Op, T>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
+                                 [fb](long long q) { return fb[q]; },
+                                 [&](int, int, long long p, cplx<T> fp, cplx<T>, cplx<T> ax) { rb[p] = fp - ax; });
 }
 
 // Weighted Jacobi of §3: y = x + (omega diag(A))^{-1} (f - A x).
@@ -259,9 +291,10 @@ __global__ __launch_bounds__(kBX * BY) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* yb = y.rhs(b);
-    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
-                             [&](int i, int j, long long p, cplx<T> xp, cplx<T> ax) {
-                                 const cplx<T> r = fb[p] - ax;
+    for_nodes_applied_pre<Op, T>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
+                                 [fb](long long q) { return fb[q]; },
+                                 [&](int i, int j, long long p, cplx<T> fp, cplx<T> xp, cplx<T> ax) {
+                                 const cplx<T> r = fp - ax;
                                  yb[p] = xp + inv_omega * cdiv(r, op.diag(i, j, p));
                              });
 }
@@ -332,6 +365,12 @@ __device__ __forceinline__ void taps(int i, bool bez, T (&w)[3]) {
     }
 }
 
+// The coarse values a block of fine nodes (columns [c0, c0 + 64), rows
+// [r0, r0 + rows), c0 and r0 even) reads: coarse columns c0/2 - 1 ..
+// c0/2 + 32 and rows r0/2 - 1 .. (r0 + rows - 1)/2 + 1, staged in LDS.
+constexpr int kProlongTW = kBX / 2 + 2;
+__host__ __device__ inline int prolong_rows(int rows) { return rows / 2 + 3; }
+
 template <typename T, bool kBez, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_prolong_add(Grid gc, Grid gf, Vec<T> e, Vec<T> u, const int* active,
                                                           int rpt) {
@@ -339,26 +378,50 @@ __global__ __launch_bounds__(kBX * BY) void k_prolong_add(Grid gc, Grid gf, Vec<
     if (!rhs_active(active, b)) return;
     const cplx<T>* eb = e.rhs(b);
     cplx<T>* ub = u.rhs(b);
-    for_nodes(gf, rpt, [&](int i, int j, long long pf) {
-        T wx[3], wy[3];
-        taps<T>(i, kBez, wx);
-        taps<T>(j, kBez, wy);
-        const long long pc = gc.at((i >> 1) - 1, (j >> 1) - 1);
-        cplx<T> acc{T(0), T(0)};
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const BlockXY bt = block_xy();
+    const int rows = BY * rpt;
+    const int C0 = bt.x * (kBX / 2) - 1, R0 = bt.y * (rows / 2) - 1;  // coarse origin of the LDS tile
+    const int ne = kProlongTW * prolong_rows(rows);
+    // coarse ghosts (index -1 and nc + 1) hold zero; indices beyond them read
+    // a clamped node and store zero
+    constexpr int kEBatch = 4;
+    cplx<T> ev[kEBatch];
+    bool ok[kEBatch];
+    for_strided_batched<kEBatch>(
+        ne,
+        [&](int v, int q) {
+            const int I = C0 + q % kProlongTW, J = R0 + q / kProlongTW;
+            const int Ic = min(I, gc.n + 1), Jc = min(J, gc.n + 1);
+            ok[v] = I == Ic && J == Jc;
+            ev[v] = eb[gc.at(Ic, Jc)];
+        },
+        [&](int v, int q) { lds[q] = ok[v] ? ev[v] : cplx<T>{T(0), T(0)}; });
+    __syncthreads();
+    constexpr int NB = 8;
+    cplx<T> uo[NB];
+    for_nodes_batched<NB>(
+        gf, rpt, [&](int v, long long pf) { uo[v] = ub[pf]; },
+        [&](int v, int i, int j, long long pf) {
+            T wx[3], wy[3];
+            taps<T>(i, kBez, wx);
+            taps<T>(j, kBez, wy);
+            const int base = ((j >> 1) - 1 - R0) * kProlongTW + (i >> 1) - 1 - C0;
+            cplx<T> acc{T(0), T(0)};
 #pragma unroll
-        for (int ty = 0; ty < 3; ++ty) {
-            cplx<T> row{T(0), T(0)};
+            for (int ty = 0; ty < 3; ++ty) {
+                cplx<T> row{T(0), T(0)};
 #pragma unroll
-            for (int tx = 0; tx < 3; ++tx) {
-                const cplx<T> v = eb[pc + (long long)ty * gc.pitch + tx];
-                row.re += wx[tx] * v.re;
-                row.im += wx[tx] * v.im;
+                for (int tx = 0; tx < 3; ++tx) {
+                    const cplx<T> x = lds[base + ty * kProlongTW + tx];
+                    row.re += wx[tx] * x.re;
+                    row.im += wx[tx] * x.im;
+                }
+                acc.re += wy[ty] * row.re;
+                acc.im += wy[ty] * row.im;
             }
-            acc.re += wy[ty] * row.re;
-            acc.im += wy[ty] * row.im;
-        }
-        ub[pf] = ub[pf] + acc;
-    });
+            ub[pf] = uo[v] + acc;
+        });
 }
 
 // ---------------------------------------------------------------- GMRES(3)
@@ -387,9 +450,10 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Ve
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     double acc[1] = {0.0};
-    for_nodes_applied<Op, T>(op, rpt, [ub](long long q) { return ub[q]; },
-                             [&](int, int, long long p, cplx<T>, cplx<T> au) {
-                                 const cplx<T> z = fb[p] - au;
+    for_nodes_applied_pre<Op, T>(op, rpt, [ub](long long q) { return ub[q]; }, Ident{},
+                                 [fb](long long q) { return fb[q]; },
+                                 [&](int, int, long long p, cplx<T> fp, cplx<T>, cplx<T> au) {
+                                 const cplx<T> z = fp - au;
                                  z0[p] = z;
                                  acc[0] += dnorm2(z);
                              });
@@ -494,11 +558,19 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     cplx<T>* zJ = Z.p + (long long)(b * 4 + J) * Z.plane;
     const cplx<T>* wi = Win.rhs(b);
     cplx<T>* wo = Wout.rhs(b);
-    auto znew = [&](long long q) {
-        cplx<T> v = sJ1 * wi[q];
+    // z_J at a tile node from w_{J-1} (v[0]) and z_0 .. z_{J-1} (v[1..J])
+    auto zload = [&](long long q) {
+        Vals<T, J + 1> o;
+        o.v[0] = wi[q];
+#pragma unroll
+        for (int a = 0; a < J; ++a) o.v[1 + a] = z[a][q];
+        return o;
+    };
+    auto zmake = [&](const Vals<T, J + 1>& o) {
+        cplx<T> v = sJ1 * o.v[0];
 #pragma unroll
         for (int a = 0; a < J; ++a) {
-            const cplx<T> zq = z[a][q];
+            const cplx<T> zq = o.v[1 + a];
             v.re -= c[a].re * zq.re - c[a].im * zq.im;
             v.im -= c[a].re * zq.im + c[a].im * zq.re;
         }
@@ -508,12 +580,19 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     double acc[KOUT];
 #pragma unroll
     for (int q = 0; q < KOUT; ++q) acc[q] = 0.0;
-    for_nodes_applied<Op, T>(op, rpt, znew, [&](int, int, long long p, cplx<T> zp, cplx<T> w) {
+    auto zold = [&](long long q) {
+        Vals<T, J> o;
+#pragma unroll
+        for (int a = 0; a < J; ++a) o.v[a] = z[a][q];
+        return o;
+    };
+    for_nodes_applied_pre<Op, T>(op, rpt, zload, zmake, zold, [&](int, int, long long p, const Vals<T, J>& zo, cplx<T> zp,
+                                                         cplx<T> w) {
         zJ[p] = zp;
         wo[p] = w;
         acc[0] += dnorm2(zp);
 #pragma unroll
-        for (int q = 0; q < J; ++q) acc_dot(acc[1 + 2 * q], acc[2 + 2 * q], z[q][p], w);
+        for (int q = 0; q < J; ++q) acc_dot(acc[1 + 2 * q], acc[2 + 2 * q], zo.v[q], w);
         acc_dot(acc[1 + 2 * J], acc[2 + 2 * J], zp, w);
         if constexpr (J == 2) acc[KOUT - 1] += dnorm2(w);
     });
@@ -588,39 +667,22 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, c
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
     cplx<T>* ub = u.rhs(b);
-    // rows software-pipelined: the loads of row rr + 1 are issued before the
-    // store of row rr
-    const int i = blockIdx.x * kBX + threadIdx.x;
-    if (i > g.n) return;
-    const int by = blockDim.y;
-    int j = blockIdx.y * rpt * by + threadIdx.y;
-    const int jend = min(g.n + 1, (blockIdx.y + 1) * rpt * by);
-    if (j >= jend) return;
-    long long p = g.at(i, j);
-    const long long step = (long long)by * g.pitch;
-    cplx<T> xu = ub[p], x0 = z0[p], x1 = z1[p], x2 = z2[p];
-    for (;;) {
-        const int jn = j + by;
-        const bool more = jn < jend;
-        cplx<T> nu{}, n0{}, n1{}, n2{};
-        if (more) {
-            nu = ub[p + step];
-            n0 = z0[p + step];
-            n1 = z1[p + step];
-            n2 = z2[p + step];
-        }
-        cplx<T> x = cfma(xu, c[0], x0);
-        if (k > 1) x = cfma(x, c[1], x1);
-        if (k > 2) x = cfma(x, c[2], x2);
-        ub[p] = x;
-        if (!more) break;
-        j = jn;
-        p += step;
-        xu = nu;
-        x0 = n0;
-        x1 = n1;
-        x2 = n2;
-    }
+    constexpr int NB = sizeof(T) == 4 ? 8 : 4;
+    cplx<T> xu[NB], x0[NB], x1[NB], x2[NB];
+    for_nodes_batched<NB>(
+        g, rpt,
+        [&](int v, long long p) {
+            xu[v] = ub[p];
+            x0[v] = z0[p];
+            x1[v] = z1[p];
+            x2[v] = z2[p];
+        },
+        [&](int v, int, int, long long p) {
+            cplx<T> x = cfma(xu[v], c[0], x0[v]);
+            if (k > 1) x = cfma(x, c[1], x1[v]);
+            if (k > 2) x = cfma(x, c[2], x2[v]);
+            ub[p] = x;
+        });
 }
 
 // Pass 5 fused with the residual that follows the last pre-smoothing step:
@@ -642,17 +704,20 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u
     const cplx<T>* fb = f.rhs(b);
     cplx<T>* nb = unew.rhs(b);
     cplx<T>* rb = r.rhs(b);
-    auto getu = [&](long long q) {
-        cplx<T> x = ub[q];
-        if (k > 0) x = cfma(x, c[0], z0[q]);
-        if (k > 1) x = cfma(x, c[1], z1[q]);
-        if (k > 2) x = cfma(x, c[2], z2[q]);
+    // u_new at a tile node from u (v[0]) and z_0 .. z_2 (v[1..3])
+    auto uload = [&](long long q) { return Vals<T, 4>{{ub[q], z0[q], z1[q], z2[q]}}; };
+    auto umake = [&](const Vals<T, 4>& o) {
+        cplx<T> x = o.v[0];
+        if (k > 0) x = cfma(x, c[0], o.v[1]);
+        if (k > 1) x = cfma(x, c[1], o.v[2]);
+        if (k > 2) x = cfma(x, c[2], o.v[3]);
         return x;
     };
-    for_nodes_applied<Op, T>(op, rpt, getu, [&](int, int, long long p, cplx<T> up, cplx<T> au) {
-        nb[p] = up;
-        rb[p] = fb[p] - au;
-    });
+    for_nodes_applied_pre<Op, T>(op, rpt, uload, umake, [fb](long long q) { return fb[q]; },
+                                 [&](int, int, long long p, cplx<T> fp, cplx<T> up, cplx<T> au) {
+                                     nb[p] = up;
+                                     rb[p] = fp - au;
+                                 });
 }
 
 // Sums the nblk partial rows of a region into row 0 (same thread count and
@@ -678,8 +743,11 @@ __global__ __launch_bounds__(kBX * BY) void k_resnorm(Op op, Vec<T> x, Vec<T> f,
     const cplx<T>* xb = x.rhs(b);
     const cplx<T>* fb = f.rhs(b);
     double acc[1] = {0.0};
-    for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
-                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { acc[0] += dnorm2(fb[p] - ax); });
+    for_nodes_applied_pre<Op, T>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
+                                 [fb](long long q) { return fb[q]; },
+                                 [&](int, int, long long p, cplx<T> fp, cplx<T>, cplx<T> ax) {
+                                     acc[0] += dnorm2(fp - ax);
+                                 });
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
@@ -718,9 +786,11 @@ __global__ __launch_bounds__(kBX * BY) void k_refine_residual(FineOp<double> op,
     const cplx<double>* fb = f.rhs(b);
     cplx<float>* rb = r32.rhs(b);
     double acc[1] = {0.0};
-    for_nodes_applied<FineOp<double>, double>(op, rpt, [xb](long long q) { return xb[q]; },
-                                              [&](int, int, long long p, cplx<double>, cplx<double> ax) {
-                                                  const cplx<double> r = fb[p] - ax;
+    for_nodes_applied_pre<FineOp<double>, double>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
+                                                  [fb](long long q) { return fb[q]; },
+                                                  [&](int, int, long long p, cplx<double> fp, cplx<double>,
+                                                      cplx<double> ax) {
+                                                  const cplx<double> r = fp - ax;
                                                   rb[p] = cast<float>(r);
                                                   acc[0] += dnorm2(r);
                                               });
@@ -739,11 +809,17 @@ __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op
     const cplx<double>* fb = f.rhs(b);
     cplx<float>* rb = r32.rhs(b);
     double acc[1] = {0.0};
-    auto xnew = [xb, eb](long long q) { return xb[q] + cast<double>(eb[q]); };
-    for_nodes_applied<FineOp<double>, double>(op, rpt, xnew,
-                                              [&](int, int, long long p, cplx<double> xp, cplx<double> ax) {
+    struct XE {
+        cplx<double> x;
+        cplx<float> e;
+    };
+    auto xload = [xb, eb](long long q) { return XE{xb[q], eb[q]}; };
+    auto xmake = [](const XE& v) { return v.x + cast<double>(v.e); };
+    for_nodes_applied_pre<FineOp<double>, double>(op, rpt, xload, xmake, [fb](long long q) { return fb[q]; },
+                                                  [&](int, int, long long p, cplx<double> fp, cplx<double> xp,
+                                                      cplx<double> ax) {
                                                   ob[p] = xp;
-                                                  const cplx<double> r = fb[p] - ax;
+                                                  const cplx<double> r = fp - ax;
                                                   rb[p] = cast<float>(r);
                                                   acc[0] += dnorm2(r);
                                               });
@@ -868,8 +944,16 @@ void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer,
 template <typename T>
 void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u) {
     const Geom q = geom(fine, false, ctx.nrhs, ctx.block_cap);
-    if (transfer == 0) HM_LAUNCH(q, (k_prolong_add<T, true, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
-    else HM_LAUNCH(q, (k_prolong_add<T, false, BY>), coarse, fine, e, u, HM_ACTIVE, q.rpt);
+    const size_t shm = size_t(kProlongTW) * prolong_rows(q.by * q.rpt) * sizeof(cplx<T>);
+    with_by(q.by, [&](auto byc) {
+        constexpr int BY = decltype(byc)::value;
+        if (transfer == 0)
+            hipLaunchKernelGGL((k_prolong_add<T, true, BY>), q.grid, q.block, shm, ctx.stream, coarse, fine, e, u,
+                               HM_ACTIVE, q.rpt);
+        else
+            hipLaunchKernelGGL((k_prolong_add<T, false, BY>), q.grid, q.block, shm, ctx.stream, coarse, fine, e, u,
+                               HM_ACTIVE, q.rpt);
+    });
 }
 
 double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }

@@ -22,25 +22,31 @@ struct FineOp {
     const T* k2;
     T ih2;    // 1 / h^2
     T two_h;  // 2 / h
-    __device__ __forceinline__ cplx<T> diag(int i, int j, long long p) const {
+    // diagonal at node (i, j) with k^2 = kk there
+    __device__ __forceinline__ cplx<T> diag_k(int i, int j, T kk) const {
         const int n = g.n;
         const T W = line_w<T>(i, n) * line_w<T>(j, n);
         const int s = (i == 0 || i == n) + (j == 0 || j == n);
-        const T kk = k2[p];
         T im = T(0);
         if (s) im = -two_h * T(s) * sqrt(kk);
         return {W * (T(4) * ih2 - kk), W * im};
     }
-    // (A_s x)_p from the centre value and the west, east, south, north neighbours
-    __device__ __forceinline__ cplx<T> apply5(int i, int j, long long p, cplx<T> c, cplx<T> xw, cplx<T> xe,
-                                              cplx<T> xs, cplx<T> xn) const {
+    __device__ __forceinline__ cplx<T> diag(int i, int j, long long p) const { return diag_k(i, j, k2[p]); }
+    // (A_s x)_p from k^2 at p, the centre value and the west, east, south,
+    // north neighbours
+    __device__ __forceinline__ cplx<T> apply5k(int i, int j, T kk, cplx<T> c, cplx<T> xw, cplx<T> xe, cplx<T> xs,
+                                               cplx<T> xn) const {
         const int n = g.n;
-        const cplx<T> d = diag(i, j, p);
+        const cplx<T> d = diag_k(i, j, kk);
         const T cx = ih2 * line_w<T>(j, n), cy = ih2 * line_w<T>(i, n);
         cplx<T> y = d * c;
         y.re -= cx * (xw.re + xe.re) + cy * (xs.re + xn.re);
         y.im -= cx * (xw.im + xe.im) + cy * (xs.im + xn.im);
         return y;
+    }
+    __device__ __forceinline__ cplx<T> apply5(int i, int j, long long p, cplx<T> c, cplx<T> xw, cplx<T> xe,
+                                              cplx<T> xs, cplx<T> xn) const {
+        return apply5k(i, j, k2[p], c, xw, xe, xs, xn);
     }
     template <typename X>
     __device__ __forceinline__ cplx<T> apply_at(const X& x, int i, int j, long long p) const {
@@ -92,17 +98,95 @@ struct ProductOp {
     __device__ __forceinline__ cplx<T> diag(int, int, long long p) const { return diagc[p]; }
 };
 
-// Calls f(i, j, p) for the nodes of this thread: column blockIdx.x * 64 + lane,
-// rows interleaved by 4 over rows_per_thread consecutive row groups.
+// Tile (column block, row block) of this workgroup. Workgroups are handed to
+// the 8 XCDs round-robin in linear-id order and each XCD has its own L2; the
+// map gives the workgroups of one XCD a contiguous run of tiles in row-major
+// order, so that the halo cache lines neighbouring tiles share are fetched
+// into one L2 instead of two. A bijection of the (x, y) block grid for every
+// right-hand side z, so correctness does not depend on the dispatch order.
+constexpr unsigned kXcds = 8;
+struct BlockXY {
+    int x, y;
+};
+__device__ __forceinline__ BlockXY block_xy() {
+    const unsigned gx = gridDim.x, nb = gx * gridDim.y;
+    const unsigned l = blockIdx.y * gx + blockIdx.x;
+    const unsigned off = (blockIdx.z * nb) % kXcds;  // XCD of local id 0
+    const unsigned c = (l + off) % kXcds;            // XCD of this workgroup
+    unsigned t = l / kXcds;                          // rank among the ids of XCD c
+    for (unsigned x = 0; x < c; ++x) {               // ids of the XCDs before c
+        const unsigned s = (x + kXcds - off) % kXcds;
+        if (s < nb) t += (nb - 1 - s) / kXcds + 1;
+    }
+    return BlockXY{int(t % gx), int(t / gx)};
+}
+
+// Calls f(i, j, p) for the nodes of this thread: column bx * 64 + lane,
+// rows interleaved by 4 over rows_per_thread consecutive row groups of row
+// block by ((bx, by) = block_xy()).
 template <typename F>
 __device__ __forceinline__ void for_nodes(const Grid& g, int rpt, F&& f) {
-    const int i = blockIdx.x * kBX + threadIdx.x;
+    const BlockXY bt = block_xy();
+    const int i = bt.x * kBX + threadIdx.x;
     if (i > g.n) return;
     const int by = blockDim.y;
     for (int rr = 0; rr < rpt; ++rr) {
-        const int j = (blockIdx.y * rpt + rr) * by + threadIdx.y;
+        const int j = (bt.y * rpt + rr) * by + threadIdx.y;
         if (j > g.n) return;
         f(i, j, g.at(i, j));
+    }
+}
+
+// Waits until every vector memory operation the wave has issued is done
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt fields at their no-wait maxima).
+// Placed after a sweep of loads so that the stores of the following
+// arithmetic do not make the compiler wait for them row by row.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// The nodes of for_nodes, taken NB rows at a time in two sweeps: load(u, p)
+// for the rows of the batch first, then body(u, i, j, p) for the rows that
+// exist. The loads of a batch are in flight together: one memory round trip
+// per batch instead of one per row. Only the row count decides which loads
+// are issued (uniform in the block, so no divergent branch separates them);
+// a row below the grid loads its column's last node instead.
+template <int NB, typename Load, typename Body>
+__device__ __forceinline__ void for_nodes_batched(const Grid& g, int rpt, Load&& load, Body&& body) {
+    const BlockXY bt = block_xy();
+    const int i = bt.x * kBX + threadIdx.x;
+    if (i > g.n) return;
+    const int by = blockDim.y;
+    const int j0 = bt.y * rpt * by + threadIdx.y;
+    if (j0 > g.n) return;
+    for (int rr0 = 0; rr0 < rpt; rr0 += NB) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            if (rr0 + u < rpt) load(u, g.at(i, min(j0 + (rr0 + u) * by, g.n)));
+        wait_vmem();
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = j0 + (rr0 + u) * by;
+            if (rr0 + u < rpt && j <= g.n) body(u, i, j, g.at(i, j));
+        }
+    }
+}
+
+// Indices q = tid, tid + nt, ... < count of a block-strided loop, NB at a
+// time in two sweeps as in for_nodes_batched: load(u, q) (q clamped to
+// count - 1 in the last, partly filled stride; strides beyond it are not
+// loaded), then body(u, q) for the indices that exist.
+template <int NB, typename Load, typename Body>
+__device__ __forceinline__ void for_strided_batched(int count, Load&& load, Body&& body) {
+    const int nt = blockDim.x * blockDim.y;
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    for (int s0 = 0; s0 < count; s0 += NB * nt) {  // uniform: first index of the round
+        const int q0 = s0 + tid;
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            if (s0 + u * nt < count) load(u, min(q0 + u * nt, count - 1));
+        wait_vmem();
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            if (q0 + u * nt < count) body(u, q0 + u * nt);
     }
 }
 
@@ -122,34 +206,40 @@ struct Tile {
 
 template <int R>
 __device__ __forceinline__ Tile<R> block_tile(int rpt) {
-    return Tile<R>{int(blockIdx.x) * kBX, int(blockIdx.y) * int(blockDim.y) * rpt, int(blockDim.y) * rpt};
+    const BlockXY bt = block_xy();
+    return Tile<R>{bt.x * kBX, bt.y * int(blockDim.y) * rpt, int(blockDim.y) * rpt};
 }
 
-// lds[t.at(i, j)] = get(g.at(i, j)) for every tile node inside the padded
-// frame (ghosts read as stored, zero); nodes beyond it hold zero and are
-// never used by an in-domain stencil. Each thread gathers up to kFillBatch
-// values before storing any, so that their loads are in flight together.
-constexpr int kFillBatch = 8;
-template <typename T, int R, typename Get>
-__device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const Grid& g, Get&& get) {
-    const int total = t.count();
-    const int nt = blockDim.x * blockDim.y;
-    for (int q0 = threadIdx.y * kBX + threadIdx.x; q0 < total; q0 += kFillBatch * nt) {
-        cplx<T> v[kFillBatch];
-#pragma unroll
-        for (int u = 0; u < kFillBatch; ++u) {
-            const int q = q0 + u * nt;
+// lds[t.at(i, j)] = make(load(g.at(i, j))) for every tile node inside the
+// padded frame (ghosts read as stored, zero); nodes beyond it hold zero and
+// are never used by an in-domain stencil. load only gathers the values that
+// make combines: the loads of FillBatch<T> nodes are issued before any
+// combination (a node outside the frame is clamped onto it, R <= kGhost, and
+// gives zero), so that they are in flight together.
+template <typename T>
+struct FillBatch {
+    static constexpr int value = sizeof(T) == 4 ? 8 : 4;  // register budget of FP64 tiles
+};
+struct Ident {
+    template <typename X>
+    __device__ __forceinline__ X operator()(const X& x) const { return x; }
+};
+template <typename T, int R, typename Load, typename Make>
+__device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const Grid& g, Load&& load, Make&& make) {
+    static_assert(R <= kGhost, "tile halo beyond the stored ghost layers");
+    constexpr int FB = FillBatch<T>::value;
+    decltype(load(0LL)) v[FB];
+    bool ok[FB];
+    for_strided_batched<FB>(
+        t.count(),
+        [&](int u, int q) {
             const int i = t.c0 - R + q % Tile<R>::TW;
             const int j = t.r0 - R + q / Tile<R>::TW;
-            v[u] = cplx<T>{T(0), T(0)};
-            if (q < total && i >= -R && j >= -R && i <= g.n + R && j <= g.n + R) v[u] = get(g.at(i, j));
-        }
-#pragma unroll
-        for (int u = 0; u < kFillBatch; ++u) {
-            const int q = q0 + u * nt;
-            if (q < total) lds[q] = v[u];
-        }
-    }
+            const int ic = min(max(i, -R), g.n + R), jc = min(max(j, -R), g.n + R);
+            ok[u] = i == ic && j == jc;
+            v[u] = load(g.at(ic, jc));
+        },
+        [&](int u, int q) { lds[q] = ok[u] ? make(v[u]) : cplx<T>{T(0), T(0)}; });
     __syncthreads();
 }
 
@@ -167,12 +257,40 @@ __device__ __forceinline__ cplx<T> apply_tile(const StencilOp<T, R>& op, const c
     return y;
 }
 
-// Level-0 operator applied at tile index li from LDS.
+// Level-0 operator applied at tile index li from LDS, with k^2 at p given.
 template <typename T>
-__device__ __forceinline__ cplx<T> apply_tile(const FineOp<T>& op, const cplx<T>* lds, int li, int i, int j,
-                                              long long p) {
+__device__ __forceinline__ cplx<T> apply_tile(const FineOp<T>& op, const cplx<T>* lds, int li, int i, int j, T kk) {
     constexpr int TW = Tile<1>::TW;
-    return op.apply5(i, j, p, lds[li], lds[li - 1], lds[li + 1], lds[li - TW], lds[li + TW]);
+    return op.apply5k(i, j, kk, lds[li], lds[li - 1], lds[li + 1], lds[li - TW], lds[li + TW]);
+}
+
+// Per-node operand of an operator that a batched sweep loads ahead of the
+// arithmetic: k^2 for the level-0 operator; nothing for stored stencils,
+// whose coefficient loads stay in the apply (one row per thread there).
+struct NoVals {};
+template <typename T, int N>
+struct Vals {
+    cplx<T> v[N];
+};
+template <typename Op>
+struct OpPre {
+    using type = NoVals;
+    __device__ __forceinline__ static NoVals load(const Op&, long long) { return {}; }
+};
+template <typename T>
+struct OpPre<FineOp<T>> {
+    using type = T;
+    __device__ __forceinline__ static T load(const FineOp<T>& op, long long p) { return op.k2[p]; }
+};
+template <typename T, int R>
+__device__ __forceinline__ cplx<T> apply_tile_pre(const StencilOp<T, R>& op, const cplx<T>* lds, int li, int,
+                                                  int, long long p, NoVals) {
+    return apply_tile(op, lds, li, p);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> apply_tile_pre(const FineOp<T>& op, const cplx<T>* lds, int li, int i, int j,
+                                                  long long, T kk) {
+    return apply_tile(op, lds, li, i, j, kk);
 }
 
 template <typename Op>
@@ -230,7 +348,13 @@ __device__ __forceinline__ bool rhs_active(const int* active, int b) { return ac
 // partials of right-hand side b and region r live at
 // partials + (r * nrhs_cap + b) * kPartStride.
 
-__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+// Row-major index of this block's tile (block_xy), the slot of its partial
+// sums: the summation order then follows the tiles, not the hardware block
+// ids, so a right-hand side gets the same sums alone and in a batch.
+__device__ __forceinline__ int block_linear() {
+    const BlockXY bt = block_xy();
+    return bt.y * int(gridDim.x) + bt.x;
+}
 __device__ __forceinline__ int thread_linear() { return threadIdx.y * kBX + threadIdx.x; }
 
 // Block sum for 64 x BY thread blocks, BY <= kMaxBY (wavefront = threadIdx.y).
