@@ -44,7 +44,12 @@ KERNEL_CLASSES = {
 # TRAFFIC_SOURCES, and a different hash reports traffic as null.
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
-MEASURED_TRAFFIC = None  # {"sources_sha256": ..., "fetch_bytes": ..., "write_bytes": ..., "profile": ...}
+MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
+    "sources_sha256": "d62780c8f8ff91e8f6c0fec267d4ee2035a653ba00737b6835998c2d5a9de55c",
+    "fetch_bytes": 31341126,  # FETCH_SIZE x 1.9998 (copy-calibrated)
+    "write_bytes": 16903745,  # WRITE_SIZE x 1.0000
+    "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
+}
 
 
 def sources_sha256():
