@@ -45,9 +45,9 @@ KERNEL_CLASSES = {
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
-    "sources_sha256": "d62780c8f8ff91e8f6c0fec267d4ee2035a653ba00737b6835998c2d5a9de55c",
-    "fetch_bytes": 31341126,  # FETCH_SIZE x 1.9998 (copy-calibrated)
-    "write_bytes": 16903745,  # WRITE_SIZE x 1.0000
+    "sources_sha256": "7312d4a0b593bfc79194ef1ac9126afbe3adebec5fb0c6e1d09676338a6fcd56",
+    "fetch_bytes": 50318368,  # FETCH_SIZE x 1.9998 (copy-calibrated)
+    "write_bytes": 16899616,  # WRITE_SIZE x 1.0000
     "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
 }
 
@@ -75,7 +75,7 @@ def parse():
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (mg_tune) on the FP32-refined cycle before timing")
-    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres"], default="mp2a",
+    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres", "media2048"], default="mp2a",
                     help="mp2a: the headline n=1024 solve (default); batch64: 64 sources on n=512 in one "
                          "batched solve; mixed32: 32 problems n=128..1024 solved together")
     return ap.parse_args()
@@ -208,6 +208,61 @@ def fgmres_workload(args):
     print(json.dumps(out))
 
 
+def media_workload(args):
+    """n = 2048 (4,198,401 unknowns) in the seeded three-layer wedge and the
+    Gaussian random velocity (MP 2-B stand-ins), max kh = 0.3, source near
+    the top centre, shift 1/max(k), GMRES(3) V(1,1), tol 1e-6: FP32-refined
+    and FP64 solves per medium, hierarchy set up beforehand (timed apart)."""
+    import numpy as np
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    n = 2048
+    res = {}
+    dof_cycles, secs = 0.0, 0.0
+    for medium in ["wedge", "grf"]:
+        c = W.wedge_velocity(n, 3) if medium == "wedge" else W.grf_velocity(n, 3)
+        k2 = W.k2_from_velocity(c, 0.3)
+        kmax = float(np.sqrt(k2.max()))
+        f = torch.from_numpy(W.point_source_rhs(n, [(n // 2, int(round(0.9 * n)))])).to(dev)
+        k2d = torch.from_numpy(k2).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = Solver(k2d, 1.0 / n, 1.0 / kmax, precision="fp32_refined")
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        row = {"k_max": kmax, "setup_ms": setup_ms}
+        for prec in ["fp32_refined", "fp64"]:
+            for _ in range(args.warmup):
+                S.solve(f, tol=1e-6, precision=prec, max_cycles=800)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, info = S.solve(f, tol=1e-6, precision=prec, max_cycles=800)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            row[prec] = {"ms": dt * 1e3, "cycles": info["cycles"][0], "relres": info["relres"][0],
+                         "ms_per_cycle": dt * 1e3 / info["cycles"][0]}
+            if prec == "fp32_refined":
+                dof_cycles += (n + 1) ** 2 * info["cycles"][0]
+                secs += dt
+        res[medium] = row
+        del S
+        torch.cuda.empty_cache()
+    out = {"metric": "V-cycle DOF/s to rel.res 1e-6, FP32-refined (both media)", "value": dof_cycles / secs,
+           "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64 cycle in c128 refinement", "data": "synthetic",
+           "config": {"workload": "n=2048 wedge and Gaussian random velocity (seed 3), max kh 0.3, source "
+                                  "(n/2, round(0.9n)), shift 1/k_max, GMRES(3) V(1,1), Bezier, coarsest 4x4, "
+                                  "tol 1e-6, setup excluded", "n": n},
+           "media": res, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -215,6 +270,9 @@ def main():
         sys.exit(2)
     if args.workload == "fgmres":
         fgmres_workload(args)
+        return
+    if args.workload == "media2048":
+        media_workload(args)
         return
     if args.workload != "mp2a":
         batch_workloads(args)

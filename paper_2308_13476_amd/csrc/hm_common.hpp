@@ -45,18 +45,23 @@ __device__ __forceinline__ cplx<T> cast(cplx<U> a) { return {T(a.re), T(a.im)}; 
 
 // Ghost frame of every level grid: zero-valued nodes around the domain so
 // that stencils of radius <= 3 and the transfer masks (radius 2) read
-// without branches. Four nodes keep the first interior node 64-byte aligned
-// for complex128.
+// without branches: kGhost rows below and above, kGhost columns on the
+// right and kGhostX on the left. kGhostX = 32 and a pitch that is a multiple
+// of 32 values put node (0, j) at the start of a 128-byte line for every
+// element size used (4-byte k^2 to 16-byte complex128), so the 64 nodes of a
+// wavefront's row segment fill whole lines instead of straddling one more.
 constexpr int kGhost = 4;
+constexpr int kGhostX = 32;
+constexpr int kPitchAlign = 32;
 
 // One level of the hierarchy in the padded layout: node (i, j), 0 <= i, j <= n,
-// lives at (j + kGhost) * pitch + (i + kGhost) of a plane of `plane` values.
+// lives at (j + kGhost) * pitch + (i + kGhostX) of a plane of `plane` values.
 struct Grid {
     int n;          // intervals per side
     int pitch;      // values per padded row
     long long plane;  // values per padded plane
     __host__ __device__ __forceinline__ long long at(int i, int j) const {
-        return (long long)(j + kGhost) * pitch + (i + kGhost);
+        return (long long)(j + kGhost) * pitch + (i + kGhostX);
     }
 };
 

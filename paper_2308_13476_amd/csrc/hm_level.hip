@@ -226,7 +226,9 @@ __device__ __forceinline__ void for_nodes_applied_pre(const Op& op, int rpt, XLo
     if constexpr (is_product<Op>::value) {
         product_stages(op, tl, lds, pget, f);
     } else {
-        constexpr int NB = is_stencil<Op>::value ? 2 : (sizeof(T) == 4 ? 8 : 4);
+        // rows per batch: stored stencils keep one row per thread on most
+        // levels and their FP64 coefficient batches need the registers
+        constexpr int NB = is_stencil<Op>::value ? (sizeof(T) == 4 ? 2 : 1) : (sizeof(T) == 4 ? 8 : 4);
         decltype(pget(0LL)) pv[NB];
         typename OpPre<Op>::type ov[NB];
         for_nodes_batched<NB>(

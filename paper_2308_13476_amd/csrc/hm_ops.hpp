@@ -98,28 +98,13 @@ struct ProductOp {
     __device__ __forceinline__ cplx<T> diag(int, int, long long p) const { return diagc[p]; }
 };
 
-// Tile (column block, row block) of this workgroup. Workgroups are handed to
-// the 8 XCDs round-robin in linear-id order and each XCD has its own L2; the
-// map gives the workgroups of one XCD a contiguous run of tiles in row-major
-// order, so that the halo cache lines neighbouring tiles share are fetched
-// into one L2 instead of two. A bijection of the (x, y) block grid for every
-// right-hand side z, so correctness does not depend on the dispatch order.
-constexpr unsigned kXcds = 8;
+// Tile (column block, row block) of this workgroup: blockIdx.x, blockIdx.y.
+// (A map that gave each XCD a contiguous run of tiles cut the halo re-reads
+// between L2s but made the cycle slower, so tiles follow the block ids.)
 struct BlockXY {
     int x, y;
 };
-__device__ __forceinline__ BlockXY block_xy() {
-    const unsigned gx = gridDim.x, nb = gx * gridDim.y;
-    const unsigned l = blockIdx.y * gx + blockIdx.x;
-    const unsigned off = (blockIdx.z * nb) % kXcds;  // XCD of local id 0
-    const unsigned c = (l + off) % kXcds;            // XCD of this workgroup
-    unsigned t = l / kXcds;                          // rank among the ids of XCD c
-    for (unsigned x = 0; x < c; ++x) {               // ids of the XCDs before c
-        const unsigned s = (x + kXcds - off) % kXcds;
-        if (s < nb) t += (nb - 1 - s) / kXcds + 1;
-    }
-    return BlockXY{int(t % gx), int(t / gx)};
-}
+__device__ __forceinline__ BlockXY block_xy() { return BlockXY{int(blockIdx.x), int(blockIdx.y)}; }
 
 // Calls f(i, j, p) for the nodes of this thread: column bx * 64 + lane,
 // rows interleaved by 4 over rows_per_thread consecutive row groups of row
@@ -348,9 +333,7 @@ __device__ __forceinline__ bool rhs_active(const int* active, int b) { return ac
 // partials of right-hand side b and region r live at
 // partials + (r * nrhs_cap + b) * kPartStride.
 
-// Row-major index of this block's tile (block_xy), the slot of its partial
-// sums: the summation order then follows the tiles, not the hardware block
-// ids, so a right-hand side gets the same sums alone and in a batch.
+// Row-major index of this block's tile, the slot of its partial sums.
 __device__ __forceinline__ int block_linear() {
     const BlockXY bt = block_xy();
     return bt.y * int(gridDim.x) + bt.x;

@@ -32,7 +32,7 @@ Grid make_grid(int n) {
     Grid g;
     g.n = n;
     const int m = n + 1;
-    g.pitch = int(align_up(size_t(m + 2 * kGhost), 16));
+    g.pitch = int(align_up(size_t(kGhostX + m + kGhost), kPitchAlign));
     g.plane = (long long)align_up(size_t(g.pitch) * size_t(m + 2 * kGhost), 64);
     return g;
 }
