@@ -75,7 +75,7 @@ def parse():
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (mg_tune) on the FP32-refined cycle before timing")
-    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres", "media2048"], default="mp2a",
+    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres", "media2048", "mp2b"], default="mp2a",
                     help="mp2a: the headline n=1024 solve (default); batch64: 64 sources on n=512 in one "
                          "batched solve; mixed32: 32 problems n=128..1024 solved together")
     return ap.parse_args()
@@ -263,6 +263,46 @@ def media_workload(args):
     print(json.dumps(out))
 
 
+def mp2b_workload(args):
+    """MP 2-B high variation (§5.3.2, Table 9): k = 10 + 65 χ with the seeded
+    node-by-node random χ on n = 120 (max(k) h = 0.625, coarsest 15
+    intervals), shift 1/75, GMRES(3) V(nu,nu) and W(nu,nu) for nu = 1..5,
+    FP64, tol 1e-5: time to tolerance per solve, hierarchy set up beforehand."""
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    k1, k2 = 10.0, 75.0
+    n = W.mp2b_grid(k2)
+    S = Solver(torch.from_numpy(W.k2_from_chi(W.chi_sharp(n, 6), k1, k2)).to(dev), 1.0 / n, 1.0 / k2,
+               coarsest_n=15)
+    f = torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev)
+    rows, total_ms = [], 0.0
+    for nu in range(1, 6):
+        for cyc in ["V", "W"]:
+            kw = dict(tol=1e-5, cycle=cyc, smoother="gmres", nu_pre=nu, nu_post=nu, max_cycles=600)
+            for _ in range(args.warmup):
+                S.solve(f, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, info = S.solve(f, **kw)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / args.steps * 1e3
+            total_ms += ms
+            rows.append({"nu": nu, "cycle": cyc, "cycles": info["cycles"][0], "ms": ms})
+    out = {"metric": "time to rel.res 1e-5 summed over the Table 9 sweep (10 solves)", "value": total_ms,
+           "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "MP 2-B high variation, k = 10 + 65 chi (chi: seeded independent uniform per node), "
+                                  "n=120, coarsest 15, shift 1/75, GMRES(3) V/W(nu,nu) nu=1..5, FP64, tol 1e-5",
+                      "n": n},
+           "solves": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -273,6 +313,9 @@ def main():
         return
     if args.workload == "media2048":
         media_workload(args)
+        return
+    if args.workload == "mp2b":
+        mp2b_workload(args)
         return
     if args.workload != "mp2a":
         batch_workloads(args)

@@ -128,3 +128,37 @@ def random_k2(n: int, seed: int, k_lo: float, k_hi: float) -> np.ndarray:
     rng = np.random.default_rng(seed)
     k = rng.uniform(k_lo, k_hi, size=(n + 1, n + 1))
     return k * k
+
+
+def _unit_range(field: np.ndarray) -> np.ndarray:
+    """Affine map of a field onto [0, 1] with both ends attained."""
+    lo, hi = float(field.min()), float(field.max())
+    chi = (field - lo) / (hi - lo)
+    return np.clip(chi, 0.0, 1.0)
+
+
+def chi_smooth(n: int, seed: int, corr: float = 0.1) -> np.ndarray:
+    """MP 2-B medium-variation profile χ (§5.2, smooth changes): seeded N(0,1)
+    white noise, Gaussian-filtered with width `corr` (periodic FFT), mapped onto
+    [0, 1] so that the minimum is 0 and the maximum 1."""
+    rng = np.random.default_rng(seed)
+    return _unit_range(_gaussian_filter_periodic(rng.standard_normal((n + 1, n + 1)), corr))
+
+
+def chi_sharp(n: int, seed: int) -> np.ndarray:
+    """MP 2-B high-variation profile χ (§5.2, sharp changes): independent U(0, 1)
+    values node by node, mapped onto [0, 1] so that both ends are attained."""
+    rng = np.random.default_rng(seed)
+    return _unit_range(rng.uniform(0.0, 1.0, size=(n + 1, n + 1)))
+
+
+def k2_from_chi(chi: np.ndarray, k1: float, k2: float) -> np.ndarray:
+    """k = k1 + (k2 - k1) χ of MP 2-B (§2), returned as k^2; k spans exactly
+    [k1, k2] when χ spans [0, 1]."""
+    k = float(k1) + (float(k2) - float(k1)) * chi
+    return (k * k).astype(np.float64)
+
+
+def mp2b_grid(k2: float, kh: float = 0.625) -> int:
+    """Intervals n with max(k) h = kh (§2: the largest wavenumber obeys kh = 0.625)."""
+    return int(round(float(k2) / kh))
