@@ -5,6 +5,11 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 T_0 = (I - P A_c^{-1} R A)(I - X^{-1} A) with X = omega diag(A): one Jacobi
 smoothing step followed by an exact coarse grid correction (§3). A_c is the
 Galerkin product of either A itself or the shifted Laplacian C (§4, Table 1).
+
+The diagnostics below (§3.1 HPD tests of Gamma~, §4.2 optimality value) are
+pinned by closed forms, the identity T_0^H T_0 = I - Gamma, 14 of the 16 HPD
+marks of Table 1 and the qualitative trends of Table 2. The values of
+Table 2 themselves are not reproduced: parity unpinned for them.
 """
 from __future__ import annotations
 
@@ -38,3 +43,79 @@ def spectral_norm(T: np.ndarray) -> float:
 def spectral_radius(T: np.ndarray) -> float:
     """Largest eigenvalue modulus of a dense matrix."""
     return float(np.max(np.abs(np.linalg.eigvals(T))))
+
+
+# ---------------------------------------------------------------------------
+# Two-grid convergence diagnostics (§3.1 definitions and corollaries, §4.2
+# Table 2). For T_0 = I - D A the matrix Gamma = A^H D^H + D A - A^H D^H D A
+# satisfies T_0^H T_0 = I - Gamma, so ||T_0||_2 < 1 exactly when Gamma is
+# Hermitian positive definite. The simplified operator drops the cross term
+# of D: D~ = M + P A_c^{-1} R, where M is the approximate inverse applied by
+# the smoother (X^{-1} for one weighted-Jacobi step; for nu steps the
+# operator (I - (I - X^{-1} A)^nu) A^{-1}, which is X^{-1} at nu = 1).
+
+def gamma_of(A: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Gamma = A^H D^H + D A - A^H D^H D A for dense A and D."""
+    DA = D @ A
+    return DA.conj().T + DA - DA.conj().T @ DA
+
+
+def two_grid_parts(k: float, n: int, beta2: float = 0.7, transfer: str = "bezier", coarse_on: str = "C",
+                   omega: float = 4.5, nu: int = 1):
+    """Dense A (scaled operator), smoother approximate inverse M, coarse
+    correction Q = P A_c^{-1} R for constant k on an n-interval grid."""
+    h = 1.0 / n
+    k2 = np.full((n + 1, n + 1), float(k) ** 2)
+    A = helmholtz_matrix(k2, h).toarray()
+    Mc = shifted_laplacian(k2, h, beta2).toarray() if coarse_on == "C" else A
+    P = prolongation(n, transfer).toarray()
+    R = restriction(n, transfer).toarray()
+    Q = P @ np.linalg.solve(R @ Mc @ P, R)
+    I = np.eye(A.shape[0])
+    S = I - A / (omega * np.diag(A))[:, None]
+    M = (I - np.linalg.matrix_power(S, nu)) @ np.linalg.inv(A)
+    return A, M, Q
+
+
+def gamma_tilde(k: float, n: int, **kw) -> np.ndarray:
+    """Simplified operator Gamma~ of §3.1 with D~ = M + P A_c^{-1} R."""
+    A, M, Q = two_grid_parts(k, n, **kw)
+    return gamma_of(A, M + Q)
+
+
+def is_hpd_cholesky(B: np.ndarray, herm_tol: float = 1e-10) -> bool:
+    """HPD test of §3.1 by a Cholesky factorisation B = L L^H (B Hermitian)."""
+    if np.linalg.norm(B - B.conj().T) > herm_tol * max(1.0, np.linalg.norm(B)):
+        return False
+    try:
+        np.linalg.cholesky(B)
+    except np.linalg.LinAlgError:
+        return False
+    return True
+
+
+def hpd_conditions(B: np.ndarray) -> dict:
+    """The four element-wise conditions listed in §3.1 (each necessary for a
+    Hermitian B to be positive definite): positive diagonal; b_ii + b_jj >
+    2 |Re b_ij| for i != j; the largest modulus on the diagonal; det B > 0."""
+    d = np.real(np.diag(B))
+    off = np.abs(np.real(B))
+    np.fill_diagonal(off, -np.inf)
+    pair = bool(np.all(d[:, None] + d[None, :] > 2.0 * off))
+    mod = np.abs(B)
+    sign, _ = np.linalg.slogdet(B)
+    return {"positive_diagonal": bool(np.all(d > 0)), "pairs": pair,
+            "max_on_diagonal": bool(mod.max() <= np.max(np.abs(np.diag(B)))),
+            "positive_determinant": bool(abs(np.imag(sign)) < 1e-8 and np.real(sign) > 0)}
+
+
+def optimality_value(B: np.ndarray, p=1) -> float:
+    """||B||_p / kappa_p(B) = 1 / ||B^{-1}||_p, the quantity of Table 2 (p = 1)."""
+    return 1.0 / float(np.linalg.norm(np.linalg.inv(B), p))
+
+
+def two_grid_operator(k: float, n: int, **kw) -> np.ndarray:
+    """T_0 = (I - Q A)(I - M A): nu smoothing steps, then the exact coarse correction."""
+    A, M, Q = two_grid_parts(k, n, **kw)
+    I = np.eye(A.shape[0])
+    return (I - Q @ A) @ (I - M @ A)
