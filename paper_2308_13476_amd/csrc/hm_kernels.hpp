@@ -64,9 +64,14 @@ template <typename T> void launch_apply(const LaunchCtx&, const LevelOp<T>&, Vec
 template <typename T> void launch_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> r);
 template <typename T>
 void launch_jacobi(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
-// fc = R r; when uc.p is not null the coarse iterate uc is zeroed in the same pass.
+// fc = R r; when uc.p is not null the coarse iterate uc is zeroed in the same
+// pass. When z0.p is not null, fc is also written to the first Arnoldi plane of
+// z0 (4 planes per right-hand side) with the partial sums of ||fc||^2 in
+// reduction region 0: the residual pass of a GMRES step from uc = 0. Returns
+// the number of blocks per right-hand side (the partial-sum count).
 template <typename T>
-void launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc);
+int launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc,
+                    Vec<T> z0 = Vec<T>{nullptr, 0});
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
@@ -76,11 +81,14 @@ void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, 
 // products A z. `between(arg, i)` (may be null) is called on the host after
 // the i-th launch of the Arnoldi passes (timing hook). With res.p set, the
 // last pass writes the updated iterate to unew (u is left as it was) and the
-// residual f - A unew to res; unew and res may be Wb and Wa.
+// residual f - A unew to res; unew and res may be Wb and Wa. r_ready_nblk > 0
+// means u = 0 and the residual pass already ran as part of the restriction
+// (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
+// starts with the second pass.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
-                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0});
+                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

@@ -309,12 +309,21 @@ __global__ __launch_bounds__(kBX * BY) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
 // same pass when `uc` is given.
 template <typename T, bool kBez, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_restrict(Grid gf, Grid gc, Vec<T> r, Vec<T> fc, Vec<T> uc,
-                                                       const int* active, int rpt) {
+                                                       Vec<T> Z, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<T>* rb = r.rhs(b);
     cplx<T>* fb = fc.rhs(b);
     cplx<T>* ub = uc.p ? uc.rhs(b) : nullptr;
+    cplx<T>* zb = Z.p ? Z.p + (long long)(b * 4) * Z.plane : nullptr;
+    double nrm[1] = {0.0};
+    auto put = [&](long long pc, cplx<T> v) {
+        fb[pc] = v;
+        if (zb) {
+            zb[pc] = v;
+            nrm[0] += dnorm2(v);
+        }
+    };
     for_nodes(gc, rpt, [&](int I, int J, long long pc) {
         if (ub) ub[pc] = cplx<T>{T(0), T(0)};
         const long long pf = gf.at(2 * I, 2 * J);
@@ -333,7 +342,7 @@ __global__ __launch_bounds__(kBX * BY) void k_restrict(Grid gf, Grid gc, Vec<T> 
                 acc.re += w[dy + 2] * row.re;
                 acc.im += w[dy + 2] * row.im;
             }
-            fb[pc] = T(1.0 / 256.0) * acc;
+            put(pc, T(1.0 / 256.0) * acc);
         } else {
             constexpr T w[3] = {T(1), T(2), T(1)};
 #pragma unroll
@@ -348,9 +357,10 @@ __global__ __launch_bounds__(kBX * BY) void k_restrict(Grid gf, Grid gc, Vec<T> 
                 acc.re += w[dy + 1] * row.re;
                 acc.im += w[dy + 1] * row.im;
             }
-            fb[pc] = T(1.0 / 16.0) * acc;
+            put(pc, T(1.0 / 16.0) * acc);
         }
     });
+    if (zb) block_partials<1>(nrm, pout + b * kPartStride);
 }
 
 // Prolongation of §4 per dimension: fine 2I <- (e[I-1] + 6 e[I] + e[I+1]) / 8,
@@ -936,11 +946,16 @@ void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T>
     });
 }
 
+double* region(const LaunchCtx& ctx, int r);
+
 template <typename T>
-void launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc) {
+int launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc,
+                    Vec<T> z0) {
     const Geom q = geom(coarse, false, ctx.nrhs, ctx.block_cap);
-    if (transfer == 0) HM_LAUNCH(q, (k_restrict<T, true, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
-    else HM_LAUNCH(q, (k_restrict<T, false, BY>), fine, coarse, r, fc, uc, HM_ACTIVE, q.rpt);
+    double* pout = z0.p ? region(ctx, 0) : nullptr;
+    if (transfer == 0) HM_LAUNCH(q, (k_restrict<T, true, BY>), fine, coarse, r, fc, uc, z0, pout, HM_ACTIVE, q.rpt);
+    else HM_LAUNCH(q, (k_restrict<T, false, BY>), fine, coarse, r, fc, uc, z0, pout, HM_ACTIVE, q.rpt);
+    return q.nblk;
 }
 
 template <typename T>
@@ -963,7 +978,7 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
-                       Vec<T> unew, Vec<T> res) {
+                       Vec<T> unew, Vec<T> res, int r_ready_nblk) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
@@ -980,10 +995,21 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
                 hipLaunchKernelGGL((k_prereduce<decltype(kc)::value>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream,
                                    part, q.nblk, HM_ACTIVE);
         };
-        HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
-        prereduce(A, std::integral_constant<int, 1>{});
+        int nb_r = nb;
+        if (r_ready_nblk > 0) {
+            // u = 0: z_0 = f and its partial norms were written by the restriction
+            nb_r = r_ready_nblk;
+            if (r_ready_nblk > ctx.block_cap) {
+                hipLaunchKernelGGL((k_prereduce<1>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, A, r_ready_nblk,
+                                   HM_ACTIVE);
+                nb_r = 1;
+            }
+        } else {
+            HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
+            prereduce(A, std::integral_constant<int, 1>{});
+        }
         if (between) between(between_arg, 0);
-        HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb, B, HM_ACTIVE, q.rpt);
+        HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
         prereduce(B, std::integral_constant<int, 2>{});
         if (between) between(between_arg, 1);
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
@@ -1096,10 +1122,11 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_apply<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>);                         \
     template void launch_residual<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>);              \
     template void launch_jacobi<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, double);        \
-    template void launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>);                \
+    template int launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>, Vec<T>);         \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
-                                       Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>);  \
+                                       Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>,   \
+                                       int);                                                                    \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

@@ -419,7 +419,8 @@ struct CycleParams {
 // last pass also forms the residual f - A u into the level's w buffer; the
 // updated iterate then lands in t and the u / t buffers exchange roles.
 template <typename T>
-void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false) {
+void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
+            int r_ready_nblk = 0) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -462,7 +463,8 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, timed ? &Hook::cb : nullptr, &hook,
-                         then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0});
+                         then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0},
+                         r_ready_nblk);
     if (then_residual) {
         std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
@@ -493,8 +495,10 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
     launch_tail<T>(lc, a);
 }
 
+// r_ready_nblk > 0: level l was entered with u = 0 and the restriction also
+// formed the first GMRES residual (see launch_restrict).
 template <typename T>
-void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
+void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0) {
     if (l == c->tail_level[sizeof(T) == 4]) {
         launch_tail_from<T>(c, lc, l, cp);
         return;
@@ -508,13 +512,19 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp) {
     // on Galerkin levels the last GMRES pre-smoothing step also forms the
     // residual to restrict
     const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && l > 0;
-    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1);
+    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0);
     if (!fused)
         launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                            vec<T>(Prec<T>::w(lb), lb));
-    launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb), vec<T>(Prec<T>::f(cb), cb),
-                       vec<T>(Prec<T>::u(cb), cb));
-    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp);
+    // the next level's first GMRES step starts from its zeroed iterate: its
+    // residual pass is the restriction itself (launched levels only)
+    const int lc1 = l + 1;
+    const bool r_in_restrict = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && lc1 != c->tail_level[sizeof(T) == 4] &&
+                               lc1 != c->L - 1;
+    const int nb_r = launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb),
+                                        vec<T>(Prec<T>::f(cb), cb), vec<T>(Prec<T>::u(cb), cb),
+                                        r_in_restrict ? vec<T>(Prec<T>::V(cb), cb) : Vec<T>{nullptr, 0});
+    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0);
     launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, vec<T>(Prec<T>::u(cb), cb), vec<T>(Prec<T>::u(lb), lb));
     for (int s = 0; s < cp.nu2; ++s) smooth<T>(c, lc, l, cp);
 }
