@@ -75,20 +75,35 @@ int launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
+// A coarse grid correction to fold into the next smoothing step: u += P e with
+// e on the coarse grid gc; xt receives u + P e.
+template <typename T>
+struct ProlongIn {
+    Grid gc{};
+    Vec<T> e{nullptr, 0};
+    int transfer = 0;
+    Vec<T> xt{nullptr, 0};
+};
+
 // One GMRES(3) smoothing step (§5.3) on A u = f: five passes (residual; apply;
 // two fused orthogonalise + apply passes; last column + least squares + update).
 // Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
 // products A z. `between(arg, i)` (may be null) is called on the host after
 // the i-th launch of the Arnoldi passes (timing hook). With res.p set, the
 // last pass writes the updated iterate to unew (u is left as it was) and the
-// residual f - A unew to res; unew and res may be Wb and Wa. r_ready_nblk > 0
+// residual f - A unew to res; unew and res may be Wb and Wa. pro.e.p set: the
+// step begins with the coarse grid correction u += P e (coarse level pro.gc),
+// formed on the fly by the first pass, which keeps u + P e in pro.xt; the last
+// pass then writes the updated iterate to u (the step never changes the
+// roles of u and pro.xt). r_ready_nblk > 0
 // means u = 0 and the residual pass already ran as part of the restriction
 // (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
 // starts with the second pass.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
-                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0);
+                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0,
+                       ProlongIn<T> pro = ProlongIn<T>{});
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

@@ -57,7 +57,7 @@ Geom geom(const Grid& g, bool heavy, int nrhs, int cap) {
 // lowered until the block's LDS stages fit kMaxTileBytes.
 constexpr size_t kMaxTileBytes = 64 * 1024;
 template <typename Op, typename T>
-size_t tile_bytes(int by, int rpt);
+__host__ __device__ size_t tile_bytes(int by, int rpt);
 template <typename Op, typename T>
 Geom geom_op(const Grid& g, int nrhs, int cap) {
     Geom q = geom(g, Op::kHeavy, nrhs, cap);
@@ -210,6 +210,10 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
     });
 }
 
+template <typename Op, typename T, typename PGet, typename F>
+__device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Tile<op_radius<Op>::value>& tl,
+                                                cplx<T>* lds, PGet&& pget, F&& f);
+
 // Runs f(i, j, p, pget(p), x at p, A x at p) over the thread's nodes, where
 // x = xmake(xload(p)) (xload only loads): x for the block tile plus halo is
 // staged in LDS first (one evaluation per tile node instead of one per
@@ -223,6 +227,14 @@ __device__ __forceinline__ void for_nodes_applied_pre(const Op& op, int rpt, XLo
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
     const Tile<R> tl = block_tile<R>(rpt);
     fill_tile<T, R>(lds, tl, op.g, xload, xmake);
+    apply_from_tile<Op, T>(op, rpt, tl, lds, pget, f);
+}
+
+// The second half of for_nodes_applied_pre: x of the block tile plus halo is
+// in LDS (after a barrier); runs f(i, j, p, pget(p), x at p, A x at p).
+template <typename Op, typename T, typename PGet, typename F>
+__device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Tile<op_radius<Op>::value>& tl,
+                                                cplx<T>* lds, PGet&& pget, F&& f) {
     if constexpr (is_product<Op>::value) {
         product_stages(op, tl, lds, pget, f);
     } else {
@@ -254,7 +266,7 @@ __device__ __forceinline__ void for_nodes_applied(const Op& op, int rpt, XGet&& 
 
 // Dynamic LDS bytes of an operator kernel launched with geometry (by, rpt).
 template <typename Op, typename T>
-size_t tile_bytes(int by, int rpt) {
+__host__ __device__ size_t tile_bytes(int by, int rpt) {
     constexpr int R = op_radius<Op>::value;
     if constexpr (is_product<Op>::value) return ProductStages<T>::values(by * rpt) * sizeof(cplx<T>);
     return size_t(Tile<R>::TW) * size_t(by * rpt + 2 * R) * sizeof(cplx<T>);
@@ -472,6 +484,98 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Ve
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
+// The coarse values that a fine tile with halo R reads through the §4
+// prolongation: coarse columns c0/2 - ceil(R/2) - 1 ... and rows likewise,
+// kept in LDS after the operator's own stages.
+template <int R>
+struct ProlongTile {
+    static constexpr int EW = (kBX - 1 + R) / 2 + (R + 1) / 2 + 3;
+    __host__ __device__ static int rows(int fine_rows) { return (fine_rows - 1 + R) / 2 + (R + 1) / 2 + 3; }
+};
+
+// Pass 1 of the first post-smoothing step fused with the coarse grid
+// correction before it: x = u + P e on the block tile and its halo (zero
+// off the grid), x to xt (u stays as it was: neighbouring blocks read it),
+// z0 = f - A x, partials ||z0||^2. The pass that ends the step reads x from
+// xt and writes the updated iterate to u.
+template <typename Op, typename T, bool kBez, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e, Vec<T> u, Vec<T> f, Vec<T> xt,
+                                                       Vec<T> Z, double* pout, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    constexpr int R = op_radius<Op>::value;
+    using PT = ProlongTile<R>;
+    const cplx<T>* eb = e.rhs(b);
+    const cplx<T>* ub = u.rhs(b);
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* xb = xt.rhs(b);
+    cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<R> tl = block_tile<R>(rpt);
+    cplx<T>* E = lds + tile_bytes<Op, T>(BY, rpt) / sizeof(cplx<T>);
+    const int C0 = (tl.c0 >> 1) - (R + 1) / 2 - 1, Q0 = (tl.r0 >> 1) - (R + 1) / 2 - 1;
+    const int nc = gc.n, n = op.g.n;
+    {  // coarse e: ghosts (index -1, nc + 1) hold zero; beyond them a clamped read gives zero
+        constexpr int EB = 8;
+        cplx<T> ev[EB];
+        bool ok[EB];
+        for_strided_batched<EB>(
+            PT::EW * PT::rows(tl.rows),
+            [&](int v, int q) {
+                const int I = C0 + q % PT::EW, J = Q0 + q / PT::EW;
+                const int Ic = min(max(I, -1), nc + 1), Jc = min(max(J, -1), nc + 1);
+                ok[v] = I == Ic && J == Jc;
+                ev[v] = eb[gc.at(Ic, Jc)];
+            },
+            [&](int v, int q) { E[q] = ok[v] ? ev[v] : cplx<T>{T(0), T(0)}; });
+    }
+    __syncthreads();
+    {  // fine tile: x = u + P e on the grid, zero on the ghost frame
+        constexpr int FB = FillBatch<T>::value;
+        cplx<T> uv[FB];
+        for_strided_batched<FB>(
+            tl.count(),
+            [&](int v, int q) {
+                const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
+                uv[v] = ub[op.g.at(min(max(i, 0), n), min(max(j, 0), n))];
+            },
+            [&](int v, int q) {
+                const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
+                cplx<T> x{T(0), T(0)};
+                if (i >= 0 && j >= 0 && i <= n && j <= n) {
+                    T wx[3], wy[3];
+                    taps<T>(i, kBez, wx);
+                    taps<T>(j, kBez, wy);
+                    const int base = ((j >> 1) - 1 - Q0) * PT::EW + (i >> 1) - 1 - C0;
+                    x = uv[v];
+#pragma unroll
+                    for (int ty = 0; ty < 3; ++ty) {
+                        cplx<T> row{T(0), T(0)};
+#pragma unroll
+                        for (int tx = 0; tx < 3; ++tx) {
+                            const cplx<T> c = E[base + ty * PT::EW + tx];
+                            row.re += wx[tx] * c.re;
+                            row.im += wx[tx] * c.im;
+                        }
+                        x.re += wy[ty] * row.re;
+                        x.im += wy[ty] * row.im;
+                    }
+                }
+                lds[q] = x;
+            });
+    }
+    __syncthreads();
+    double acc[1] = {0.0};
+    apply_from_tile<Op, T>(op, rpt, tl, lds, [fb](long long q) { return fb[q]; },
+                           [&](int, int, long long p, cplx<T> fp, cplx<T> x, cplx<T> ax) {
+                               const cplx<T> z = fp - ax;
+                               xb[p] = x;
+                               z0[p] = z;
+                               acc[0] += dnorm2(z);
+                           });
+    block_partials<1>(acc, pout + b * kPartStride);
+}
+
 // Pass 2: beta = ||z0|| from pass 1; w0 = A z0 (unnormalised); partials <z0, w0>.
 template <typename Op, typename T, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
@@ -668,29 +772,34 @@ __device__ __forceinline__ int gm_update_weights(const GmState* st, int b, doubl
 
 // Pass 5: u += sum y_i s_i z_i.
 template <typename T, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, const GmState* st, double breakdown,
-                                                   const double* pin, int nblk_in, const int* active, int rpt) {
+__global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, Vec<T> uin, const GmState* st,
+                                                   double breakdown, const double* pin, int nblk_in, const int* active,
+                                                   int rpt) {
     const int b = blockIdx.z;
     const bool act = rhs_active(active, b);
     cplx<T> c[3];
     const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
-    if (!act || k == 0) return;
+    // in place (uin.p null) nothing changes for k = 0; from a separate uin the
+    // iterate is always written
+    if (!act || (k == 0 && !uin.p)) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
     cplx<T>* ub = u.rhs(b);
+    const cplx<T>* ib = uin.p ? uin.rhs(b) : ub;
     constexpr int NB = sizeof(T) == 4 ? 8 : 4;
     cplx<T> xu[NB], x0[NB], x1[NB], x2[NB];
     for_nodes_batched<NB>(
         g, rpt,
         [&](int v, long long p) {
-            xu[v] = ub[p];
+            xu[v] = ib[p];
             x0[v] = z0[p];
             x1[v] = z1[p];
             x2[v] = z2[p];
         },
         [&](int v, int, int, long long p) {
-            cplx<T> x = cfma(xu[v], c[0], x0[v]);
+            cplx<T> x = xu[v];
+            if (k > 0) x = cfma(x, c[0], x0[v]);
             if (k > 1) x = cfma(x, c[1], x1[v]);
             if (k > 2) x = cfma(x, c[2], x2[v]);
             ub[p] = x;
@@ -978,11 +1087,12 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
-                       Vec<T> unew, Vec<T> res, int r_ready_nblk) {
+                       Vec<T> unew, Vec<T> res, int r_ready_nblk, ProlongIn<T> pro) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
     int nb_op = 0;
+    Vec<T> uin{nullptr, 0};  // iterate the update pass starts from, when not u itself
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
         const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
@@ -996,7 +1106,25 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
                                    part, q.nblk, HM_ACTIVE);
         };
         int nb_r = nb;
-        if (r_ready_nblk > 0) {
+        // fused coarse grid correction: its LDS stage must fit beside the operator's
+        constexpr int R = op_radius<Op>::value;
+        const size_t pro_bytes = tile_bytes<Op, T>(q.by, q.rpt) +
+                                 size_t(ProlongTile<R>::EW) * ProlongTile<R>::rows(q.by * q.rpt) * sizeof(cplx<T>);
+        const bool fuse_pro = pro.e.p && pro_bytes <= kMaxTileBytes;
+        if (pro.e.p && !fuse_pro) launch_prolong_add<T>(ctx, pro.gc, lop.g, pro.transfer, pro.e, u);
+        if (fuse_pro) {
+            with_by<Op::kHeavy>(q.by, [&](auto byc) {
+                constexpr int BY = decltype(byc)::value;
+                if (pro.transfer == 0)
+                    hipLaunchKernelGGL((k_gm_r_pro<Op, T, true, BY>), q.grid, q.block, pro_bytes, ctx.stream, op,
+                                       pro.gc, pro.e, u, f, pro.xt, Z, A, HM_ACTIVE, q.rpt);
+                else
+                    hipLaunchKernelGGL((k_gm_r_pro<Op, T, false, BY>), q.grid, q.block, pro_bytes, ctx.stream, op,
+                                       pro.gc, pro.e, u, f, pro.xt, Z, A, HM_ACTIVE, q.rpt);
+            });
+            prereduce(A, std::integral_constant<int, 1>{});
+            uin = pro.xt;
+        } else if (r_ready_nblk > 0) {
             // u = 0: z_0 = f and its partial norms were written by the restriction
             nb_r = r_ready_nblk;
             if (r_ready_nblk > ctx.block_cap) {
@@ -1023,7 +1151,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             HM_LAUNCH_OP(q, (k_gm_u_res<Op, T, BY>), op, Z, u, f, unew, res, st, breakdown, B, nb, HM_ACTIVE,
                          q.rpt);
     });
-    if (!res.p) HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
+    if (!res.p) HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
 }
 
 void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
@@ -1126,7 +1254,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
                                        Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>,   \
-                                       int);                                                                    \
+                                       int, ProlongIn<T>);                                                      \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

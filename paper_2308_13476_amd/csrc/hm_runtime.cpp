@@ -420,11 +420,12 @@ struct CycleParams {
 // updated iterate then lands in t and the u / t buffers exchange roles.
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
-            int r_ready_nblk = 0) {
+            int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
     if (cp.smoother == MG_JACOBI) {
+        if (pro.e.p) launch_prolong_add<T>(lc, pro.gc, lb.g, pro.transfer, pro.e, vec<T>(Prec<T>::u(lb), lb));
         {
             TimedScope ts(c, lc.stream, l == 0 ? 2 : -1, nodes);
             launch_jacobi<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
@@ -464,7 +465,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, timed ? &Hook::cb : nullptr, &hook,
                          then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0},
-                         r_ready_nblk);
+                         r_ready_nblk, pro);
     if (then_residual) {
         std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
@@ -525,8 +526,20 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
                                         vec<T>(Prec<T>::f(cb), cb), vec<T>(Prec<T>::u(cb), cb),
                                         r_in_restrict ? vec<T>(Prec<T>::V(cb), cb) : Vec<T>{nullptr, 0});
     for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0);
-    launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, vec<T>(Prec<T>::u(cb), cb), vec<T>(Prec<T>::u(lb), lb));
-    for (int s = 0; s < cp.nu2; ++s) smooth<T>(c, lc, l, cp);
+    // the coarse grid correction u += P e is formed by the first pass of the
+    // first post-smoothing GMRES step, into the fourth Arnoldi plane (unused
+    // by the step's own passes)
+    const bool pro_fused = cp.smoother == MG_GMRES3 && cp.nu2 > 0;
+    const Vec<T> e = vec<T>(Prec<T>::u(cb), cb);
+    if (!pro_fused) launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, e, vec<T>(Prec<T>::u(lb), lb));
+    for (int s = 0; s < cp.nu2; ++s) {
+        ProlongIn<T> pro{};
+        if (pro_fused && s == 0) {
+            const Vec<T> Z = vec<T>(Prec<T>::V(lb), lb);
+            pro = ProlongIn<T>{cb.g, e, c->transfer, Vec<T>{Z.p + 3 * Z.plane, 4 * Z.plane}};
+        }
+        smooth<T>(c, lc, l, cp, false, 0, pro);
+    }
 }
 
 // Zeroes every vector and coefficient plane (ghost frames must read zero).
