@@ -82,11 +82,4 @@ constexpr long long kPartStride = (long long)kMaxPartialBlocks * 8;  // doubles 
 template <typename T>
 __device__ __forceinline__ T line_w(int i, int n) { return (i == 0 || i == n) ? T(0.5) : T(1); }
 
-// Wavefront (64 lanes) sum.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 }  // namespace hm

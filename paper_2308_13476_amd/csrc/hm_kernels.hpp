@@ -159,7 +159,9 @@ struct TailLevel {
 template <typename T>
 struct TailArgs {
     int nlev;
-    long long lds_bytes;  // sum of tail_plane_values over the levels, in bytes
+    long long lds_bytes;    // total dynamic LDS: the planes, then the inverse when it is staged
+    long long plane_bytes;  // sum of tail_plane_values over the levels, in bytes
+    long long inv_off;      // byte offset of the LDS copy of inv, or -1 (read from global memory)
     TailLevel<T> lv[kMaxTailLevels];
     cplx<T>* u_top;         // level l0 iterate (read, then overwritten), right-hand side 0; stride g.plane
     const cplx<T>* f_top;   // level l0 right-hand side

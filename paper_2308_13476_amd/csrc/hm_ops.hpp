@@ -340,22 +340,44 @@ __device__ __forceinline__ int block_linear() {
 }
 __device__ __forceinline__ int thread_linear() { return threadIdx.y * kBX + threadIdx.x; }
 
-// Block sum for 64 x BY thread blocks, BY <= kMaxBY (wavefront = threadIdx.y).
+// Sum over the 64 lanes of a wavefront by DPP lane moves (no LDS traffic):
+// pairwise within quads, rotations by 4 and 8 within rows of 16, then the
+// sums of rows 0 and 2 broadcast into rows 1 and 3 and of rows 0-1 into rows
+// 2-3. Lane 63 ends with the total; the order of the additions is fixed, so
+// the result is deterministic. Doubles move as two 32-bit halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b & 0xffffffffu)), CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, ROW_MASK, 0xF, true);
+    return __longlong_as_double((unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
+}
+
+// Block sum for 64 x BY thread blocks, BY <= kMaxBY (wavefront = threadIdx.y):
+// each wavefront reduces its K values with DPP moves, lane 63 stores them,
+// and every thread adds the wavefront totals in wavefront order.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
     __shared__ double sh[K][kMaxBY];
     const int lane = threadIdx.x, wave = threadIdx.y;
     __syncthreads();  // sh may still be read from an earlier call
-    // butterfly over the K values together: the cross-lane exchanges of one
-    // step are independent and overlap (same sums as K separate wave_sum)
     double w[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) w[k] = v[k];
+    // the K values of one step are independent: their moves overlap
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0xb1, 0xF>(w[k]);  // quad_perm [1,0,3,2]
 #pragma unroll
-        for (int k = 0; k < K; ++k) w[k] += __shfl_xor(w[k], off, 64);
-    if (lane == 0)
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0x4e, 0xF>(w[k]);  // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0x124, 0xF>(w[k]);  // row_ror 4
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0x128, 0xF>(w[k]);  // row_ror 8
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0x142, 0xA>(w[k]);  // row_bcast 15 into rows 1, 3
+#pragma unroll
+    for (int k = 0; k < K; ++k) w[k] += dpp_move<0x143, 0xC>(w[k]);  // row_bcast 31 into rows 2, 3
+    if (lane == kBX - 1)
 #pragma unroll
         for (int k = 0; k < K; ++k) sh[k][wave] = w[k];
     __syncthreads();
@@ -363,7 +385,9 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += sh[k][w];
+#pragma unroll
+        for (int q = 0; q < kMaxBY; ++q)
+            if (q < nw) s += sh[k][q];
         tot[k] = s;
     }
 }

@@ -476,12 +476,24 @@ template <typename T>
 void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams& cp) {
     TailArgs<T> a{};
     a.nlev = c->L - l0;
-    a.lds_bytes = 0;
+    a.plane_bytes = 0;
     for (int q = 0; q < a.nlev; ++q) {
         LevelBuf& lb = c->lv[l0 + q];
         a.lv[q] = TailLevel<T>{lb.g, lb.radius, Prec<T>::coef(lb)};
-        a.lds_bytes += tail_plane_values(lb.g.n, q, a.nlev) * (long long)sizeof(cplx<T>);
+        a.plane_bytes += tail_plane_values(lb.g.n, q, a.nlev) * (long long)sizeof(cplx<T>);
     }
+    // the coarsest inverse is copied to LDS when it fits beside the planes
+    // (each visit of the coarsest level then reads it without global round trips)
+    long long end = a.plane_bytes;
+    auto place = [&](long long bytes) -> long long {
+        const long long off = (end + 15) / 16 * 16;
+        if (off + bytes > kTailMaxLdsBytes) return -1;
+        end = off + bytes;
+        return off;
+    };
+    const long long Nc = (long long)(c->lv[c->L - 1].g.n + 1) * (c->lv[c->L - 1].g.n + 1);
+    a.inv_off = c->inv ? place(Nc * Nc * (long long)sizeof(cplx<double>)) : -1;
+    a.lds_bytes = end;
     LevelBuf& top = c->lv[l0];
     a.u_top = Prec<T>::u(top);
     a.f_top = Prec<T>::f(top);

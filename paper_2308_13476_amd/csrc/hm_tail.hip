@@ -46,9 +46,9 @@ __device__ __forceinline__ TLv<T> tail_level(const TailArgs<T>& a, int q, cplx<T
     TLv<T> v;
     v.g = a.lv[q].g;
     v.radius = a.lv[q].radius;
-    v.coef = a.lv[q].coef;
     v.m = v.g.n + 1;
     v.lp = tail_pitch(v.g.n);
+    v.coef = a.lv[q].coef;
     long long off = 0;
     for (int r = 0; r < q; ++r) off += tail_plane_values(a.lv[r].g.n, r, a.nlev);
     v.pl = lds + off;
@@ -342,19 +342,31 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int*
     if (!rhs_active(active, b)) return;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
     const int last = a.nlev - 1;
-    // zero every plane (the frames must read zero), then load the top level
+    // zero every plane (the frames must read zero), stage the coarsest
+    // inverse in LDS when it fits, then load the top level
     {
-        const long long total = a.lds_bytes / (long long)sizeof(cplx<T>);
+        const long long total = a.plane_bytes / (long long)sizeof(cplx<T>);
         for (long long q = thread_linear(); q < total; q += kTailThreads) lds[q] = cplx<T>{T(0), T(0)};
+        unsigned char* base = reinterpret_cast<unsigned char*>(lds);
+        if (a.inv_off >= 0) {
+            const int N = (a.lv[a.nlev - 1].g.n + 1) * (a.lv[a.nlev - 1].g.n + 1);
+            cplx<double>* dst = reinterpret_cast<cplx<double>*>(base + a.inv_off);
+            constexpr int IB = 4;
+            cplx<double> v[IB];
+            for_strided_batched<IB>(N * N, [&](int u, int q) { v[u] = a.inv[q]; }, [&](int u, int q) { dst[q] = v[u]; });
+        }
         __syncthreads();
         const TLv<T> L = tail_level(a, 0, lds);
         const long long off = (long long)b * L.g.plane;
-        tnodes(L, [&](int, int, int li, long long gp) {
-            L.u()[li] = a.u_top[off + gp];
-            L.f()[li] = a.f_top[off + gp];
+        tnodes(L, [&](int i, int j, int li, long long) {
+            L.u()[li] = a.u_top[off + L.g.at(i, j)];
+            L.f()[li] = a.f_top[off + L.g.at(i, j)];
         });
         __syncthreads();
     }
+    const cplx<double>* inv = a.inv_off >= 0
+                                  ? reinterpret_cast<const cplx<double>*>(reinterpret_cast<unsigned char*>(lds) + a.inv_off)
+                                  : a.inv;
     const double inv_omega = 1.0 / a.omega;
     const bool bez = a.bez != 0;
     // Cycle state machine with a single smoothing site (keeps the GMRES
@@ -365,13 +377,13 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int*
     int q = 0;
     bool up = false;
     if (last == 0) {
-        tail_coarse(tail_level(a, 0, lds), a.inv);
+        tail_coarse(tail_level(a, 0, lds), inv);
     } else {
         for (;;) {
             int nu;
             if (!up) {
                 if (q == last) {
-                    tail_coarse(tail_level(a, q, lds), a.inv);
+                    tail_coarse(tail_level(a, q, lds), inv);
                     q -= 1;
                     up = true;
                     continue;
@@ -408,7 +420,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int*
     }
     const TLv<T> L = tail_level(a, 0, lds);
     const long long off = (long long)b * L.g.plane;
-    tnodes(L, [&](int, int, int li, long long gp) { a.u_top[off + gp] = L.u()[li]; });
+    tnodes(L, [&](int i, int j, int li, long long) { a.u_top[off + L.g.at(i, j)] = L.u()[li]; });
 }
 
 // X = A^{-1} from the row-major LU factor with row swaps piv (X = U^{-1} L^{-1} P),
