@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--k", type=float, default=200.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=12, help="oracle cycles in the CPU sample")
+    ap.add_argument("--cpu-cycles", type=int, default=36, help="oracle cycles in the CPU sample")
     ap.add_argument("--kernel-class", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
