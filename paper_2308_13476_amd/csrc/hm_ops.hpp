@@ -508,6 +508,25 @@ static __device__ __noinline__ void gm_least_squares(GmState& st, LsWork& w) {
     }
 }
 
+// 1 / sqrt(x) and 1 / x for x > 0 in FP64: the hardware estimates refined by
+// two Newton steps each (the estimate's relative error squares per step,
+// ending at about one unit in the last place). They stand in for the
+// correctly rounded sqrt and division sequences in the short dependent chain
+// of the least-squares solve below.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return y;
+}
+
 // The same least-squares solve with every index fixed at compile time, so
 // that H, the rotations and y stay in registers: for kernels in which every
 // thread holds H. Columns at or beyond k are skipped; y_i s_i for i < k, zero
@@ -545,18 +564,16 @@ __device__ __forceinline__ void gm_least_squares_regs(const double (&Hr)[4][3], 
             // operator norm, so the squares stay far from overflow)
             const double ar = hr[j][j], ai = hi[j][j], br = hr[j + 1][j], bi = hi[j + 1][j];
             const double a2 = ar * ar + ai * ai;
-            const double rho = sqrt(a2 + (br * br + bi * bi));
+            const double ir = rsqrt_nr(a2 + (br * br + bi * bi));  // 1 / rho
             double c, s_r, s_i;
             if (a2 == 0.0) {
-                const double ir = 1.0 / rho;
                 c = 0.0;
                 s_r = br * ir;
                 s_i = -bi * ir;
             } else {
-                const double na = sqrt(a2);
-                const double ir = 1.0 / rho;
-                const double inr = ir / na;
-                c = na * ir;
+                const double ina = rsqrt_nr(a2);  // 1 / |a|
+                const double inr = ir * ina;
+                c = a2 * ina * ir;
                 s_r = (ar * br + ai * bi) * inr;
                 s_i = (ai * br - ar * bi) * inr;
             }
@@ -587,7 +604,7 @@ __device__ __forceinline__ void gm_least_squares_regs(const double (&Hr)[4][3], 
                 }
             }
             const double dr = hr[j][j], di = hi[j][j];
-            const double inv = 1.0 / (dr * dr + di * di);
+            const double inv = rcp_nr(dr * dr + di * di);
             wr[j] = (tr * dr + ti * di) * inv;
             wi[j] = (ti * dr - tr * di) * inv;
         }
