@@ -32,6 +32,7 @@ struct LaunchCtx {
     double* partials;   // per-block partial sums: 2 regions x nrhs_cap x kPartStride doubles
     int nrhs_cap;       // right-hand sides the partials were sized for
     int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
+    int fuse_correction = 1;  // 0: the coarse grid correction always runs as its own pass
 };
 
 // The operator of one level: analytic on level 0 (from k^2), stored Galerkin

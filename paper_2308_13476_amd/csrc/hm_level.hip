@@ -1110,7 +1110,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         constexpr int R = op_radius<Op>::value;
         const size_t pro_bytes = tile_bytes<Op, T>(q.by, q.rpt) +
                                  size_t(ProlongTile<R>::EW) * ProlongTile<R>::rows(q.by * q.rpt) * sizeof(cplx<T>);
-        const bool fuse_pro = pro.e.p && pro_bytes <= kMaxTileBytes;
+        const bool fuse_pro = pro.e.p && ctx.fuse_correction && pro_bytes <= kMaxTileBytes;
         if (pro.e.p && !fuse_pro) launch_prolong_add<T>(ctx, pro.gc, lop.g, pro.transfer, pro.e, u);
         if (fuse_pro) {
             with_by<Op::kHeavy>(q.by, [&](auto byc) {

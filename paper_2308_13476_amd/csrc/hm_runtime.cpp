@@ -116,6 +116,9 @@ struct mg_ctx {
     // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
     // beyond it reductions are pre-reduced in a one-block pass
     int block_cap = 640;
+    // the coarse grid correction folded into the first post-smoothing pass
+    // where its LDS stage fits (HELMG_FUSE_CORRECTION=0: always a pass of its own)
+    int fuse_correction = 1;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -260,7 +263,7 @@ template <typename T>
 Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
-    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap};
+    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap, c->fuse_correction};
 }
 
 // Timing hook: events around the launches of one kernel class.
@@ -894,6 +897,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
+    if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
         const int v = std::atoi(e);
         c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);

@@ -203,13 +203,16 @@ def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
 
 
 @pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"},
-                                 {"HELMG_L1_PRODUCT": "2", "HELMG_MAX_BLOCKS": "200"}],
-                         ids=["block_cap_64", "stored_level1", "product_level1_fp64"])
+                                 {"HELMG_L1_PRODUCT": "2", "HELMG_MAX_BLOCKS": "200"},
+                                 {"HELMG_FUSE_CORRECTION": "0"}],
+                         ids=["block_cap_64", "stored_level1", "product_level1_fp64", "unfused_correction"])
 def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
     """With a block cap of 64 every GMRES reduction goes through the one-block
     pre-reduction pass; HELMG_L1_PRODUCT=0 makes level 1 apply its stored
     Galerkin stencil in both precisions, =2 the product R C_s P in both (FP32
-    cycles use the product by default, FP64 cycles the stored stencil). Each
+    cycles use the product by default, FP64 cycles the stored stencil);
+    HELMG_FUSE_CORRECTION=0 runs the coarse grid correction as a pass of its
+    own instead of inside the first post-smoothing pass. Each
     gives the oracle's level-1 apply and cycle (FP64) and stays close to it in
     FP32."""
     require_gpu()
