@@ -103,6 +103,65 @@ __global__ __launch_bounds__(kThreads) void k_galerkin(FineCoupling A, Grid gc, 
     }
 }
 
+// Level 1 from the level-0 couplings, one coarse node per thread with its D^2
+// coefficients (D = 5 Bézier, 3 linear) in registers:
+//   A_1(I, I + dK) = sum_a sum_e W(a, e, dK) C(2I + a, e),
+// a the restriction tap (|a| <= 2 per dimension), e one of the five couplings
+// of the fine node p = 2I + a, and W = (1/4) m(a) m(a + e - 2 dK) with the 1D
+// masks m per dimension: a compile-time table, so only the couplings C are
+// loaded (25 fine nodes per coarse node). Taps and couplings off the grid and
+// coarse neighbours off the coarse grid contribute nothing.
+template <bool kBez>
+__global__ __launch_bounds__(kThreads) void k_galerkin0(FineCoupling A, Grid gc, cplx<double>* out) {
+    constexpr int rc = kBez ? 2 : 1;
+    constexpr int D = 2 * rc + 1;
+    const long long mc = gc.n + 1;
+    const int nf = A.g.n, nc = gc.n;
+    for (long long node = blockIdx.x * (long long)kThreads + threadIdx.x; node < mc * mc;
+         node += (long long)gridDim.x * kThreads) {
+        const int Ix = int(node % mc), Iy = int(node / mc);
+        cplx<double> acc[D * D];
+#pragma unroll
+        for (int d = 0; d < D * D; ++d) acc[d] = {0.0, 0.0};
+#pragma unroll
+        for (int ay = -2; ay <= 2; ++ay)
+#pragma unroll
+            for (int ax = -2; ax <= 2; ++ax) {
+                const double rw = 0.25 * mask1(ax, kBez) * mask1(ay, kBez);
+                if (rw == 0.0) continue;  // compile-time (linear transfer)
+                const int px = 2 * Ix + ax, py = 2 * Iy + ay;
+                const bool pin = px >= 0 && px <= nf && py >= 0 && py <= nf;
+                const int pxc = min(max(px, 0), nf), pyc = min(max(py, 0), nf);
+#pragma unroll
+                for (int e = 0; e < 5; ++e) {
+                    const int ex = e == 1 ? -1 : e == 2 ? 1 : 0;
+                    const int ey = e == 3 ? -1 : e == 4 ? 1 : 0;
+                    const int qx = px + ex, qy = py + ey;
+                    const bool ok = pin && qx >= 0 && qx <= nf && qy >= 0 && qy <= nf;
+                    const cplx<double> a = ok ? A(pxc, pyc, ex, ey) : cplx<double>{0.0, 0.0};
+#pragma unroll
+                    for (int dy = -rc; dy <= rc; ++dy)
+#pragma unroll
+                        for (int dx = -rc; dx <= rc; ++dx) {
+                            const double w = rw * mask1(ax + ex - 2 * dx, kBez) * mask1(ay + ey - 2 * dy, kBez);
+                            if (w == 0.0) continue;  // compile-time
+                            acc[(dy + rc) * D + dx + rc].re += w * a.re;
+                            acc[(dy + rc) * D + dx + rc].im += w * a.im;
+                        }
+                }
+            }
+#pragma unroll
+        for (int dy = -rc; dy <= rc; ++dy)
+#pragma unroll
+            for (int dx = -rc; dx <= rc; ++dx) {
+                const int Kx = Ix + dx, Ky = Iy + dy;
+                const bool kin = Kx >= 0 && Kx <= nc && Ky >= 0 && Ky <= nc;
+                out[(long long)((dy + rc) * D + dx + rc) * gc.plane + gc.at(Ix, Iy)] =
+                    kin ? acc[(dy + rc) * D + dx + rc] : cplx<double>{0.0, 0.0};
+            }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_cast_coef(const cplx<double>* src, cplx<float>* dst, long long count) {
     for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < count; q += (long long)gridDim.x * kThreads)
         dst[q] = cast<float>(src[q]);
@@ -239,6 +298,15 @@ void launch_galerkin(hipStream_t s, int fine_level, Grid fine, int fine_radius, 
                      cplx<double>* coarse_coef) {
     FineCoupling A{fine_level, fine, fine_radius, fine_coef, k2_64, 1.0 / (h * h), 2.0 / h, shift};
     const long long mc = coarse.n + 1;
+    if (fine_level == 0 && coarse_radius == (transfer == 0 ? 2 : 1)) {
+        if (transfer == 0)
+            hipLaunchKernelGGL(k_galerkin0<true>, dim3(blocks_for(mc * mc)), dim3(kThreads), 0, s, A, coarse,
+                               coarse_coef);
+        else
+            hipLaunchKernelGGL(k_galerkin0<false>, dim3(blocks_for(mc * mc)), dim3(kThreads), 0, s, A, coarse,
+                               coarse_coef);
+        return;
+    }
     const long long D = 2 * coarse_radius + 1;
     hipLaunchKernelGGL(k_galerkin, dim3(blocks_for(mc * mc * D * D)), dim3(kThreads), 0, s, A, coarse, coarse_radius,
                        int(transfer == 0), coarse_coef);
