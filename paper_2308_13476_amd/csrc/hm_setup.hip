@@ -1,5 +1,7 @@
 // Setup kernels: k^2 layout, Galerkin coarse operators on the complex
 // shifted Laplacian, FP32 copies, the coarsest dense LU and its solves.
+#include <algorithm>
+
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -162,6 +164,95 @@ __global__ __launch_bounds__(kThreads) void k_galerkin0(FineCoupling A, Grid gc,
     }
 }
 
+// Levels >= 1 from a stored fine stencil of radius RF, one coarse node per
+// thread. With s = a + e the offset of the fine column node q = 2I + s from the
+// fine image 2I of coarse node I, the product factors as
+//   G(I, s)      = sum_a R(a) A(2I + a, s - a)          (restriction taps a)
+//   A_c(I, I+d)  = sum_s G(I, s) m(s_x - 2d_x) m(s_y - 2d_y)
+// since P(q, I + d) depends on q - 2(I + d) = s - 2d only. Rows s_y are formed
+// one at a time (row of G, then the x mask, then the y mask into the D_c^2
+// coefficients), so each fine coupling is loaded once per coarse node and only
+// one row of G is live. Loads use clamped indices and are masked afterwards,
+// so they carry no branches and overlap.
+constexpr int kNodeThreads = 64;
+
+template <bool kBez, int RF>
+__global__ __launch_bounds__(kNodeThreads) void k_galerkin_node(Grid gf, const cplx<double>* coef, Grid gc,
+                                                                cplx<double>* out) {
+    constexpr int RA = kBez ? 2 : 1;  // restriction taps |a| <= RA per dimension
+    constexpr int RS = RA + RF;
+    constexpr int NS = 2 * RS + 1;
+    constexpr int RC = (2 * RA + RF) / 2;  // coarse stencil radius
+    constexpr int DC = 2 * RC + 1;
+    constexpr int DF = 2 * RF + 1;
+    const long long mc = gc.n + 1;
+    const int nf = gf.n, nc = gc.n;
+    for (long long node = blockIdx.x * (long long)kNodeThreads + threadIdx.x; node < mc * mc;
+         node += (long long)gridDim.x * kNodeThreads) {
+        const int Ix = int(node % mc), Iy = int(node / mc);
+        cplx<double> acc[DC * DC];
+#pragma unroll
+        for (int d = 0; d < DC * DC; ++d) acc[d] = {0.0, 0.0};
+#pragma unroll
+        for (int sy = -RS; sy <= RS; ++sy) {
+            cplx<double> G[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q) G[q] = {0.0, 0.0};
+#pragma unroll
+            for (int ay = -RA; ay <= RA; ++ay) {
+                const int ey = sy - ay;
+                if (ey < -RF || ey > RF) continue;  // compile-time
+                const int py = 2 * Iy + ay, qy = py + ey;
+                const bool yok = py >= 0 && py <= nf && qy >= 0 && qy <= nf;
+                const int pyc = min(max(py, 0), nf);
+#pragma unroll
+                for (int ax = -RA; ax <= RA; ++ax) {
+                    const double rw = 0.25 * mask1(ax, kBez) * mask1(ay, kBez);
+                    if (rw == 0.0) continue;  // compile-time
+                    const int px = 2 * Ix + ax;
+                    const bool pok = yok && px >= 0 && px <= nf;
+                    const long long at = gf.at(min(max(px, 0), nf), pyc);
+#pragma unroll
+                    for (int ex = -RF; ex <= RF; ++ex) {
+                        const int qx = px + ex;
+                        const bool ok = pok && qx >= 0 && qx <= nf;
+                        const cplx<double> v = coef[(long long)((ey + RF) * DF + ex + RF) * gf.plane + at];
+                        G[ax + ex + RS].re += ok ? rw * v.re : 0.0;
+                        G[ax + ex + RS].im += ok ? rw * v.im : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int dx = -RC; dx <= RC; ++dx) {
+                cplx<double> h{0.0, 0.0};
+#pragma unroll
+                for (int sx = -RS; sx <= RS; ++sx) {
+                    const double w = mask1(sx - 2 * dx, kBez);
+                    if (w == 0.0) continue;  // compile-time
+                    h.re += w * G[sx + RS].re;
+                    h.im += w * G[sx + RS].im;
+                }
+#pragma unroll
+                for (int dy = -RC; dy <= RC; ++dy) {
+                    const double w = mask1(sy - 2 * dy, kBez);
+                    if (w == 0.0) continue;  // compile-time
+                    acc[(dy + RC) * DC + dx + RC].re += w * h.re;
+                    acc[(dy + RC) * DC + dx + RC].im += w * h.im;
+                }
+            }
+        }
+#pragma unroll
+        for (int dy = -RC; dy <= RC; ++dy)
+#pragma unroll
+            for (int dx = -RC; dx <= RC; ++dx) {
+                const int Kx = Ix + dx, Ky = Iy + dy;
+                const bool kin = Kx >= 0 && Kx <= nc && Ky >= 0 && Ky <= nc;
+                out[(long long)((dy + RC) * DC + dx + RC) * gc.plane + gc.at(Ix, Iy)] =
+                    kin ? acc[(dy + RC) * DC + dx + RC] : cplx<double>{0.0, 0.0};
+            }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_cast_coef(const cplx<double>* src, cplx<float>* dst, long long count) {
     for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < count; q += (long long)gridDim.x * kThreads)
         dst[q] = cast<float>(src[q]);
@@ -306,6 +397,25 @@ void launch_galerkin(hipStream_t s, int fine_level, Grid fine, int fine_radius, 
             hipLaunchKernelGGL(k_galerkin0<false>, dim3(blocks_for(mc * mc)), dim3(kThreads), 0, s, A, coarse,
                                coarse_coef);
         return;
+    }
+    const unsigned node_blocks = (unsigned)std::min<long long>((mc * mc + kNodeThreads - 1) / kNodeThreads, 65536);
+    const bool bez = transfer == 0;
+    if (fine_level > 0 && coarse_radius == (bez ? (4 + fine_radius) / 2 : (2 + fine_radius) / 2)) {
+        if (bez && fine_radius == 2) {
+            hipLaunchKernelGGL((k_galerkin_node<true, 2>), dim3(node_blocks), dim3(kNodeThreads), 0, s, fine, fine_coef,
+                               coarse, coarse_coef);
+            return;
+        }
+        if (bez && fine_radius == 3) {
+            hipLaunchKernelGGL((k_galerkin_node<true, 3>), dim3(node_blocks), dim3(kNodeThreads), 0, s, fine, fine_coef,
+                               coarse, coarse_coef);
+            return;
+        }
+        if (!bez && fine_radius == 1) {
+            hipLaunchKernelGGL((k_galerkin_node<false, 1>), dim3(node_blocks), dim3(kNodeThreads), 0, s, fine,
+                               fine_coef, coarse, coarse_coef);
+            return;
+        }
     }
     const long long D = 2 * coarse_radius + 1;
     hipLaunchKernelGGL(k_galerkin, dim3(blocks_for(mc * mc * D * D)), dim3(kThreads), 0, s, A, coarse, coarse_radius,
