@@ -24,6 +24,29 @@ struct RhsNorms {
     double r2;   // latest ||f_s - A_s x||^2
 };
 
+// Stop test of one cycle (§5 stopping criterion), taken on the device by the
+// norm pass that ends the cycle, one block per right-hand side: with
+// r = sqrt(r2 / f2), a right-hand side stops as diverged when r is not finite
+// or exceeds its divergence limit, else as converged when r <= tol. A stopped
+// right-hand side has its active flag cleared, so cycles already queued
+// behind this one skip it. Every test writes one report into a ring that the
+// host reads after the cycle's completion event.
+constexpr int kReportRing = 4;
+
+struct RhsReport {
+    double f2, r2;  // norms of the test
+    int stop;       // 0 running, 1 converged, 2 diverged
+    int cycle;      // 1-based count of tests of this right-hand side in the solve
+};
+
+struct StopTest {
+    RhsReport* ring;       // host-visible [kReportRing][stride]; nullptr: no test
+    int* active;           // [nrhs] the solve's active flags (cleared on a stop)
+    int* count;            // [nrhs] tests taken so far (zeroed when the solve begins)
+    const double* limits;  // [nrhs][2]: tolerance, divergence limit
+    int stride;
+};
+
 // Shared launch parameters of one batched call.
 struct LaunchCtx {
     hipStream_t stream;
@@ -33,6 +56,7 @@ struct LaunchCtx {
     int nrhs_cap;       // right-hand sides the partials were sized for
     int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
     int fuse_correction = 1;  // 0: the coarse grid correction always runs as its own pass
+    StopTest stop{};          // taken by the residual-norm pass when stop.ring is set
 };
 
 // The operator of one level: analytic on level 0 (from k^2), stored Galerkin

@@ -883,16 +883,30 @@ __global__ __launch_bounds__(kBX * BY) void k_norm(Grid g, Vec<T> f, double* pou
 }
 
 // One block per right-hand side: sum the partials of a norm kernel into
-// norms[b].f2 (which = 0) or norms[b].r2 (which = 1).
+// norms[b].f2 (which = 0) or norms[b].r2 (which = 1), and take the stop test
+// of a solve cycle on the latter when st.ring is set.
 __global__ __launch_bounds__(kThreads) void k_sum_norms(const double* pin, int nblk_in, RhsNorms* norms, int which,
-                                                        const int* active) {
+                                                        const int* active, StopTest st) {
     const int b = blockIdx.x;
     if (!rhs_active(active, b)) return;
     double t[1];
     reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
     if (thread_linear() == 0) {
-        if (which == 0) norms[b].f2 = t[0];
-        else norms[b].r2 = t[0];
+        if (which == 0) {
+            norms[b].f2 = t[0];
+        } else {
+            norms[b].r2 = t[0];
+            if (st.ring) {
+                const double f2 = norms[b].f2;
+                const double r = sqrt(t[0] / f2);
+                const double* lim = st.limits + 2 * b;
+                const int stop = (!isfinite(r) || r > lim[1]) ? 2 : (r <= lim[0] ? 1 : 0);
+                const int c = st.count[b] + 1;
+                st.ring[((c - 1) % kReportRing) * st.stride + b] = RhsReport{f2, t[0], stop, c};
+                st.count[b] = c;
+                if (stop) st.active[b] = 0;
+            }
+        }
     }
 }
 
@@ -1157,7 +1171,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
 void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
     // 64 x 4 threads: the block reduction indexes wavefronts by threadIdx.y
     hipLaunchKernelGGL(k_sum_norms, dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, region(ctx, 0), nb, norms, which,
-                       HM_ACTIVE);
+                       HM_ACTIVE, which == 1 ? ctx.stop : StopTest{});
 }
 
 template <typename T>

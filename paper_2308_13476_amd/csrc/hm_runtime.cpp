@@ -78,12 +78,17 @@ struct mg_ctx {
     GmState* gm = nullptr;
     RhsNorms* norms = nullptr;
     int* active = nullptr;
+    int* stop_count = nullptr;      // [max_batch] stop tests taken per right-hand side
+    double* stop_limits = nullptr;  // [max_batch][2] tolerance, divergence limit
     double* partials = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     // host mirrors (pinned)
     RhsNorms* h_norms = nullptr;
     int* h_active = nullptr;
+    double* h_limits = nullptr;
+    RhsReport* h_ring = nullptr;  // stop-test reports, written by the device
+    hipEvent_t cycle_done[2] = {nullptr, nullptr};
     std::string err;
     // kernel timing hook: event pairs of eager launches, and of the graph run last
     int timing_class = 0;
@@ -193,6 +198,8 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     GmState* gm = cv.take<GmState>(B * sizeof(GmState));
     RhsNorms* norms = cv.take<RhsNorms>(B * sizeof(RhsNorms));
     int* active = cv.take<int>(B * 4);
+    int* stop_count = cv.take<int>(B * 4);
+    double* stop_limits = cv.take<double>(B * 16);
     double* partials = cv.take<double>(2 * B * size_t(kPartStride) * 8);
     if (c) {
         c->k2_64 = k64;
@@ -203,6 +210,8 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
         c->gm = gm;
         c->norms = norms;
         c->active = active;
+        c->stop_count = stop_count;
+        c->stop_limits = stop_limits;
         c->partials = partials;
     }
     return align_up(cv.off, kAlign);
@@ -638,11 +647,14 @@ mg_status check_solve_args(mg_ctx* c, int nrhs, double tol, int cyc, int smoothe
 
 // Core solve of A_s x = f_s on level-0 buffers: f_s already in lv[0].f64, the
 // initial guess in lv[0].u64. Leaves every solution in lv[0].u64.
-// One solve on one handle, driven cycle by cycle (a9 stop test): start()
+// One solve on one handle, driven cycle by cycle (§5 stop test): start()
 // enqueues the initial norms; after the stream has synchronised, begin()
-// reads them. enqueue_cycle() enqueues one cycle plus the residual norms on a
-// stream (captured or eager), and after_cycle() reads the norms after the
-// next synchronisation. finish() gathers every right-hand side's last iterate.
+// reads them and hands the device its stop limits. enqueue_cycle() enqueues
+// one cycle and its residual norms with the device-side stop test on a stream
+// (captured or eager); enqueued(it) records the buffer state after cycle it,
+// and after_cycle(it) reads that cycle's stop-test reports once it has
+// completed, so cycles may be queued ahead of the reports. gather() collects
+// every right-hand side's last iterate.
 struct SolveRun {
     mg_ctx* c = nullptr;
     int nrhs = 0;
@@ -650,8 +662,9 @@ struct SolveRun {
     CycleParams cp{};
     mg_solve_opts o{};
     bool fp32 = false;
-    std::vector<double> rel0, rel;
+    std::vector<double> rel0, rel, rel_prev;
     std::vector<int> cycles, state;  // state: 0 running, 1 converged, 2 diverged
+    std::vector<int> buf_after;      // cur_buf after each enqueued cycle
     int running = 0;
     std::vector<uintptr_t> key;
     std::chrono::steady_clock::time_point t0;
@@ -690,6 +703,7 @@ struct SolveRun {
         LevelBuf& l0 = c->lv[0];
         rel0.assign(nrhs, 0.0);
         rel.assign(nrhs, 0.0);
+        rel_prev.assign(nrhs, 0.0);
         cycles.assign(nrhs, 0);
         state.assign(nrhs, 0);
         running = 0;
@@ -712,7 +726,14 @@ struct SolveRun {
                 ++running;
             }
         }
+        for (int b = 0; b < nrhs; ++b) {
+            c->h_limits[2 * b] = tol;
+            c->h_limits[2 * b + 1] = o.divergence * rel0[b];
+        }
         HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
+        HM_HIP(hipMemcpyAsync(c->stop_limits, c->h_limits, sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s));
+        HM_HIP(hipMemsetAsync(c->stop_count, 0, sizeof(int) * nrhs, s));
+        buf_after.clear();
         return MG_OK;
     }
 
@@ -720,52 +741,71 @@ struct SolveRun {
         LevelBuf& l0 = c->lv[0];
         const LevelOp<double> op0 = level_op<double>(c, 0);
         LaunchCtx l2 = ctx(st);
+        // the closing norm pass takes the stop test
+        LaunchCtx lt = l2;
+        lt.stop = StopTest{c->h_ring, c->active, c->stop_count, c->stop_limits, c->max_batch};
         if (fp32) {
             launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
             cycle<float>(c, l2, 0, cp);
             cplx<double>* xin = c->cur_buf == 0 ? l0.u64 : l0.t64;
             cplx<double>* xout = c->cur_buf == 0 ? l0.t64 : l0.u64;
-            launch_correct_residual(l2, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0), vec<double>(xout, l0),
+            launch_correct_residual(lt, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0), vec<double>(xout, l0),
                                     vec<double>(l0.f64, l0), vec<float>(l0.f32, l0), c->norms);
             c->cur_buf ^= 1;
         } else {
             cycle<double>(c, l2, 0, cp);
-            launch_resnorm<double>(l2, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
+            launch_resnorm<double>(lt, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
         }
     }
 
-    mg_status read_norms(hipStream_t s) {
-        HM_HIP(hipMemcpyAsync(c->h_norms, c->norms, sizeof(RhsNorms) * nrhs, hipMemcpyDeviceToHost, s));
-        return MG_OK;
+    // cycle `it` (1-based) has been enqueued (eagerly or as a graph replay)
+    void enqueued(int it) {
+        if ((int)buf_after.size() < it) buf_after.resize(it, 0);
+        buf_after[it - 1] = c->cur_buf;
     }
 
-    // after cycle `it` (1-based) and a synchronisation of the stream
-    mg_status after_cycle(int it, hipStream_t s, mg_solve_stats* stats) {
+    // after cycle `it` has completed: the device's stop decisions and norms.
+    // A right-hand side's iterate stays where its stopping cycle left it,
+    // since later cycles skip it.
+    mg_status after_cycle(int it, mg_solve_stats* stats) {
         harvest_timing(c);
-        bool changed = false;
         for (int b = 0; b < nrhs; ++b) {
             if (state[b] != 0) {
                 if (stats && stats->history) stats->history[(size_t)(it - 1) * nrhs + b] = NAN;
                 continue;
             }
-            const double r = std::sqrt(c->h_norms[b].r2 / c->h_norms[b].f2);
+            const RhsReport rep = c->h_ring[((it - 1) % kReportRing) * c->max_batch + b];
+            if (rep.cycle != it) {
+                c->err = "stop-test report out of sequence";
+                return MG_E_HIP;
+            }
+            const double r = std::sqrt(rep.r2 / rep.f2);
+            rel_prev[b] = rel[b];
             rel[b] = r;
             cycles[b] = it;
             if (stats && stats->history) stats->history[(size_t)(it - 1) * nrhs + b] = r;
-            int ns = 0;
-            if (!std::isfinite(r) || r > o.divergence * rel0[b]) ns = 2;
-            else if (r <= tol) ns = 1;
-            if (ns) {
-                state[b] = ns;
+            if (rep.stop) {
+                state[b] = rep.stop;
                 c->h_active[b] = 0;
-                c->final_buf[b] = c->cur_buf;
+                c->final_buf[b] = buf_after[it - 1];
                 --running;
-                changed = true;
             }
         }
-        if (changed && running > 0)
-            HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
         return MG_OK;
+    }
+
+    // Whether the cycle after the next one is worth queueing now: false when
+    // every running right-hand side, its relative residual extrapolated by its
+    // last contraction factor, is expected within twice the tolerance after
+    // the next cycle (a cycle queued behind the last one does no work but
+    // still costs most of a cycle's launches).
+    bool continues_past_next() const {
+        for (int b = 0; b < nrhs; ++b) {
+            if (state[b] != 0) continue;
+            const double q = rel_prev[b] > 0.0 ? rel[b] / rel_prev[b] : 1.0;
+            if (!(rel[b] * q <= 2.0 * tol)) return true;
+        }
+        return false;
     }
 
     // enqueues the gather of the final iterates (no synchronisation)
@@ -817,14 +857,24 @@ mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, in
     HM_HIP(hipStreamSynchronize(s));
     if (mg_status st = run.begin(s)) return st;
     auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
-    int it = 0;
+    // One cycle is queued ahead of the one whose reports the host waits for,
+    // so the GPU does not idle through the host's turn-around, except where
+    // the next cycle is expected to be the last. Per-kernel timing (eager
+    // launches with events) stays in step.
+    const bool may_run_ahead = c->timing_class == 0;
+    int it = 0, enq = 0;
     while (run.running > 0 && it < o.max_cycles) {
+        const int ahead = may_run_ahead && run.continues_past_next() ? 1 : 0;
+        while (enq < o.max_cycles && enq <= it + ahead) {
+            ++enq;
+            if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
+            if (mg_status st = check_launch(c)) return st;
+            run.enqueued(enq);
+            HM_HIP(hipEventRecord(c->cycle_done[enq & 1], s));
+        }
         ++it;
-        if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
-        if (mg_status st = check_launch(c)) return st;
-        if (mg_status st = run.read_norms(s)) return st;
-        HM_HIP(hipStreamSynchronize(s));
-        if (mg_status st = run.after_cycle(it, s, stats)) return st;
+        HM_HIP(hipEventSynchronize(c->cycle_done[it & 1]));
+        if (mg_status st = run.after_cycle(it, stats)) return st;
     }
     if (mg_status st = run.gather(s)) return st;
     HM_HIP(hipStreamSynchronize(s));
@@ -916,8 +966,14 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_active), sizeof(int) * max_batch, hipHostMallocDefault) !=
-            hipSuccess) {
-        g_setup_error = "hipHostMalloc failed";
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_limits), sizeof(double) * 2 * max_batch, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_ring), sizeof(RhsReport) * kReportRing * max_batch,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&c->cycle_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->cycle_done[1], hipEventDisableTiming) != hipSuccess) {
+        g_setup_error = "pinned host buffers or events could not be created";
         mg_destroy(c);
         return MG_E_HIP;
     }
@@ -1121,11 +1177,11 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
             for (int p : R) runs[p].enqueue_cycle(s);
         for (int p : R) {
             if (mg_status st = check_launch(runs[p].c)) return st;
-            if (mg_status st = runs[p].read_norms(s)) return st;
+            runs[p].enqueued(it);
         }
         HM_HIP(hipStreamSynchronize(s));
         for (int p : R)
-            if (mg_status st = runs[p].after_cycle(it, s, stats ? stats + p : nullptr)) return st;
+            if (mg_status st = runs[p].after_cycle(it, stats ? stats + p : nullptr)) return st;
     }
     for (SolveRun& r : runs)
         if (mg_status st = r.gather(s)) return st;
@@ -1529,6 +1585,10 @@ mg_status mg_destroy(mg_handle c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->h_norms) (void)hipHostFree(c->h_norms);
     if (c->h_active) (void)hipHostFree(c->h_active);
+    if (c->h_limits) (void)hipHostFree(c->h_limits);
+    if (c->h_ring) (void)hipHostFree(c->h_ring);
+    for (hipEvent_t e : c->cycle_done)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return MG_OK;
 }
