@@ -124,35 +124,52 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
     const int nf = op.fine.g.n;
     const int fx0 = 2 * tl.c0 - 3, fy0 = 2 * tl.r0 - 3;  // fine origin of y
     // y = P x: even fine index 2K takes (1/8, 3/4, 1/8) of K-1, K, K+1 (Bezier)
-    // or x_K (linear); odd 2K+1 takes (x_K + x_{K+1}) / 2. Zero off the fine grid.
-    const int ny = PS::YW * PS::yrows(rows);
-    for (int q = tid; q < ny; q += nt) {
-        const int fi = fx0 + q % PS::YW, fj = fy0 + q / PS::YW;
-        cplx<T> acc{T(0), T(0)};
-        if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
-            T wx[3], wy[3];
-            const bool ox = fi & 1, oy = fj & 1;
-            wx[0] = ox ? T(0) : (kBez ? T(0.125) : T(0));
-            wx[1] = ox ? T(0.5) : (kBez ? T(0.75) : T(1));
-            wx[2] = ox ? T(0.5) : (kBez ? T(0.125) : T(0));
-            wy[0] = oy ? T(0) : (kBez ? T(0.125) : T(0));
-            wy[1] = oy ? T(0.5) : (kBez ? T(0.75) : T(1));
-            wy[2] = oy ? T(0.5) : (kBez ? T(0.125) : T(0));
-            const int base = tl.at((fi >> 1) - 1, (fj >> 1) - 1);
+    // or x_K (linear); odd 2K+1 takes (x_K + x_{K+1}) / 2. Zero off the fine
+    // grid. One step forms the 2 x 2 fine nodes 2K + {0, 1}, 2L + {0, 1} from
+    // the 3 x 3 coarse values around (K, L), rows first. K = c0 - 2 .. c0 + 64
+    // and L = r0 - 2 .. r0 + rows cover y; the fine column and row 2 c0 - 4,
+    // 2 r0 - 4 of the first steps lie outside it and are dropped.
+    constexpr int PX = kBX + 3;
+    const int np = PX * (rows + 3);
+    const int ny = PS::yrows(rows);
+    auto put = [&](int fi, int fj, cplx<T> val) {
+        const int a = fi - fx0, bq = fj - fy0;
+        if (a < 0 || bq < 0 || a >= PS::YW || bq >= ny) return;
+        const bool in = fi >= 0 && fj >= 0 && fi <= nf && fj <= nf;
+        y[bq * PS::YW + a] = in ? val : cplx<T>{T(0), T(0)};
+    };
+    for (int q = tid; q < np; q += nt) {
+        const int K = tl.c0 - 2 + q % PX, L = tl.r0 - 2 + q / PX;
+        const int base = tl.at(K - 1, L - 1);
+        cplx<T> he[3], ho[3];  // rows L - 1 .. L + 1 at fine columns 2K, 2K + 1
 #pragma unroll
-            for (int ty = 0; ty < 3; ++ty) {
-                cplx<T> row{T(0), T(0)};
-#pragma unroll
-                for (int tx = 0; tx < 3; ++tx) {
-                    const cplx<T> xv = lds[base + ty * Tile<3>::TW + tx];
-                    row.re += wx[tx] * xv.re;
-                    row.im += wx[tx] * xv.im;
-                }
-                acc.re += wy[ty] * row.re;
-                acc.im += wy[ty] * row.im;
+        for (int t = 0; t < 3; ++t) {
+            const cplx<T> xa = lds[base + t * Tile<3>::TW];
+            const cplx<T> xb = lds[base + t * Tile<3>::TW + 1];
+            const cplx<T> xc = lds[base + t * Tile<3>::TW + 2];
+            if (kBez) {
+                he[t].re = T(0.125) * xa.re + T(0.75) * xb.re + T(0.125) * xc.re;
+                he[t].im = T(0.125) * xa.im + T(0.75) * xb.im + T(0.125) * xc.im;
+            } else {
+                he[t] = xb;
             }
+            ho[t].re = T(0.5) * (xb.re + xc.re);
+            ho[t].im = T(0.5) * (xb.im + xc.im);
         }
-        y[q] = acc;
+        cplx<T> e0, o0;  // fine row 2L
+        if (kBez) {
+            e0.re = T(0.125) * he[0].re + T(0.75) * he[1].re + T(0.125) * he[2].re;
+            e0.im = T(0.125) * he[0].im + T(0.75) * he[1].im + T(0.125) * he[2].im;
+            o0.re = T(0.125) * ho[0].re + T(0.75) * ho[1].re + T(0.125) * ho[2].re;
+            o0.im = T(0.125) * ho[0].im + T(0.75) * ho[1].im + T(0.125) * ho[2].im;
+        } else {
+            e0 = he[1];
+            o0 = ho[1];
+        }
+        put(2 * K, 2 * L, e0);
+        put(2 * K + 1, 2 * L, o0);
+        put(2 * K, 2 * L + 1, cplx<T>{T(0.5) * (he[1].re + he[2].re), T(0.5) * (he[1].im + he[2].im)});
+        put(2 * K + 1, 2 * L + 1, cplx<T>{T(0.5) * (ho[1].re + ho[2].re), T(0.5) * (ho[1].im + ho[2].im)});
     }
     __syncthreads();
     // v = C_s y = A_s y - i beta2 W k^2 y on fine nodes of the grid, zero elsewhere
