@@ -172,31 +172,55 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
         put(2 * K + 1, 2 * L + 1, cplx<T>{T(0.5) * (ho[1].re + ho[2].re), T(0.5) * (ho[1].im + ho[2].im)});
     }
     __syncthreads();
-    // v = C_s y = A_s y - i beta2 W k^2 y on fine nodes of the grid, zero elsewhere
-    // k^2 of kVBatch fine nodes is loaded before their arithmetic (nodes off
-    // the fine grid read a clamped in-grid node and give zero)
-    constexpr int kVBatch = 8;
-    const int nv = PS::VW * PS::vrows(rows);
-    T kk[kVBatch];
-    for_strided_batched<kVBatch>(
-        nv,
+    // v = C_s y = A_s y - i beta2 W k^2 y on fine nodes of the grid, zero
+    // elsewhere. One step takes the 2 x 2 fine nodes 2K + {0, 1}, 2L + {0, 1}
+    // with their 12 distinct y neighbours, K = c0 - 1 .. c0 + 64 and
+    // L = r0 - 1 .. r0 + rows; the last fine column and row of these steps lie
+    // outside v and are dropped (their neighbours beyond y are read clamped).
+    // k^2 of kVBlocks steps is loaded before their arithmetic (nodes off the
+    // fine grid read a clamped in-grid node and give zero).
+    constexpr int VX = kBX + 2;
+    constexpr int kVBlocks = 2;
+    const int nvb = VX * (rows + 2);
+    T kk[kVBlocks][4];
+    auto yat = [&](int c, int r) { return y[min(r, ny - 1) * PS::YW + min(c, PS::YW - 1)]; };
+    auto cs_node = [&](int i, int j, T k2v, cplx<T> c, cplx<T> xw, cplx<T> xe, cplx<T> xs, cplx<T> xn) {
+        cplx<T> r{T(0), T(0)};
+        if (i >= 0 && j >= 0 && i <= nf && j <= nf) {
+            r = op.fine.apply5k(i, j, k2v, c, xw, xe, xs, xn);
+            const T sw = op.shift * line_w<T>(i, nf) * line_w<T>(j, nf) * k2v;
+            r.re += sw * c.im;
+            r.im -= sw * c.re;
+        }
+        return r;
+    };
+    for_strided_batched<kVBlocks>(
+        nvb,
         [&](int u, int q) {
-            const int fi = fx0 + 1 + q % PS::VW, fj = fy0 + 1 + q / PS::VW;
-            kk[u] = op.fine.k2[op.fine.g.at(min(max(fi, 0), nf), min(max(fj, 0), nf))];
+            const int fi = 2 * (tl.c0 - 1 + q % VX), fj = 2 * (tl.r0 - 1 + q / VX);
+            const int i0 = min(max(fi, 0), nf), i1 = min(max(fi + 1, 0), nf);
+            const int j0 = min(max(fj, 0), nf), j1 = min(max(fj + 1, 0), nf);
+            kk[u][0] = op.fine.k2[op.fine.g.at(i0, j0)];
+            kk[u][1] = op.fine.k2[op.fine.g.at(i1, j0)];
+            kk[u][2] = op.fine.k2[op.fine.g.at(i0, j1)];
+            kk[u][3] = op.fine.k2[op.fine.g.at(i1, j1)];
         },
         [&](int u, int q) {
-            const int a = q % PS::VW, bb = q / PS::VW;
-            const int fi = fx0 + 1 + a, fj = fy0 + 1 + bb;
-            cplx<T> r{T(0), T(0)};
-            if (fi >= 0 && fj >= 0 && fi <= nf && fj <= nf) {
-                const int yi = (bb + 1) * PS::YW + a + 1;
-                const cplx<T> yc = y[yi];
-                r = op.fine.apply5k(fi, fj, kk[u], yc, y[yi - 1], y[yi + 1], y[yi - PS::YW], y[yi + PS::YW]);
-                const T sw = op.shift * line_w<T>(fi, nf) * line_w<T>(fj, nf) * kk[u];
-                r.re += sw * yc.im;
-                r.im -= sw * yc.re;
+            const int bx = q % VX, by = q / VX;
+            const int fi = 2 * (tl.c0 - 1 + bx), fj = 2 * (tl.r0 - 1 + by);
+            const int c = 2 * bx + 1, r = 2 * by + 1;  // y column and row of (fi, fj)
+            const cplx<T> s0 = yat(c, r - 1), s1 = yat(c + 1, r - 1);
+            const cplx<T> w0 = yat(c - 1, r), c00 = yat(c, r), c10 = yat(c + 1, r), e0 = yat(c + 2, r);
+            const cplx<T> w1 = yat(c - 1, r + 1), c01 = yat(c, r + 1), c11 = yat(c + 1, r + 1), e1 = yat(c + 2, r + 1);
+            const cplx<T> n0 = yat(c, r + 2), n1 = yat(c + 1, r + 2);
+            const int vi = 2 * by * PS::VW + 2 * bx;
+            const bool east = bx < VX - 1, north = by < rows + 1;
+            v[vi] = cs_node(fi, fj, kk[u][0], c00, w0, c10, s0, c01);
+            if (east) v[vi + 1] = cs_node(fi + 1, fj, kk[u][1], c10, c00, e0, s1, c11);
+            if (north) {
+                v[vi + PS::VW] = cs_node(fi, fj + 1, kk[u][2], c01, w1, c11, c00, n0);
+                if (east) v[vi + PS::VW + 1] = cs_node(fi + 1, fj + 1, kk[u][3], c11, c01, e1, c10, n1);
             }
-            v[q] = r;
         });
     __syncthreads();
     // (R v)_I = (1/4) sum of the prolongation weights of I times v

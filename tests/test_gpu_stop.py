@@ -1,0 +1,49 @@
+"""The stop test of a solve (§5: relative residual after each cycle against the
+tolerance) is taken on the device while the host keeps a cycle queued ahead.
+A solve stopped by its cycle cap and one stopped by its tolerance at the same
+cycle hand back the same iterate, bit for bit, in both precisions and at both
+parities of the FP64 iterate's ping-pong buffer (the iterate stays where the
+stopping cycle left it, also when a further cycle was already queued). The
+FP64 iterate equals the oracle's after that many cycles, and the history ends
+at the stopping cycle with the reported relative residual."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2308_13476_amd import workloads as W
+from tests.gpu_common import require_gpu, to_gpu, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("stop_at", [5, 6])
+@pytest.mark.parametrize("precision,smoother,k", [("fp64", "gmres", 30.0), ("fp64", "jacobi", 12.0),
+                                                  ("fp32_refined", "gmres", 30.0)])
+def test_cap_and_tolerance_stops_agree(precision, smoother, k, stop_at):
+    """Jacobi runs at k = 12, where its residual decreases every cycle (at
+    k = 30 it stalls after three)."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    n = 128
+    k2 = W.constant_k2(n, k)
+    f = W.point_source_rhs(n, [W.center_node(n)])
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, precision=precision)
+    kw = dict(precision=precision, smoother=smoother, history=True)
+    xc, ic = S.solve(to_gpu(f), tol=1e-30, max_cycles=stop_at, raise_on_error=False, **kw)
+    assert ic["status_name"] == "MG_NOT_CONVERGED" and ic["cycles"] == [stop_at], ic
+    h = ic["history"][0]
+    assert len(h) == stop_at and np.all(np.isfinite(h))
+    assert ic["relres"][0] == h[-1]
+    assert h[-1] < min(h[:-1]), h  # a tolerance between the last two residuals stops exactly here
+    tol = 0.5 * (h[-1] + min(h[:-1]))
+    xt, it = S.solve(to_gpu(f), tol=tol, max_cycles=100, **kw)
+    assert it["status"] == 0 and it["cycles"] == [stop_at], it
+    assert it["history"][0] == h
+    assert torch.equal(xt, xc)
+    if precision == "fp64":
+        H = O.build_hierarchy(k2, 1.0 / n, 1.0 / k)
+        fs = O.scaled_rhs(f[0]).ravel()
+        ref = O.solve(H, fs, O.CycleOptions(smoother=smoother), tol=1e-30, max_cycles=stop_at)
+        x = to_np(xc)[0].ravel()
+        assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-10
