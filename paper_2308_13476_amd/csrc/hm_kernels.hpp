@@ -123,12 +123,14 @@ struct ProlongIn {
 // roles of u and pro.xt). r_ready_nblk > 0
 // means u = 0 and the residual pass already ran as part of the restriction
 // (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
-// starts with the second pass.
+// starts with the second pass. u_zero: the step starts from u = 0 although u
+// does not hold zeros (its update pass then writes sum y_i s_i z_i without
+// reading u; only with res unset).
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
                        Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0,
-                       ProlongIn<T> pro = ProlongIn<T>{});
+                       ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>
@@ -136,12 +138,17 @@ void launch_resnorm(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Rhs
 // ||f||^2 into norms[b].f2.
 template <typename T> void launch_norm(const LaunchCtx&, Grid g, Vec<T> f, RhsNorms* norms);
 
-// FP32-in-FP64 refinement: r = f - A_s x in FP64, stored as complex64, norm into norms[b].r2.
-void launch_refine_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x, Vec<double> f,
-                            Vec<float> r32, RhsNorms* norms);
+// FP32-in-FP64 refinement: r = f - A_s x in FP64, stored as complex64, norm
+// into norms[b].r2. With z0.p set (the level-0 Arnoldi planes of the FP32
+// cycle), r also becomes that cycle's first residual z_0 (its iterate starting
+// at zero) with the partial sums of ||z_0||^2 in region 0, and the norm's
+// partials use region 1. Returns the number of partial sums per right-hand side.
+int launch_refine_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x, Vec<double> f, Vec<float> r32,
+                           RhsNorms* norms, Vec<float> z0 = Vec<float>{nullptr, 0});
 // x_out = x_in + e (e complex64), then r = f - A_s x_out as above.
-void launch_correct_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x_in, Vec<float> e,
-                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms);
+int launch_correct_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x_in, Vec<float> e,
+                            Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms,
+                            Vec<float> z0 = Vec<float>{nullptr, 0});
 
 // Layout conversion between the caller's dense [b][n+1][n+1] arrays and the
 // padded planes. src_is_f32 / dst_is_f32 select complex64 on the caller side.

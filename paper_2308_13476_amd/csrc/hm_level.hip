@@ -812,7 +812,7 @@ __device__ __forceinline__ int gm_update_weights(const GmState* st, int b, doubl
 }
 
 // Pass 5: u += sum y_i s_i z_i.
-template <typename T, int BY>
+template <typename T, int BY, bool kFromZero = false>
 __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, Vec<T> uin, const GmState* st,
                                                    double breakdown, const double* pin, int nblk_in, const int* active,
                                                    int rpt) {
@@ -820,9 +820,10 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, V
     const bool act = rhs_active(active, b);
     cplx<T> c[3];
     const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
-    // in place (uin.p null) nothing changes for k = 0; from a separate uin the
-    // iterate is always written
-    if (!act || (k == 0 && !uin.p)) return;
+    // in place (uin.p null) nothing changes for k = 0; from a separate uin or
+    // from zero (kFromZero: the step began at u = 0, which u does not hold)
+    // the iterate is always written
+    if (!act || (k == 0 && !uin.p && !kFromZero)) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
@@ -833,7 +834,8 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, V
     for_nodes_batched<NB>(
         g, rpt,
         [&](int v, long long p) {
-            xu[v] = ib[p];
+            if constexpr (kFromZero) xu[v] = {T(0), T(0)};
+            else xu[v] = ib[p];
             x0[v] = z0[p];
             x1[v] = z1[p];
             x2[v] = z2[p];
@@ -952,31 +954,43 @@ __global__ __launch_bounds__(kThreads) void k_sum_norms(const double* pin, int n
 }
 
 // ---------------------------------------------------------------- refinement
+// r32 = f - A_s x (complex64), partial sums of ||f - A_s x||^2 to pout. With
+// Z.p set, r32 also goes to the first Arnoldi plane of the FP32 cycle that
+// follows (z_0 = r32 - A 0) and the partial sums of ||z_0||^2 to pz, so that
+// the cycle's first GMRES step starts with its second pass.
 template <int BY>
 __global__ __launch_bounds__(kBX * BY) void k_refine_residual(FineOp<double> op, Vec<double> x, Vec<double> f,
-                                                              Vec<float> r32, double* pout, const int* active,
-                                                              int rpt) {
+                                                              Vec<float> r32, Vec<float> Z, double* pout, double* pz,
+                                                              const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<double>* xb = x.rhs(b);
     const cplx<double>* fb = f.rhs(b);
     cplx<float>* rb = r32.rhs(b);
-    double acc[1] = {0.0};
+    cplx<float>* zb = Z.p ? Z.p + (long long)(b * 4) * Z.plane : nullptr;
+    double acc[1] = {0.0}, accz[1] = {0.0};
     for_nodes_applied_pre<FineOp<double>, double>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
                                                   [fb](long long q) { return fb[q]; },
                                                   [&](int, int, long long p, cplx<double> fp, cplx<double>,
                                                       cplx<double> ax) {
                                                   const cplx<double> r = fp - ax;
-                                                  rb[p] = cast<float>(r);
+                                                  const cplx<float> r1 = cast<float>(r);
+                                                  rb[p] = r1;
                                                   acc[0] += dnorm2(r);
+                                                  if (zb) {
+                                                      zb[p] = r1;
+                                                      accz[0] += dnorm2(r1);
+                                                  }
                                               });
     block_partials<1>(acc, pout + b * kPartStride);
+    if (zb) block_partials<1>(accz, pz + b * kPartStride);
 }
 
 template <int BY>
 __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op, Vec<double> x_in, Vec<float> e,
                                                                Vec<double> x_out, Vec<double> f, Vec<float> r32,
-                                                               double* pout, const int* active, int rpt) {
+                                                               Vec<float> Z, double* pout, double* pz,
+                                                               const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const cplx<double>* xb = x_in.rhs(b);
@@ -984,7 +998,8 @@ __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op
     cplx<double>* ob = x_out.rhs(b);
     const cplx<double>* fb = f.rhs(b);
     cplx<float>* rb = r32.rhs(b);
-    double acc[1] = {0.0};
+    cplx<float>* zb = Z.p ? Z.p + (long long)(b * 4) * Z.plane : nullptr;
+    double acc[1] = {0.0}, accz[1] = {0.0};
     struct XE {
         cplx<double> x;
         cplx<float> e;
@@ -996,10 +1011,16 @@ __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op
                                                       cplx<double> ax) {
                                                   ob[p] = xp;
                                                   const cplx<double> r = fp - ax;
-                                                  rb[p] = cast<float>(r);
+                                                  const cplx<float> r1 = cast<float>(r);
+                                                  rb[p] = r1;
                                                   acc[0] += dnorm2(r);
+                                                  if (zb) {
+                                                      zb[p] = r1;
+                                                      accz[0] += dnorm2(r1);
+                                                  }
                                               });
     block_partials<1>(acc, pout + b * kPartStride);
+    if (zb) block_partials<1>(accz, pz + b * kPartStride);
 }
 
 // ---------------------------------------------------------------- layout
@@ -1142,7 +1163,7 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
-                       Vec<T> unew, Vec<T> res, int r_ready_nblk, ProlongIn<T> pro) {
+                       Vec<T> unew, Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
@@ -1206,13 +1227,16 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             HM_LAUNCH_OP(q, (k_gm_u_res<Op, T, BY>), op, Z, u, f, unew, res, st, breakdown, B, nb, HM_ACTIVE,
                          q.rpt);
     });
-    if (!res.p) HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
+    if (!res.p && u_zero)
+        HM_LAUNCH(qv, (k_gm_u<T, BY, true>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
+    else if (!res.p)
+        HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
 }
 
-void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which) {
+void launch_sum_norms(const LaunchCtx& ctx, int nb, RhsNorms* norms, int which, int reg = 0) {
     // 64 x 4 threads: the block reduction indexes wavefronts by threadIdx.y
-    hipLaunchKernelGGL(k_sum_norms, dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, region(ctx, 0), nb, norms, which,
-                       HM_ACTIVE, which == 1 ? ctx.stop : StopTest{});
+    hipLaunchKernelGGL(k_sum_norms, dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, region(ctx, reg), nb, norms,
+                       which, HM_ACTIVE, which == 1 ? ctx.stop : StopTest{});
 }
 
 template <typename T>
@@ -1234,24 +1258,31 @@ void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
     launch_sum_norms(ctx, q.nblk, norms, 0);
 }
 
-void launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
-                            Vec<float> r32, RhsNorms* norms) {
+// With z0.p set the residual norms use region 1 and z_0's region 0 (where the
+// first GMRES step of the next FP32 cycle reads them).
+int launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
+                           Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
     const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
-    launch_sum_norms(ctx, q.nblk, norms, 1);
+    const int rn = z0.p ? 1 : 0;
+    HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, z0, region(ctx, rn), region(ctx, 0), HM_ACTIVE, q.rpt);
+    launch_sum_norms(ctx, q.nblk, norms, 1, rn);
+    return q.nblk;
 }
 
-void launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
-                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms) {
+int launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
+                            Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
     const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
-    HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, region(ctx, 0), HM_ACTIVE, q.rpt);
-    launch_sum_norms(ctx, q.nblk, norms, 1);
+    const int rn = z0.p ? 1 : 0;
+    HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, z0, region(ctx, rn), region(ctx, 0),
+                 HM_ACTIVE, q.rpt);
+    launch_sum_norms(ctx, q.nblk, norms, 1, rn);
+    return q.nblk;
 }
 
 template <typename T>
@@ -1309,7 +1340,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
                                        Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>,   \
-                                       int, ProlongIn<T>);                                                      \
+                                       int, ProlongIn<T>, bool);                                                \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

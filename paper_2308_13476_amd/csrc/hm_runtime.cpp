@@ -430,9 +430,11 @@ struct CycleParams {
 // One smoothing step on level l. With then_residual (GMRES only), the step's
 // last pass also forms the residual f - A u into the level's w buffer; the
 // updated iterate then lands in t and the u / t buffers exchange roles.
+// u_zero (GMRES, without then_residual): the step starts from u = 0, which u
+// does not hold.
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
-            int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}) {
+            int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -477,7 +479,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, timed ? &Hook::cb : nullptr, &hook,
                          then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0},
-                         r_ready_nblk, pro);
+                         r_ready_nblk, pro, u_zero && !then_residual);
     if (then_residual) {
         std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
@@ -520,10 +522,12 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
     launch_tail<T>(lc, a);
 }
 
-// r_ready_nblk > 0: level l was entered with u = 0 and the restriction also
-// formed the first GMRES residual (see launch_restrict).
+// r_ready_nblk > 0: level l was entered with u = 0 and the restriction (or,
+// on level 0 of an FP32 cycle, the FP64 residual pass before it) also formed
+// the first GMRES residual. u_zero: u itself does not hold those zeros (level
+// 0 only, where no pre-smoothing step forms the residual to restrict).
 template <typename T>
-void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0) {
+void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false) {
     if (l == c->tail_level[sizeof(T) == 4]) {
         launch_tail_from<T>(c, lc, l, cp);
         return;
@@ -537,7 +541,9 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     // on Galerkin levels the last GMRES pre-smoothing step also forms the
     // residual to restrict
     const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && l > 0;
-    for (int s = 0; s < cp.nu1; ++s) smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0);
+    for (int s = 0; s < cp.nu1; ++s)
+        smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
+                  s == 0 && u_zero && !fused);
     if (!fused)
         launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                            vec<T>(Prec<T>::w(lb), lb));
@@ -666,6 +672,11 @@ struct SolveRun {
     std::vector<int> cycles, state;  // state: 0 running, 1 converged, 2 diverged
     std::vector<int> buf_after;      // cur_buf after each enqueued cycle
     int running = 0;
+    // FP32 cycles whose first level-0 GMRES residual comes from the FP64
+    // residual pass before them (u = 0 is not stored; no zeroing pass), and
+    // that pass's partial sums per right-hand side
+    bool z_ready = false;
+    int z_nblk = 0;
     std::vector<uintptr_t> key;
     std::chrono::steady_clock::time_point t0;
 
@@ -678,6 +689,10 @@ struct SolveRun {
                uintptr_t(omega_bits), uintptr_t(nrhs), uintptr_t(c->timing_class)};
     }
     LaunchCtx ctx(hipStream_t s) const { return launch_ctx(c, s, nrhs); }
+    Vec<float> z_plane() const {
+        LevelBuf& l0 = c->lv[0];
+        return z_ready ? vec<float>(Prec<float>::V(l0), l0) : Vec<float>{nullptr, 0};
+    }
 
     mg_status start(hipStream_t s) {
         t0 = std::chrono::steady_clock::now();
@@ -689,9 +704,11 @@ struct SolveRun {
         HM_HIP(hipMemcpyAsync(c->active, c->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, s));
         LaunchCtx lc = ctx(s);
         launch_norm<double>(lc, l0.g, vec<double>(l0.f64, l0), c->norms);
-        if (fp32)
-            launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0),
-                                   vec<float>(l0.f32, l0), c->norms);
+        if (fp32) {
+            z_ready = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && c->L > 1 && c->tail_level[1] != 0;
+            z_nblk = launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0),
+                                            vec<float>(l0.f32, l0), c->norms, z_plane());
+        }
         else
             launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
         if (mg_status st = check_launch(c)) return st;
@@ -745,12 +762,13 @@ struct SolveRun {
         LaunchCtx lt = l2;
         lt.stop = StopTest{c->h_ring, c->active, c->stop_count, c->stop_limits, c->max_batch};
         if (fp32) {
-            launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
-            cycle<float>(c, l2, 0, cp);
+            if (!z_ready) launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
+            cycle<float>(c, l2, 0, cp, z_ready ? z_nblk : 0, z_ready);
             cplx<double>* xin = c->cur_buf == 0 ? l0.u64 : l0.t64;
             cplx<double>* xout = c->cur_buf == 0 ? l0.t64 : l0.u64;
-            launch_correct_residual(lt, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0), vec<double>(xout, l0),
-                                    vec<double>(l0.f64, l0), vec<float>(l0.f32, l0), c->norms);
+            z_nblk = launch_correct_residual(lt, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0),
+                                             vec<double>(xout, l0), vec<double>(l0.f64, l0), vec<float>(l0.f32, l0),
+                                             c->norms, z_plane());
             c->cur_buf ^= 1;
         } else {
             cycle<double>(c, l2, 0, cp);
