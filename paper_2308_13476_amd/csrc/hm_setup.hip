@@ -253,87 +253,94 @@ __global__ __launch_bounds__(kNodeThreads) void k_galerkin_node(Grid gf, const c
     }
 }
 
-// The same product on small coarse grids, one thread per coarse node and
-// stencil row dy: the rows s_y = 2 dy + t (|t| <= RA) of G, each reduced over
-// s_x into the row's D_c coefficients, in the node kernel's order (equal
-// results). Few coarse nodes fill little of the GPU, and one node per thread
-// holds D_c^2 accumulators, leaving few registers for loads in flight; a
-// row per thread holds D_c.
+// The same product on small coarse grids, where a node kernel's long
+// per-thread chain of loads sets the time: one thread per coarse node,
+// stencil row dy and y-mask tap t. It forms the row s_y = 2 dy + t of G,
+// reduces it over s_x and scales it by m(t); the taps of a row are then summed
+// in LDS in ascending t (a fixed order). A block holds 64 (node, row) pairs
+// times the taps, threadIdx.y being the tap.
+constexpr int kSplitLanes = 64;
+
 template <bool kBez, int RF>
-__global__ __launch_bounds__(kThreads) void k_galerkin_rows(Grid gf, const cplx<double>* coef, Grid gc,
-                                                            cplx<double>* out) {
-    constexpr int RA = kBez ? 2 : 1;
+__global__ __launch_bounds__(kSplitLanes * (kBez ? 5 : 3)) void k_galerkin_split(Grid gf, const cplx<double>* coef,
+                                                                                Grid gc, cplx<double>* out) {
+    constexpr int RA = kBez ? 2 : 1;  // restriction taps and nonzero y-mask taps: |t| <= RA
+    constexpr int NT = 2 * RA + 1;
     constexpr int RS = RA + RF;
     constexpr int NS = 2 * RS + 1;
     constexpr int RC = (2 * RA + RF) / 2;
     constexpr int DC = 2 * RC + 1;
     constexpr int DF = 2 * RF + 1;
+    __shared__ cplx<double> part[NT][DC][kSplitLanes];
     const long long mc = gc.n + 1;
     const int nf = gf.n, nc = gc.n;
-    for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < mc * mc * DC;
-         q += (long long)gridDim.x * kThreads) {
-        const long long node = q % (mc * mc);
-        const int dy = int(q / (mc * mc)) - RC;
-        const int Ix = int(node % mc), Iy = int(node / mc);
-        cplx<double> acc[DC];
+    const int lane = threadIdx.x, ti = threadIdx.y, t = ti - RA;
+    const long long q = blockIdx.x * (long long)kSplitLanes + lane;  // (node, row) pair; the grid covers them once
+    const bool pair_ok = q < mc * mc * DC;
+    const long long node = pair_ok ? q % (mc * mc) : 0;
+    const int dy = pair_ok ? int(q / (mc * mc)) - RC : 0;
+    const int Ix = int(node % mc), Iy = int(node / mc);
+    const int sy = 2 * dy + t;
+    const bool row_ok = pair_ok && sy >= -RS && sy <= RS;
+    cplx<double> G[NS];
 #pragma unroll
-        for (int d = 0; d < DC; ++d) acc[d] = {0.0, 0.0};
+    for (int s = 0; s < NS; ++s) G[s] = {0.0, 0.0};
+    if (row_ok) {
 #pragma unroll
-        for (int t = -RA; t <= RA; ++t) {
-            const double wy = mask1(t, kBez);
-            if (wy == 0.0) continue;  // compile-time
-            const int sy = 2 * dy + t;
-            if (sy < -RS || sy > RS) continue;
-            cplx<double> G[NS];
+        for (int ay = -RA; ay <= RA; ++ay) {
+            const int ey = sy - ay;
+            const bool eok = ey >= -RF && ey <= RF;
+            const int eyc = min(max(ey, -RF), RF);
+            const int py = 2 * Iy + ay, qy = py + ey;
+            const bool yok = eok && py >= 0 && py <= nf && qy >= 0 && qy <= nf;
+            const int pyc = min(max(py, 0), nf);
+            const cplx<double>* crow = coef + (long long)((eyc + RF) * DF + RF) * gf.plane;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) G[s] = {0.0, 0.0};
+            for (int ax = -RA; ax <= RA; ++ax) {
+                const double rw = 0.25 * mask1(ax, kBez) * mask1(ay, kBez);
+                if (rw == 0.0) continue;  // compile-time
+                const int px = 2 * Ix + ax;
+                const bool pok = yok && px >= 0 && px <= nf;
+                const long long at = gf.at(min(max(px, 0), nf), pyc);
 #pragma unroll
-            for (int ay = -RA; ay <= RA; ++ay) {
-                const int ey = sy - ay;
-                if (ey < -RF || ey > RF) continue;
-                const int py = 2 * Iy + ay, qy = py + ey;
-                const bool yok = py >= 0 && py <= nf && qy >= 0 && qy <= nf;
-                const int pyc = min(max(py, 0), nf);
-                const cplx<double>* crow = coef + (long long)((ey + RF) * DF + RF) * gf.plane;
-#pragma unroll
-                for (int ax = -RA; ax <= RA; ++ax) {
-                    const double rw = 0.25 * mask1(ax, kBez) * mask1(ay, kBez);
-                    if (rw == 0.0) continue;  // compile-time
-                    const int px = 2 * Ix + ax;
-                    const bool pok = yok && px >= 0 && px <= nf;
-                    const long long at = gf.at(min(max(px, 0), nf), pyc);
-#pragma unroll
-                    for (int ex = -RF; ex <= RF; ++ex) {
-                        const int qx = px + ex;
-                        const bool ok = pok && qx >= 0 && qx <= nf;
-                        const cplx<double> v = crow[(long long)ex * gf.plane + at];
-                        G[ax + ex + RS].re += ok ? rw * v.re : 0.0;
-                        G[ax + ex + RS].im += ok ? rw * v.im : 0.0;
-                    }
+                for (int ex = -RF; ex <= RF; ++ex) {
+                    const int qx = px + ex;
+                    const bool ok = pok && qx >= 0 && qx <= nf;
+                    const cplx<double> v = crow[(long long)ex * gf.plane + at];
+                    G[ax + ex + RS].re += ok ? rw * v.re : 0.0;
+                    G[ax + ex + RS].im += ok ? rw * v.im : 0.0;
                 }
             }
-#pragma unroll
-            for (int dx = -RC; dx <= RC; ++dx) {
-                cplx<double> h{0.0, 0.0};
-#pragma unroll
-                for (int sx = -RS; sx <= RS; ++sx) {
-                    const double w = mask1(sx - 2 * dx, kBez);
-                    if (w == 0.0) continue;  // compile-time
-                    h.re += w * G[sx + RS].re;
-                    h.im += w * G[sx + RS].im;
-                }
-                acc[dx + RC].re += wy * h.re;
-                acc[dx + RC].im += wy * h.im;
-            }
         }
-        const int Ky = Iy + dy;
+    }
+    // y weight m(t) of this tap (0 for |t| > RA never occurs: NT covers |t| <= RA)
+    const double wy = kBez ? (t == 0 ? 0.75 : (t == 1 || t == -1) ? 0.5 : 0.125) : (t == 0 ? 1.0 : 0.5);
 #pragma unroll
-        for (int dx = -RC; dx <= RC; ++dx) {
-            const int Kx = Ix + dx;
-            const bool kin = Kx >= 0 && Kx <= nc && Ky >= 0 && Ky <= nc;
-            out[(long long)((dy + RC) * DC + dx + RC) * gc.plane + gc.at(Ix, Iy)] =
-                kin ? acc[dx + RC] : cplx<double>{0.0, 0.0};
+    for (int dx = -RC; dx <= RC; ++dx) {
+        cplx<double> h{0.0, 0.0};
+#pragma unroll
+        for (int sx = -RS; sx <= RS; ++sx) {
+            const double w = mask1(sx - 2 * dx, kBez);
+            if (w == 0.0) continue;  // compile-time
+            h.re += w * G[sx + RS].re;
+            h.im += w * G[sx + RS].im;
         }
+        part[ti][dx + RC][lane] = cplx<double>{wy * h.re, wy * h.im};
+    }
+    __syncthreads();
+    if (ti != 0 || !pair_ok) return;
+    const int Ky = Iy + dy;
+#pragma unroll
+    for (int dx = -RC; dx <= RC; ++dx) {
+        cplx<double> acc{0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            acc.re += part[k][dx + RC][lane].re;
+            acc.im += part[k][dx + RC][lane].im;
+        }
+        const int Kx = Ix + dx;
+        const bool kin = Kx >= 0 && Kx <= nc && Ky >= 0 && Ky <= nc;
+        out[(long long)((dy + RC) * DC + dx + RC) * gc.plane + gc.at(Ix, Iy)] = kin ? acc : cplx<double>{0.0, 0.0};
     }
 }
 
@@ -484,28 +491,28 @@ void launch_galerkin(hipStream_t s, int fine_level, Grid fine, int fine_radius, 
     }
     const unsigned node_blocks = (unsigned)std::min<long long>((mc * mc + kNodeThreads - 1) / kNodeThreads, 65536);
     const bool bez = transfer == 0;
-    // coarse grids of at most 128 intervals: one stencil row per thread
+    // coarse grids of at most 128 intervals: one stencil row and y tap per thread
     const bool rows = mc <= 129;
     const long long dc = 2 * coarse_radius + 1;
     auto run = [&](auto node_kernel, auto rows_kernel) {
         if (rows)
-            hipLaunchKernelGGL(rows_kernel, dim3(blocks_for(mc * mc * dc)), dim3(kThreads), 0, s, fine, fine_coef,
-                               coarse, coarse_coef);
+            hipLaunchKernelGGL(rows_kernel, dim3(unsigned((mc * mc * dc + kSplitLanes - 1) / kSplitLanes)),
+                               dim3(kSplitLanes, bez ? 5 : 3), 0, s, fine, fine_coef, coarse, coarse_coef);
         else
             hipLaunchKernelGGL(node_kernel, dim3(node_blocks), dim3(kNodeThreads), 0, s, fine, fine_coef, coarse,
                                coarse_coef);
     };
     if (fine_level > 0 && coarse_radius == (bez ? (4 + fine_radius) / 2 : (2 + fine_radius) / 2)) {
         if (bez && fine_radius == 2) {
-            run(k_galerkin_node<true, 2>, k_galerkin_rows<true, 2>);
+            run(k_galerkin_node<true, 2>, k_galerkin_split<true, 2>);
             return;
         }
         if (bez && fine_radius == 3) {
-            run(k_galerkin_node<true, 3>, k_galerkin_rows<true, 3>);
+            run(k_galerkin_node<true, 3>, k_galerkin_split<true, 3>);
             return;
         }
         if (!bez && fine_radius == 1) {
-            run(k_galerkin_node<false, 1>, k_galerkin_rows<false, 1>);
+            run(k_galerkin_node<false, 1>, k_galerkin_split<false, 1>);
             return;
         }
     }
