@@ -23,13 +23,17 @@
  * Conventions for every entry point:
  *  - Pointers marked [dev] are device pointers owned by the caller; the
  *    library never allocates device memory: all of its device state lives in
- *    the caller's workspace. [host] pointers are ordinary host memory.
+ *    the caller's workspace (a handle also holds a few small pinned host
+ *    arrays and two events, freed by mg_destroy). [host] pointers are
+ *    ordinary host memory.
  *  - Grid functions are row-major [batch][n+1][n+1] with x (index i) fastest,
  *    node (i, j) at x = i h, y = j h. Complex values are interleaved
  *    (re, im): complex128 = 2 doubles, complex64 = 2 floats.
  *  - All work is enqueued on the caller's HIP stream (NULL = default stream).
- *    mg_solve / mg_grad synchronise that stream once per cycle to read the
- *    residual norms. A handle must not be used from two threads at once.
+ *    mg_solve / mg_grad take the stop test on the device after every cycle
+ *    and synchronise with that stream once per cycle to read its result, with
+ *    up to one further cycle already enqueued (it skips right-hand sides that
+ *    have stopped). A handle must not be used from two threads at once.
  *  - Functions return an mg_status and never abort; argument checks happen
  *    before any HIP call. The detail of the last error is in mg_last_error().
  */
