@@ -375,8 +375,9 @@ def main():
     r32 = timed("fp32_refined", args.steps)
     print(f"bench: fp32-refined {r32['ms_per_step']:.2f} ms/step, {r32['cycles_per_solve']:.0f} cycles",
           file=sys.stderr, flush=True)
-    # the same steps again with HIP events around every launch of the roofline
-    # kernel (kernel-by-kernel launches instead of captured graphs)
+    # the same steps again, every launch of the roofline kernel recording a
+    # start and a stop HIP event with its own dispatch (kernel-by-kernel
+    # launches instead of captured graphs)
     rk = timed("fp32_refined", max(1, args.steps // 2), args.kernel_class)
     r64 = timed("fp64", max(2, args.steps // 2))
     print(f"bench: fp64 {r64['ms_per_step']:.2f} ms/step, {r64['cycles_per_solve']:.0f} cycles", file=sys.stderr,
@@ -434,7 +435,8 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kc["name"],
                            "avg_launch_us": avg_ms * 1e3, "launches": launches,
-                           "timed_in": "repeat of the timed steps with HIP events per launch (no graphs)"}
+                           "timed_in": "repeat of the timed steps; HIP start/stop events recorded by each "
+                                       "launch's own dispatch (hipExtLaunchKernelGGL), no graphs"}
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_cycles)

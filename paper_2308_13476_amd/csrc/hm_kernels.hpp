@@ -113,8 +113,10 @@ struct ProlongIn {
 // One GMRES(3) smoothing step (§5.3) on A u = f: five passes (residual; apply;
 // two fused orthogonalise + apply passes; last column + least squares + update).
 // Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
-// products A z. `between(arg, i)` (may be null) is called on the host after
-// the i-th launch of the Arnoldi passes (timing hook). With res.p set, the
+// products A z. timed (may be null): a start and a stop event that the
+// dispatch of the second orthogonalise + apply pass records itself
+// (hipExtLaunchKernelGGL), so that their interval is that kernel's execution
+// (timing hook; eager launches only). With res.p set, the
 // last pass writes the updated iterate to unew (u is left as it was) and the
 // residual f - A unew to res; unew and res may be Wb and Wa. pro.e.p set: the
 // step begins with the coarse grid correction u += P e (coarse level pro.gc),
@@ -128,7 +130,7 @@ struct ProlongIn {
 // reading u; only with res unset).
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
-                       GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
+                       GmState* st, double breakdown, const hipEvent_t* timed,
                        Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0,
                        ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false);
 

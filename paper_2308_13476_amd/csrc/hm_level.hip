@@ -3,6 +3,8 @@
 #include <cstdlib>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -1162,7 +1164,7 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
-                       Vec<T> Wb, GmState* st, double breakdown, void (*between)(void*, int), void* between_arg,
+                       Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
                        Vec<T> unew, Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
@@ -1212,15 +1214,20 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
             prereduce(A, std::integral_constant<int, 1>{});
         }
-        if (between) between(between_arg, 0);
         HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
         prereduce(B, std::integral_constant<int, 2>{});
-        if (between) between(between_arg, 1);
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
         prereduce(A, std::integral_constant<int, 5>{});
-        if (between) between(between_arg, 2);
-        HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
-        if (between) between(between_arg, 3);
+        if (timed) {
+            with_by<Op::kHeavy>(q.by, [&](auto byc) {
+                constexpr int BY = decltype(byc)::value;
+                hipExtLaunchKernelGGL((k_gm_oa<Op, T, 2, BY>), q.grid, q.block, uint32_t(tile_bytes<Op, T>(q.by, q.rpt)),
+                                      ctx.stream, timed[0], timed[1], 0u, op, Z, Wb, Wa, st, breakdown,
+                                      (const double*)A, nb, B, (const int*)HM_ACTIVE, q.rpt);
+            });
+        } else {
+            HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
+        }
         prereduce(B, std::integral_constant<int, 8>{});
         nb_op = nb;
         if (res.p)
@@ -1339,7 +1346,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template int launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>, Vec<T>);         \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
-                                       Vec<T>, GmState*, double, void (*)(void*, int), void*, Vec<T>, Vec<T>,   \
+                                       Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>, Vec<T>,             \
                                        int, ProlongIn<T>, bool);                                                \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \

@@ -449,37 +449,23 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
         return;
     }
-    // timing hook: events around the fused orthogonalise + apply pass that
-    // builds the third Arnoldi vector (launch 3 of the step)
-    struct Hook {
-        mg_ctx* c;
-        hipStream_t s;
-        double nodes;
-        hipEvent_t e0 = nullptr;
-        static void cb(void* arg, int i) {
-            Hook* h = static_cast<Hook*>(arg);
-            if (i == 2) {
-                if (hipEventCreate(&h->e0) == hipSuccess) (void)hipEventRecord(h->e0, h->s);
-                else h->e0 = nullptr;
-            } else if (i == 3 && h->e0) {
-                hipEvent_t e1;
-                if (hipEventCreate(&e1) == hipSuccess) {
-                    (void)hipEventRecord(e1, h->s);
-                    h->c->ev_pending.push_back({h->e0, e1});
-                    h->c->t_nodes += h->nodes;
-                } else {
-                    (void)hipEventDestroy(h->e0);
-                }
-                h->e0 = nullptr;
-            }
-        }
-    } hook{c, lc.stream, nodes};
+    // timing hook: the second fused orthogonalise + apply pass (launch 3 of
+    // the step) records a start and a stop event with its own dispatch
     const bool timed = c->timing_class == (l == 0 ? 1 : (l == 1 ? 4 : -1));
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    if (timed && (hipEventCreate(&tev[0]) != hipSuccess || hipEventCreate(&tev[1]) != hipSuccess)) {
+        if (tev[0]) (void)hipEventDestroy(tev[0]);
+        tev[0] = tev[1] = nullptr;
+    }
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
-                         w, t, c->gm, Prec<T>::breakdown, timed ? &Hook::cb : nullptr, &hook,
+                         w, t, c->gm, Prec<T>::breakdown, tev[1] ? tev : nullptr,
                          then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0},
                          r_ready_nblk, pro, u_zero && !then_residual);
+    if (tev[1]) {
+        c->ev_pending.push_back({tev[0], tev[1]});
+        c->t_nodes += nodes;
+    }
     if (then_residual) {
         std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
         if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
