@@ -24,7 +24,24 @@ int tall_rows() {
     }();
     return v;
 }
-int block_rows(const Grid& g, bool heavy) { return (!heavy && g.n >= 256) ? tall_rows() : kBY; }
+// Grids of at most 128 intervals: small_rows() rows (HELMG_SMALL_ROWS = 2 or
+// 4; default 2). Their passes are latency-bound, and two wavefronts per block
+// shorten each block's reductions and spread a pass over twice the compute
+// units. Tiles keep an even first row, which the staging of the coarse grid
+// correction relies on (it takes coarse row r0 / 2 as its reference).
+constexpr int kSmallDefault = 2;
+int small_rows() {
+    static const int v = [] {
+        int r = kSmallDefault;
+        if (const char* e = std::getenv("HELMG_SMALL_ROWS")) r = std::atoi(e);
+        return r == 4 ? kBY : kSmallDefault;
+    }();
+    return v;
+}
+int block_rows(const Grid& g, bool heavy) {
+    if (g.n <= 128) return small_rows();
+    return (!heavy && g.n >= 256) ? tall_rows() : kBY;
+}
 
 // Rows per thread: enough that a level grid has at most `cap` blocks (the
 // block cap of the context: every consumer of a reduction reads all partial
@@ -75,6 +92,10 @@ Geom geom_op(const Grid& g, int nrhs, int cap) {
 // of register-heavy operators are only instantiated with short blocks.
 template <bool kHeavy = false, typename F>
 void with_by(int by, F&& f) {
+    if (by == 2) {
+        f(std::integral_constant<int, 2>{});
+        return;
+    }
     if constexpr (kHeavy) {
         f(std::integral_constant<int, kBY>{});
     } else {
