@@ -10,8 +10,12 @@
 namespace hm {
 namespace {
 
-constexpr int kTailBY = 8;
-constexpr int kTailThreads = kBX * kTailBY;
+// Wavefronts of the tail workgroup: 8 in FP32; 4 in FP64, whose larger
+// registers would spill at 8 (measured faster: 4 wavefronts in FP64, 8 in FP32).
+template <typename T>
+constexpr int kTailBY = sizeof(T) == 8 ? 4 : 8;
+template <typename T>
+constexpr int kTailThreads = kBX * kTailBY<T>;
 
 template <typename T>
 __device__ __forceinline__ double tn2(cplx<T> z) {
@@ -59,7 +63,7 @@ __device__ __forceinline__ TLv<T> tail_level(const TailArgs<T>& a, int q, cplx<T
 template <typename T, typename F>
 __device__ __forceinline__ void tnodes(const TLv<T>& L, F&& f) {
     const int N = L.m * L.m;
-    for (int q = thread_linear(); q < N; q += kTailThreads) {
+    for (int q = thread_linear(); q < N; q += kTailThreads<T>) {
         const int i = q % L.m, j = q / L.m;
         f(i, j, L.li(i, j), L.g.at(i, j));
     }
@@ -327,7 +331,7 @@ template <typename T>
 __device__ void tail_coarse(const TLv<T>& C, const cplx<double>* inv) {
     const int N = C.m * C.m;
     const cplx<T>* f = C.f();
-    for (int r = thread_linear(); r < N; r += kTailThreads) {
+    for (int r = thread_linear(); r < N; r += kTailThreads<T>) {
         const cplx<double>* row = inv + (long long)r * N;
         cplx<double> acc{0.0, 0.0};
         for (int P = 0; P < N; ++P) acc = cfma(acc, row[P], cast<double>(f[C.li(P % C.m, P / C.m)]));
@@ -337,7 +341,7 @@ __device__ void tail_coarse(const TLv<T>& C, const cplx<double>* inv) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int* active) {
+__global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const int* active) {
     const int b = blockIdx.x;
     if (!rhs_active(active, b)) return;
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(kTailThreads) void k_tail(TailArgs<T> a, const int*
     // inverse in LDS when it fits, then load the top level
     {
         const long long total = a.plane_bytes / (long long)sizeof(cplx<T>);
-        for (long long q = thread_linear(); q < total; q += kTailThreads) lds[q] = cplx<T>{T(0), T(0)};
+        for (long long q = thread_linear(); q < total; q += kTailThreads<T>) lds[q] = cplx<T>{T(0), T(0)};
         unsigned char* base = reinterpret_cast<unsigned char*>(lds);
         if (a.inv_off >= 0) {
             const int N = (a.lv[a.nlev - 1].g.n + 1) * (a.lv[a.nlev - 1].g.n + 1);
@@ -483,7 +487,7 @@ void tail_init() {
 
 template <typename T>
 void launch_tail(const LaunchCtx& ctx, const TailArgs<T>& args) {
-    hipLaunchKernelGGL((k_tail<T>), dim3(ctx.nrhs), dim3(kBX, kTailBY), size_t(args.lds_bytes), ctx.stream, args,
+    hipLaunchKernelGGL((k_tail<T>), dim3(ctx.nrhs), dim3(kBX, kTailBY<T>), size_t(args.lds_bytes), ctx.stream, args,
                        ctx.active);
 }
 template void launch_tail<double>(const LaunchCtx&, const TailArgs<double>&);
