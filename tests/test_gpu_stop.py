@@ -47,3 +47,28 @@ def test_cap_and_tolerance_stops_agree(precision, smoother, k, stop_at):
         ref = O.solve(H, fs, O.CycleOptions(smoother=smoother), tol=1e-30, max_cycles=stop_at)
         x = to_np(xc)[0].ravel()
         assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_batch_members_stopped_before_the_first_cycle(precision):
+    """A batch of a point source, a right-hand side holding a NaN (stopped as
+    diverged before the first cycle) and a zero right-hand side (solution
+    zero, no cycles): the call reports the divergence, and the point source's
+    iterate and cycle count equal its solve alone, bit for bit."""
+    require_gpu()
+    from paper_2308_13476_amd import _binding as B
+    from paper_2308_13476_amd.solver import Solver
+    n, k = 128, 30.0
+    k2 = W.constant_k2(n, k)
+    f0 = W.point_source_rhs(n, [W.center_node(n)])
+    bad = W.point_source_rhs(n, [(n // 3, n // 4)])
+    bad[0, 5, 7] = np.nan
+    batch = np.concatenate([f0, bad, np.zeros_like(f0)])
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, precision=precision, max_batch=3)
+    x, info = S.solve(to_gpu(batch), tol=1e-8, precision=precision, raise_on_error=False)
+    assert info["status"] == B.MG_E_DIVERGED, info
+    assert info["cycles"][1] == 0 and info["cycles"][2] == 0 and info["cycles"][0] > 0, info
+    assert not to_np(x[2]).any()
+    xs, alone = S.solve(to_gpu(f0), tol=1e-8, precision=precision)
+    assert alone["status"] == 0 and alone["cycles"][0] == info["cycles"][0]
+    assert torch.equal(x[0:1], xs)
