@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <complex>
 #include <cmath>
@@ -103,8 +104,12 @@ struct mg_ctx {
         double timed_nodes = 0.0;
         std::vector<void*> after_ptrs;
         int after_cur = 0;
+        std::vector<int> marks;  // graph_marks left by the captured body
     };
     std::vector<GraphEntry> graphs;
+    // host bookkeeping that a cycle body records while it enqueues (the
+    // buffer parity after each of its cycles); replays restore it
+    std::vector<int> graph_marks;
     int last_graph = -1;
     hipStream_t cap_stream = nullptr;
     bool use_graph = true;
@@ -358,6 +363,7 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
     // per-kernel event timing needs eager launches (events recorded inside a
     // capture cannot be queried for elapsed time)
     if (!c->use_graph || c->timing_class != 0) {
+        c->graph_marks.clear();
         body(s);
         return check_launch(c);
     }
@@ -368,6 +374,7 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
         if (c->graphs[i].key != key) continue;
         restore_pointer_state(c, c->graphs[i].after_ptrs);
         c->cur_buf = c->graphs[i].after_cur;
+        c->graph_marks = c->graphs[i].marks;
         HM_HIP(hipGraphLaunch(c->graphs[i].exec, s));
         c->last_graph = int(i);
         return MG_OK;
@@ -378,6 +385,7 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
     destroy_pairs(c->ev_pending);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    c->graph_marks.clear();
     bool ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) == hipSuccess;
     if (ok) {
         body(c->cap_stream);
@@ -393,6 +401,7 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
         c->t_nodes = nodes_before;
         restore_pointer_state(c, before);
         c->cur_buf = cur_before;
+        c->graph_marks.clear();
         body(s);
         return check_launch(c);
     }
@@ -405,6 +414,7 @@ mg_status run_cycle_graph(mg_ctx* c, hipStream_t s, std::vector<uintptr_t> key, 
     c->t_nodes = nodes_before;
     e.after_ptrs = pointer_state(c);
     e.after_cur = c->cur_buf;
+    e.marks = c->graph_marks;
     c->graphs.push_back(std::move(e));
     HM_HIP(hipGraphLaunch(c->graphs.back().exec, s));
     c->last_graph = int(c->graphs.size() - 1);
@@ -762,10 +772,11 @@ struct SolveRun {
         }
     }
 
-    // cycle `it` (1-based) has been enqueued (eagerly or as a graph replay)
-    void enqueued(int it) {
+    // cycle `it` (1-based) has been enqueued (eagerly or as a graph replay),
+    // leaving the FP64 iterate in buffer cur
+    void enqueued(int it, int cur) {
         if ((int)buf_after.size() < it) buf_after.resize(it, 0);
-        buf_after[it - 1] = c->cur_buf;
+        buf_after[it - 1] = cur;
     }
 
     // after cycle `it` has completed: the device's stop decisions and norms.
@@ -798,18 +809,22 @@ struct SolveRun {
         return MG_OK;
     }
 
-    // Whether the cycle after the next one is worth queueing now: false when
-    // every running right-hand side, its relative residual extrapolated by its
-    // last contraction factor, is expected within twice the tolerance after
-    // the next cycle (a cycle queued behind the last one does no work but
-    // still costs most of a cycle's launches).
-    bool continues_past_next() const {
+    // The cycle after which every running right-hand side is expected within
+    // twice the tolerance, its relative residual after cycle `it` extrapolated
+    // by its last contraction factor (INT_MAX when one does not contract).
+    // Cycles queued beyond the last one do no work but still cost most of a
+    // cycle's launches, so the host queues ahead only up to this cycle.
+    int predicted_last(int it) const {
+        int last = it;
         for (int b = 0; b < nrhs; ++b) {
             if (state[b] != 0) continue;
             const double q = rel_prev[b] > 0.0 ? rel[b] / rel_prev[b] : 1.0;
-            if (!(rel[b] * q <= 2.0 * tol)) return true;
+            if (!(q < 1.0)) return INT_MAX;
+            int m = 1;
+            for (double r = rel[b] * q; r > 2.0 * tol && m < 4096; r *= q) ++m;
+            last = std::max(last, it + m);
         }
-        return false;
+        return last;
     }
 
     // enqueues the gather of the final iterates (no synchronisation)
@@ -860,25 +875,52 @@ mg_status solve_core(mg_ctx* c, hipStream_t s, int nrhs, double tol, int cyc, in
     if (mg_status st = run.start(s)) return st;
     HM_HIP(hipStreamSynchronize(s));
     if (mg_status st = run.begin(s)) return st;
-    auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
-    // One cycle is queued ahead of the one whose reports the host waits for,
-    // so the GPU does not idle through the host's turn-around, except where
-    // the next cycle is expected to be the last. Per-kernel timing (eager
-    // launches with events) stays in step.
+    // Cycles are launched in groups of one or two (one captured graph and one
+    // completion event per group: each graph launch costs a gap of about 13 us
+    // on the GPU), and a second group is queued behind the one whose reports
+    // the host waits for, so the GPU does not idle through the host's
+    // turn-around. Both only up to the cycle at which the solve is expected to
+    // end (predicted_last); the next cycle is always queued. Per-kernel timing
+    // (eager launches with events) runs one cycle at a time.
     const bool may_run_ahead = c->timing_class == 0;
-    int it = 0, enq = 0;
+    struct Group {
+        int last;  // its cycles end with this one
+        int ev;
+    };
+    Group inflight[2];
+    int n_inflight = 0, ev_next = 0, it = 0, enq = 0;
+    auto launch = [&](int count) -> mg_status {
+        std::vector<uintptr_t> key = run.key;
+        key.push_back(uintptr_t(count));
+        auto body = [&](hipStream_t st) {
+            for (int q = 0; q < count; ++q) {
+                run.enqueue_cycle(st);
+                c->graph_marks.push_back(c->cur_buf);
+            }
+        };
+        if (mg_status st = run_cycle_graph(c, s, key, body)) return st;
+        if (mg_status st = check_launch(c)) return st;
+        for (int q = 0; q < count; ++q) run.enqueued(enq + 1 + q, c->graph_marks[q]);
+        enq += count;
+        HM_HIP(hipEventRecord(c->cycle_done[ev_next], s));
+        inflight[n_inflight++] = Group{enq, ev_next};
+        ev_next ^= 1;
+        return MG_OK;
+    };
     while (run.running > 0 && it < o.max_cycles) {
-        const int ahead = may_run_ahead && run.continues_past_next() ? 1 : 0;
-        while (enq < o.max_cycles && enq <= it + ahead) {
-            ++enq;
-            if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
-            if (mg_status st = check_launch(c)) return st;
-            run.enqueued(enq);
-            HM_HIP(hipEventRecord(c->cycle_done[enq & 1], s));
+        const int plast = may_run_ahead ? run.predicted_last(it) : it + 1;
+        while (n_inflight < 2 && enq < o.max_cycles && (enq == it || (may_run_ahead && enq < plast))) {
+            const int count = (may_run_ahead && enq + 2 <= plast && enq + 2 <= o.max_cycles) ? 2 : 1;
+            if (mg_status st = launch(count)) return st;
         }
-        ++it;
-        HM_HIP(hipEventSynchronize(c->cycle_done[it & 1]));
-        if (mg_status st = run.after_cycle(it, stats)) return st;
+        const Group g = inflight[0];
+        inflight[0] = inflight[1];
+        --n_inflight;
+        HM_HIP(hipEventSynchronize(c->cycle_done[g.ev]));
+        while (it < g.last && run.running > 0) {
+            ++it;
+            if (mg_status st = run.after_cycle(it, stats)) return st;
+        }
     }
     if (mg_status st = run.gather(s)) return st;
     HM_HIP(hipStreamSynchronize(s));
@@ -1181,7 +1223,7 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
             for (int p : R) runs[p].enqueue_cycle(s);
         for (int p : R) {
             if (mg_status st = check_launch(runs[p].c)) return st;
-            runs[p].enqueued(it);
+            runs[p].enqueued(it, runs[p].c->cur_buf);
         }
         HM_HIP(hipStreamSynchronize(s));
         for (int p : R)
