@@ -358,7 +358,7 @@ __device__ __forceinline__ double dpp_move(double x) {
 // and every thread adds the wavefront totals in wavefront order.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
-    __shared__ double sh[K][kMaxBY];
+    __shared__ double sh[kMaxBY][K];
     const int lane = threadIdx.x, wave = threadIdx.y;
     __syncthreads();  // sh may still be read from an earlier call
     double w[K];
@@ -379,17 +379,16 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
     for (int k = 0; k < K; ++k) w[k] += dpp_move<0x143, 0xC>(w[k]);  // row_bcast 31 into rows 2, 3
     if (lane == kBX - 1)
 #pragma unroll
-        for (int k = 0; k < K; ++k) sh[k][wave] = w[k];
+        for (int k = 0; k < K; ++k) sh[wave][k] = w[k];
     __syncthreads();
+    // only the block's own wavefronts (a loop over every possible one with a
+    // guard per term costs two selects and an add per term and wavefront)
     const int nw = blockDim.y;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
+    for (int k = 0; k < K; ++k) tot[k] = 0.0;
+    for (int q = 0; q < nw; ++q)
 #pragma unroll
-        for (int q = 0; q < kMaxBY; ++q)
-            if (q < nw) s += sh[k][q];
-        tot[k] = s;
-    }
+        for (int k = 0; k < K; ++k) tot[k] += sh[q][k];
 }
 
 // Writes this block's K sums to out[block * K + k].
