@@ -31,10 +31,13 @@ HBM_PEAK_GBS = 8000.0
 # output) of the kernel classes the library can time with HIP events.
 # Class 1: the level-0 GMRES(3) pass that orthogonalises the second Arnoldi
 # vector and applies the operator to it: reads w_1, z_0, z_1 and k^2, writes
-# z_2 and w_2 = A z_2 (inner products <z_i, w_2> and ||z_2||^2 ride along).
-# In the FP32 cycle a vector is 8 B and k^2 is 4 B: 3*8 + 4 + 2*8 = 44 B.
+# z_2 (inner products <z_i, w_2>, ||z_2||^2 and ||w_2||^2 ride along) and, in
+# the last pre-smoothing step only, w_2 = A z_2 for the residual that the
+# update pass forms by recurrence. In the FP32 cycle a vector is 8 B and k^2
+# is 4 B: 3*8 + 4 + 8 = 36 B, plus 8 B for w_2 in one of the two launches per
+# cycle that the timing covers, 40 B per launch on average.
 KERNEL_CLASSES = {
-    1: {"name": "level-0 GMRES(3) orthogonalise + apply pass (complex64)", "bytes_per_node": 44.0},
+    1: {"name": "level-0 GMRES(3) orthogonalise + apply pass (complex64)", "bytes_per_node": 40.0},
 }
 
 # HBM traffic of the class-1 kernel per launch from two rocprofv3 --pmc runs

@@ -117,8 +117,9 @@ struct ProlongIn {
 // dispatch of the second orthogonalise + apply pass records itself
 // (hipExtLaunchKernelGGL), so that their interval is that kernel's execution
 // (timing hook; eager launches only). With res.p set, the
-// last pass writes the updated iterate to unew (u is left as it was) and the
-// residual f - A unew to res; unew and res may be Wb and Wa. pro.e.p set: the
+// last pass updates u in place and writes the residual f - A u of the updated
+// iterate to res (which may be Wa), formed by recurrence from the first
+// residual and the products A z_i of the Arnoldi passes. pro.e.p set: the
 // step begins with the coarse grid correction u += P e (coarse level pro.gc),
 // formed on the fly by the first pass, which keeps u + P e in pro.xt; the last
 // pass then writes the updated iterate to u (the step never changes the
@@ -127,11 +128,11 @@ struct ProlongIn {
 // (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
 // starts with the second pass. u_zero: the step starts from u = 0 although u
 // does not hold zeros (its update pass then writes sum y_i s_i z_i without
-// reading u; only with res unset).
+// reading u).
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
-                       GmState* st, double breakdown, const hipEvent_t* timed,
-                       Vec<T> unew = Vec<T>{nullptr, 0}, Vec<T> res = Vec<T>{nullptr, 0}, int r_ready_nblk = 0,
+                       GmState* st, double breakdown, const hipEvent_t* timed, Vec<T> res = Vec<T>{nullptr, 0},
+                       int r_ready_nblk = 0,
                        ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).

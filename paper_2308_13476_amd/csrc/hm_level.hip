@@ -737,7 +737,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     for (int q = 0; q < J; ++q) z[q] = Z.p + (long long)(b * 4 + q) * Z.plane;
     cplx<T>* zJ = Z.p + (long long)(b * 4 + J) * Z.plane;
     const cplx<T>* wi = Win.rhs(b);
-    cplx<T>* wo = Wout.rhs(b);
+    cplx<T>* wo = Wout.p ? Wout.rhs(b) : nullptr;  // w_2 is stored only for a residual by recurrence
     // z_J at a tile node from w_{J-1} (v[0]) and z_0 .. z_{J-1} (v[1..J])
     auto zload = [&](long long q) {
         Vals<T, J + 1> o;
@@ -769,7 +769,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     for_nodes_applied_pre<Op, T>(op, rpt, zload, zmake, zold, [&](int, int, long long p, const Vals<T, J>& zo, cplx<T> zp,
                                                          cplx<T> w) {
         zJ[p] = zp;
-        wo[p] = w;
+        if (J == 1 || wo) wo[p] = w;
         acc[0] += dnorm2(zp);
 #pragma unroll
         for (int q = 0; q < J; ++q) acc_dot(acc[1 + 2 * q], acc[2 + 2 * q], zo.v[q], w);
@@ -872,13 +872,17 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u(Grid g, Vec<T> Z, Vec<T> u, V
         });
 }
 
-// Pass 5 fused with the residual that follows the last pre-smoothing step:
-// u_new = u + sum y_i s_i z_i goes to unew (a different buffer: neighbouring
-// blocks still read u), r = f - A u_new to r.
-template <typename Op, typename T, int BY>
-__global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u, Vec<T> f, Vec<T> unew, Vec<T> r,
-                                                       const GmState* st, double breakdown, const double* pin,
-                                                       int nblk_in, const int* active, int rpt) {
+// Pass 5 of the last pre-smoothing step together with the residual that the
+// restriction needs: u' = u + sum_i c_i z_i (in place; from u = 0 with
+// kFromZero) and r' = z_0 - sum_i c_i w_i, with w_i = A z_i from the Arnoldi
+// passes (w_0 in Wa, w_1 in Wb, w_2 in the fourth Arnoldi plane). As
+// z_0 = f - A u, this is f - A u' exactly; the pass is pointwise (no stencil,
+// no tile), so u' and r' may overwrite u and w_0 in place. Only the k terms of
+// the Arnoldi columns in use enter.
+template <typename T, int BY, bool kFromZero>
+__global__ __launch_bounds__(kBX * BY) void k_gm_u_rr(Grid g, Vec<T> Z, Vec<T> u, Vec<T> Wa, Vec<T> Wb, Vec<T> r,
+                                                      const GmState* st, double breakdown, const double* pin,
+                                                      int nblk_in, const int* active, int rpt) {
     const int b = blockIdx.z;
     const bool act = rhs_active(active, b);
     cplx<T> c[3];
@@ -887,24 +891,45 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_res(Op op, Vec<T> Z, Vec<T> u
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     const cplx<T>* z1 = z0 + Z.plane;
     const cplx<T>* z2 = z1 + Z.plane;
-    const cplx<T>* ub = u.rhs(b);
-    const cplx<T>* fb = f.rhs(b);
-    cplx<T>* nb = unew.rhs(b);
+    const cplx<T>* w2 = z2 + Z.plane;
+    const cplx<T>* w0 = Wa.rhs(b);
+    const cplx<T>* w1 = Wb.rhs(b);
+    cplx<T>* ub = u.rhs(b);
     cplx<T>* rb = r.rhs(b);
-    // u_new at a tile node from u (v[0]) and z_0 .. z_2 (v[1..3])
-    auto uload = [&](long long q) { return Vals<T, 4>{{ub[q], z0[q], z1[q], z2[q]}}; };
-    auto umake = [&](const Vals<T, 4>& o) {
-        cplx<T> x = o.v[0];
-        if (k > 0) x = cfma(x, c[0], o.v[1]);
-        if (k > 1) x = cfma(x, c[1], o.v[2]);
-        if (k > 2) x = cfma(x, c[2], o.v[3]);
-        return x;
-    };
-    for_nodes_applied_pre<Op, T>(op, rpt, uload, umake, [fb](long long q) { return fb[q]; },
-                                 [&](int, int, long long p, cplx<T> fp, cplx<T> up, cplx<T> au) {
-                                     nb[p] = up;
-                                     rb[p] = fp - au;
-                                 });
+    cplx<T> mc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) mc[q] = {-c[q].re, -c[q].im};
+    constexpr int NB = sizeof(T) == 4 ? 4 : 2;
+    cplx<T> xu[NB], x0[NB], x1[NB], x2[NB], y0[NB], y1[NB], y2[NB];
+    for_nodes_batched<NB>(
+        g, rpt,
+        [&](int v, long long p) {
+            if constexpr (kFromZero) xu[v] = {T(0), T(0)};
+            else xu[v] = ub[p];
+            x0[v] = z0[p];
+            x1[v] = z1[p];
+            x2[v] = z2[p];
+            y0[v] = w0[p];
+            y1[v] = w1[p];
+            y2[v] = w2[p];
+        },
+        [&](int v, int, int, long long p) {
+            cplx<T> x = xu[v], rr = x0[v];
+            if (k > 0) {
+                x = cfma(x, c[0], x0[v]);
+                rr = cfma(rr, mc[0], y0[v]);
+            }
+            if (k > 1) {
+                x = cfma(x, c[1], x1[v]);
+                rr = cfma(rr, mc[1], y1[v]);
+            }
+            if (k > 2) {
+                x = cfma(x, c[2], x2[v]);
+                rr = cfma(rr, mc[2], y2[v]);
+            }
+            ub[p] = x;
+            rb[p] = rr;
+        });
 }
 
 // Sums the nblk partial rows of a region into row 0 (same thread count and
@@ -1186,7 +1211,7 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
-                       Vec<T> unew, Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
+                       Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
@@ -1239,23 +1264,28 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         prereduce(B, std::integral_constant<int, 2>{});
         HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
         prereduce(A, std::integral_constant<int, 5>{});
+        // w_2 is kept (in the fourth Arnoldi plane, w_0 stays in Wa) only for a
+        // residual by recurrence
+        const Vec<T> w2 = res.p ? Vec<T>{Z.p + 3 * Z.plane, 4 * Z.plane} : Vec<T>{nullptr, 0};
         if (timed) {
             with_by<Op::kHeavy>(q.by, [&](auto byc) {
                 constexpr int BY = decltype(byc)::value;
                 hipExtLaunchKernelGGL((k_gm_oa<Op, T, 2, BY>), q.grid, q.block, uint32_t(tile_bytes<Op, T>(q.by, q.rpt)),
-                                      ctx.stream, timed[0], timed[1], 0u, op, Z, Wb, Wa, st, breakdown,
+                                      ctx.stream, timed[0], timed[1], 0u, op, Z, Wb, w2, st, breakdown,
                                       (const double*)A, nb, B, (const int*)HM_ACTIVE, q.rpt);
             });
         } else {
-            HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, Wa, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
+            HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, w2, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         }
         prereduce(B, std::integral_constant<int, 8>{});
         nb_op = nb;
-        if (res.p)
-            HM_LAUNCH_OP(q, (k_gm_u_res<Op, T, BY>), op, Z, u, f, unew, res, st, breakdown, B, nb, HM_ACTIVE,
-                         q.rpt);
     });
-    if (!res.p && u_zero)
+    if (res.p && u_zero)
+        HM_LAUNCH(qv, (k_gm_u_rr<T, BY, true>), lop.g, Z, u, Wa, Wb, res, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
+    else if (res.p)
+        HM_LAUNCH(qv, (k_gm_u_rr<T, BY, false>), lop.g, Z, u, Wa, Wb, res, st, breakdown, B, nb_op, HM_ACTIVE,
+                  qv.rpt);
+    else if (u_zero)
         HM_LAUNCH(qv, (k_gm_u<T, BY, true>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
     else if (!res.p)
         HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
@@ -1367,7 +1397,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template int launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>, Vec<T>);         \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
-                                       Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>, Vec<T>,             \
+                                       Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>,                     \
                                        int, ProlongIn<T>, bool);                                                \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \

@@ -438,10 +438,9 @@ struct CycleParams {
 };
 
 // One smoothing step on level l. With then_residual (GMRES only), the step's
-// last pass also forms the residual f - A u into the level's w buffer; the
-// updated iterate then lands in t and the u / t buffers exchange roles.
-// u_zero (GMRES, without then_residual): the step starts from u = 0, which u
-// does not hold.
+// last pass also forms the residual f - A u of the updated iterate into the
+// level's w buffer. u_zero (GMRES): the step starts from u = 0, which u does
+// not hold.
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
             int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false) {
@@ -470,15 +469,10 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, tev[1] ? tev : nullptr,
-                         then_residual ? t : Vec<T>{nullptr, 0}, then_residual ? w : Vec<T>{nullptr, 0},
-                         r_ready_nblk, pro, u_zero && !then_residual);
+                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero);
     if (tev[1]) {
         c->ev_pending.push_back({tev[0], tev[1]});
         c->t_nodes += nodes;
-    }
-    if (then_residual) {
-        std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
-        if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
     }
 }
 
@@ -520,8 +514,7 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
 
 // r_ready_nblk > 0: level l was entered with u = 0 and the restriction (or,
 // on level 0 of an FP32 cycle, the FP64 residual pass before it) also formed
-// the first GMRES residual. u_zero: u itself does not hold those zeros (level
-// 0 only, where no pre-smoothing step forms the residual to restrict).
+// the first GMRES residual. u_zero: u itself does not hold those zeros.
 template <typename T>
 void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false) {
     if (l == c->tail_level[sizeof(T) == 4]) {
@@ -534,12 +527,11 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
         return;
     }
     LevelBuf& cb = c->lv[l + 1];
-    // on Galerkin levels the last GMRES pre-smoothing step also forms the
-    // residual to restrict
-    const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && l > 0;
+    // the last GMRES pre-smoothing step also forms the residual to restrict
+    const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0;
     for (int s = 0; s < cp.nu1; ++s)
         smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
-                  s == 0 && u_zero && !fused);
+                  s == 0 && u_zero);
     if (!fused)
         launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                            vec<T>(Prec<T>::w(lb), lb));
