@@ -48,9 +48,9 @@ KERNEL_CLASSES = {
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
-    "sources_sha256": "76f213b38b6c2fc8213572bfd4c60ac85a1fab85bd179005406d8b985308a9f8",
-    "fetch_bytes": 50904816,  # FETCH_SIZE x 1.9998 (copy-calibrated)
-    "write_bytes": 16899616,  # WRITE_SIZE x 1.0000
+    "sources_sha256": "62141ba33e3c51557e1f29117aba8efd754d9e797451d7bef8975e04440c03c3",
+    "fetch_bytes": 50599531,  # FETCH_SIZE x 1.9998 (copy-calibrated)
+    "write_bytes": 12684816,  # WRITE_SIZE x 1.0000
     "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
 }
 
