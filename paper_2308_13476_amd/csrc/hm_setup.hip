@@ -43,11 +43,14 @@ struct FineCoupling {
             const int D = 2 * r + 1;
             return coef[(long long)((ey + r) * D + ex + r) * g.plane + g.at(px, py)];
         }
+        return level0(px, py, ex, ey, k2[g.at(px, py)]);
+    }
+    // level 0 with k^2 at p given
+    __device__ __forceinline__ cplx<double> level0(int px, int py, int ex, int ey, double kk) const {
         const int n = g.n;
         if (ex == 0 && ey == 0) {
             const double W = line_w<double>(px, n) * line_w<double>(py, n);
             const int s = (px == 0 || px == n) + (py == 0 || py == n);
-            const double kk = k2[g.at(px, py)];
             const double im = -shift * kk - (s ? two_h * s * sqrt(kk) : 0.0);
             return {W * (4.0 * ih2 - kk), W * im};
         }
@@ -125,6 +128,15 @@ __global__ __launch_bounds__(kThreads) void k_galerkin0(FineCoupling A, Grid gc,
         cplx<double> acc[D * D];
 #pragma unroll
         for (int d = 0; d < D * D; ++d) acc[d] = {0.0, 0.0};
+        // k^2 of the 25 taps, loaded before any is used (left to itself the
+        // compiler waits for each load in turn)
+        double kk[5][5];
+#pragma unroll
+        for (int ay = -2; ay <= 2; ++ay)
+#pragma unroll
+            for (int ax = -2; ax <= 2; ++ax)
+                kk[ay + 2][ax + 2] = A.k2[A.g.at(min(max(2 * Ix + ax, 0), nf), min(max(2 * Iy + ay, 0), nf))];
+        __asm__ volatile("" ::: "memory");
 #pragma unroll
         for (int ay = -2; ay <= 2; ++ay)
 #pragma unroll
@@ -140,7 +152,8 @@ __global__ __launch_bounds__(kThreads) void k_galerkin0(FineCoupling A, Grid gc,
                     const int ey = e == 3 ? -1 : e == 4 ? 1 : 0;
                     const int qx = px + ex, qy = py + ey;
                     const bool ok = pin && qx >= 0 && qx <= nf && qy >= 0 && qy <= nf;
-                    const cplx<double> a = ok ? A(pxc, pyc, ex, ey) : cplx<double>{0.0, 0.0};
+                    const cplx<double> a =
+                        ok ? A.level0(pxc, pyc, ex, ey, kk[ay + 2][ax + 2]) : cplx<double>{0.0, 0.0};
 #pragma unroll
                     for (int dy = -rc; dy <= rc; ++dy)
 #pragma unroll
@@ -205,20 +218,30 @@ __global__ __launch_bounds__(kNodeThreads) void k_galerkin_node(Grid gf, const c
                 const int py = 2 * Iy + ay, qy = py + ey;
                 const bool yok = py >= 0 && py <= nf && qy >= 0 && qy <= nf;
                 const int pyc = min(max(py, 0), nf);
+                // the couplings of this tap row are loaded before any is used
+                // (left to itself the compiler waits for each load in turn)
+                cplx<double> v[2 * RA + 1][DF];
+#pragma unroll
+                for (int ax = -RA; ax <= RA; ++ax) {
+                    const long long at = gf.at(min(max(2 * Ix + ax, 0), nf), pyc);
+#pragma unroll
+                    for (int ex = -RF; ex <= RF; ++ex)
+                        v[ax + RA][ex + RF] = coef[(long long)((ey + RF) * DF + ex + RF) * gf.plane + at];
+                }
+                __asm__ volatile("" ::: "memory");
 #pragma unroll
                 for (int ax = -RA; ax <= RA; ++ax) {
                     const double rw = 0.25 * mask1(ax, kBez) * mask1(ay, kBez);
                     if (rw == 0.0) continue;  // compile-time
                     const int px = 2 * Ix + ax;
                     const bool pok = yok && px >= 0 && px <= nf;
-                    const long long at = gf.at(min(max(px, 0), nf), pyc);
 #pragma unroll
                     for (int ex = -RF; ex <= RF; ++ex) {
                         const int qx = px + ex;
                         const bool ok = pok && qx >= 0 && qx <= nf;
-                        const cplx<double> v = coef[(long long)((ey + RF) * DF + ex + RF) * gf.plane + at];
-                        G[ax + ex + RS].re += ok ? rw * v.re : 0.0;
-                        G[ax + ex + RS].im += ok ? rw * v.im : 0.0;
+                        const cplx<double> a = v[ax + RA][ex + RF];
+                        G[ax + ex + RS].re += ok ? rw * a.re : 0.0;
+                        G[ax + ex + RS].im += ok ? rw * a.im : 0.0;
                     }
                 }
             }
