@@ -676,7 +676,9 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
 // pass's sums, then build z_J = s_{J-1} w_{J-1} - sum_i H[i][J-1] s_i z_i,
 // w_J = A z_J (z_J recomputed at the stencil neighbours), partials
 // ||z_J||^2 and <z_i, w_J> for i <= J, and for J = 2 also ||w_2||^2 (the last
-// Arnoldi norm then follows without another pass over the vectors).
+// Arnoldi norm then follows without another pass over the vectors). w_1 goes
+// to Wout for pass 4; w_2 only where Wout.p is set (the update pass of the
+// last pre-smoothing step forms its residual from it).
 template <typename Op, typename T, int J, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
