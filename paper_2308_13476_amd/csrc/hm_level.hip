@@ -217,6 +217,18 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
         }
         return r;
     };
+    // fine regions strictly inside the grid skip the boundary terms (a uniform
+    // branch between two versions of the loop)
+    const bool interior = 2 * tl.c0 - 2 >= 1 && 2 * tl.c0 + 2 * VX - 3 <= nf - 1 && 2 * tl.r0 - 2 >= 1 &&
+                          2 * tl.r0 + 2 * rows + 1 <= nf - 1;
+    auto cs_inner = [&](T k2v, cplx<T> c, cplx<T> xw, cplx<T> xe, cplx<T> xs, cplx<T> xn) {
+        cplx<T> r = op.fine.apply5k_interior(k2v, c, xw, xe, xs, xn);
+        const T sw = op.shift * k2v;
+        r.re += sw * c.im;
+        r.im -= sw * c.re;
+        return r;
+    };
+    auto vstage = [&](auto inner) {
     for_strided_batched<kVBlocks>(
         nvb,
         [&](int u, int q) {
@@ -238,13 +250,25 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
             const cplx<T> n0 = yat(c, r + 2), n1 = yat(c + 1, r + 2);
             const int vi = 2 * by * PS::VW + 2 * bx;
             const bool east = bx < VX - 1, north = by < rows + 1;
-            v[vi] = cs_node(fi, fj, kk[u][0], c00, w0, c10, s0, c01);
-            if (east) v[vi + 1] = cs_node(fi + 1, fj, kk[u][1], c10, c00, e0, s1, c11);
-            if (north) {
-                v[vi + PS::VW] = cs_node(fi, fj + 1, kk[u][2], c01, w1, c11, c00, n0);
-                if (east) v[vi + PS::VW + 1] = cs_node(fi + 1, fj + 1, kk[u][3], c11, c01, e1, c10, n1);
+            if constexpr (decltype(inner)::value) {
+                v[vi] = cs_inner(kk[u][0], c00, w0, c10, s0, c01);
+                if (east) v[vi + 1] = cs_inner(kk[u][1], c10, c00, e0, s1, c11);
+                if (north) {
+                    v[vi + PS::VW] = cs_inner(kk[u][2], c01, w1, c11, c00, n0);
+                    if (east) v[vi + PS::VW + 1] = cs_inner(kk[u][3], c11, c01, e1, c10, n1);
+                }
+            } else {
+                v[vi] = cs_node(fi, fj, kk[u][0], c00, w0, c10, s0, c01);
+                if (east) v[vi + 1] = cs_node(fi + 1, fj, kk[u][1], c10, c00, e0, s1, c11);
+                if (north) {
+                    v[vi + PS::VW] = cs_node(fi, fj + 1, kk[u][2], c01, w1, c11, c00, n0);
+                    if (east) v[vi + PS::VW + 1] = cs_node(fi + 1, fj + 1, kk[u][3], c11, c01, e1, c10, n1);
+                }
             }
         });
+    };
+    if (interior) vstage(std::true_type{});
+    else vstage(std::false_type{});
     __syncthreads();
     // (R v)_I = (1/4) sum of the prolongation weights of I times v
     const T m5[5] = {T(1), T(4), T(6), T(4), T(1)};
@@ -301,6 +325,34 @@ __device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Til
                                                 cplx<T>* lds, PGet&& pget, F&& f) {
     if constexpr (is_product<Op>::value) {
         product_stages(op, tl, lds, pget, f);
+    } else if constexpr (std::is_same<Op, FineOp<T>>::value) {
+        // tiles whose nodes all lie strictly inside the grid skip the boundary
+        // terms (a uniform branch between two versions of the row loop)
+        const int n = op.g.n;
+        const bool interior = tl.c0 >= 1 && tl.c0 + kBX <= n && tl.r0 >= 1 && tl.r0 + tl.rows <= n;
+        constexpr int NB = sizeof(T) == 4 ? 8 : 4;
+        constexpr int TW = Tile<1>::TW;
+        decltype(pget(0LL)) pv[NB];
+        T kk[NB];
+        auto rows = [&](auto inner) {
+            for_nodes_batched<NB>(
+                op.g, rpt,
+                [&](int u, long long p) {
+                    pv[u] = pget(p);
+                    kk[u] = op.k2[p];
+                },
+                [&](int u, int i, int j, long long p) {
+                    const int li = tl.at(i, j);
+                    const cplx<T> c = lds[li];
+                    const cplx<T> ax =
+                        decltype(inner)::value
+                            ? op.apply5k_interior(kk[u], c, lds[li - 1], lds[li + 1], lds[li - TW], lds[li + TW])
+                            : op.apply5k(i, j, kk[u], c, lds[li - 1], lds[li + 1], lds[li - TW], lds[li + TW]);
+                    f(i, j, p, pv[u], c, ax);
+                });
+        };
+        if (interior) rows(std::true_type{});
+        else rows(std::false_type{});
     } else {
         // rows per batch: stored stencils keep one row per thread on most
         // levels and their FP64 coefficient batches need the registers

@@ -44,6 +44,16 @@ struct FineOp {
         y.im -= cx * (xw.im + xe.im) + cy * (xs.im + xn.im);
         return y;
     }
+    // the same at a node strictly inside the grid (W = 1, no Sommerfeld term):
+    // equal to apply5k there, without the boundary arithmetic
+    __device__ __forceinline__ cplx<T> apply5k_interior(T kk, cplx<T> c, cplx<T> xw, cplx<T> xe, cplx<T> xs,
+                                                        cplx<T> xn) const {
+        const T d = T(4) * ih2 - kk;
+        cplx<T> y{d * c.re, d * c.im};
+        y.re -= ih2 * (xw.re + xe.re) + ih2 * (xs.re + xn.re);
+        y.im -= ih2 * (xw.im + xe.im) + ih2 * (xs.im + xn.im);
+        return y;
+    }
     __device__ __forceinline__ cplx<T> apply5(int i, int j, long long p, cplx<T> c, cplx<T> xw, cplx<T> xe,
                                               cplx<T> xs, cplx<T> xn) const {
         return apply5k(i, j, k2[p], c, xw, xe, xs, xn);
