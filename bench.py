@@ -48,8 +48,8 @@ KERNEL_CLASSES = {
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
-    "sources_sha256": "26ee9cb2032b94adaed0a001f2e1e2a370a177c5bd2e23df50d3927cde94c61d",
-    "fetch_bytes": 50599531,  # FETCH_SIZE x 1.9998 (copy-calibrated)
+    "sources_sha256": "c64b008c6440533b1379ddb7049bedebabd10a61eaa5ffe4ca647e10abc52e61",
+    "fetch_bytes": 50445306,  # FETCH_SIZE x 1.9998 (copy-calibrated)
     "write_bytes": 12684816,  # WRITE_SIZE x 1.0000
     "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
 }
