@@ -198,12 +198,13 @@ struct TailArgs {
     long long plane_bytes;  // sum of tail_plane_values over the levels, in bytes
     long long inv_off;      // byte offset of the LDS copy of inv, or -1 (read from global memory)
     TailLevel<T> lv[kMaxTailLevels];
-    cplx<T>* u_top;         // level l0 iterate (read, then overwritten), right-hand side 0; stride g.plane
+    cplx<T>* u_top;         // level l0 iterate (read unless top_zero, then overwritten), right-hand side 0; stride g.plane
     const cplx<T>* f_top;   // level l0 right-hand side
     const cplx<double>* inv;  // explicit inverse of the coarsest operator [N][N] (FP64)
     int gamma, smoother, nu1, nu2;  // smoother: 0 Jacobi, 1 GMRES(3)
     double omega, breakdown;
     int bez;
+    int top_zero;  // the level l0 iterate holds zeros (its first visit, entered by restriction)
 };
 template <typename T> void launch_tail(const LaunchCtx&, const TailArgs<T>&);
 // Raises the dynamic-LDS limit of the tail kernels (once per process; call

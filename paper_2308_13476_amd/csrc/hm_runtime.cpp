@@ -477,7 +477,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
 }
 
 template <typename T>
-void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams& cp) {
+void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams& cp, bool top_zero) {
     TailArgs<T> a{};
     a.nlev = c->L - l0;
     a.plane_bytes = 0;
@@ -509,16 +509,19 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
     a.omega = cp.omega;
     a.breakdown = Prec<T>::breakdown;
     a.bez = c->transfer == MG_TRANSFER_BEZIER;
+    a.top_zero = top_zero;
     launch_tail<T>(lc, a);
 }
 
 // r_ready_nblk > 0: level l was entered with u = 0 and the restriction (or,
 // on level 0 of an FP32 cycle, the FP64 residual pass before it) also formed
 // the first GMRES residual. u_zero: u itself does not hold those zeros.
+// first_visit: level l was entered by the restriction that zeroed its u.
 template <typename T>
-void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false) {
+void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false,
+           bool first_visit = false) {
     if (l == c->tail_level[sizeof(T) == 4]) {
-        launch_tail_from<T>(c, lc, l, cp);
+        launch_tail_from<T>(c, lc, l, cp, first_visit);
         return;
     }
     LevelBuf& lb = c->lv[l];
@@ -543,7 +546,7 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     const int nb_r = launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb),
                                         vec<T>(Prec<T>::f(cb), cb), vec<T>(Prec<T>::u(cb), cb),
                                         r_in_restrict ? vec<T>(Prec<T>::V(cb), cb) : Vec<T>{nullptr, 0});
-    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0);
+    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0, false, g == 0);
     // the coarse grid correction u += P e is formed by the first pass of the
     // first post-smoothing GMRES step, into the fourth Arnoldi plane (unused
     // by the step's own passes)

@@ -130,12 +130,15 @@ __device__ void tail_jacobi(const TLv<T>& L, double inv_omega) {
 
 // One GMRES(3) smoothing step (§5.3): classical Gram-Schmidt Arnoldi on
 // unnormalised vectors z_j with scale s_j = 1 / ||z_j||, the same recurrences
-// as the multi-kernel path, reductions inside the block.
+// as the multi-kernel path, reductions inside the block. u_zero: u holds
+// zeros (the level was just entered by restriction), so the first residual
+// is f itself and is read in place.
 template <typename T>
-__device__ void tail_gmres(const TLv<T>& L, double breakdown) {
+__device__ void tail_gmres(const TLv<T>& L, double breakdown, bool u_zero) {
     cplx<T>* u = L.u();
     const cplx<T>* f = L.f();
-    cplx<T>* z0 = L.s(0);
+    cplx<T>* z0w = L.s(0);
+    const cplx<T>* z0 = u_zero ? f : z0w;
     cplx<T>* z1 = L.s(1);
     cplx<T>* z2 = L.s(2);
     cplx<T>* wa = L.s(3);
@@ -146,11 +149,15 @@ __device__ void tail_gmres(const TLv<T>& L, double breakdown) {
     with_radius(L, [&](auto Rc) {
         constexpr int R = decltype(Rc)::value;
         double a1[1] = {0.0}, t1[1];
-        tnodes(L, [&](int, int, int li, long long gp) {
-            const cplx<T> z = f[li] - tapply<T, R>(L, u, li, gp);
-            z0[li] = z;
-            a1[0] += tn2(z);
-        });
+        if (u_zero) {
+            tnodes(L, [&](int, int, int li, long long) { a1[0] += tn2(f[li]); });
+        } else {
+            tnodes(L, [&](int, int, int li, long long gp) {
+                const cplx<T> z = f[li] - tapply<T, R>(L, u, li, gp);
+                z0w[li] = z;
+                a1[0] += tn2(z);
+            });
+        }
         block_sum<1>(a1, t1);
         beta = sqrt(t1[0]);
         if (!(beta > 0.0)) {
@@ -362,8 +369,9 @@ __global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const i
         __syncthreads();
         const TLv<T> L = tail_level(a, 0, lds);
         const long long off = (long long)b * L.g.plane;
+        const bool load_u = a.top_zero == 0;  // otherwise the zeroed plane is the iterate
         tnodes(L, [&](int i, int j, int li, long long) {
-            L.u()[li] = a.u_top[off + L.g.at(i, j)];
+            if (load_u) L.u()[li] = a.u_top[off + L.g.at(i, j)];
             L.f()[li] = a.f_top[off + L.g.at(i, j)];
         });
         __syncthreads();
@@ -380,6 +388,7 @@ __global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const i
     unsigned visits = 0u;  // 2 bits per level: coarse visits left
     int q = 0;
     bool up = false;
+    bool fresh = a.top_zero != 0;  // level q holds u = 0 (entered by restriction, not yet smoothed)
     if (last == 0) {
         tail_coarse(tail_level(a, 0, lds), inv);
     } else {
@@ -394,7 +403,8 @@ __global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const i
                 }
                 nu = a.nu1;
             } else {
-                // back from one visit of level q + 1
+                // back from one visit of level q + 1: u now holds a result
+                fresh = false;
                 const unsigned left = ((visits >> (2 * q)) & 3u) - 1u;
                 visits = (visits & ~(3u << (2 * q))) | (left << (2 * q));
                 if (left > 0) {
@@ -409,13 +419,14 @@ __global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const i
                 const TLv<T> L = tail_level(a, q, lds);
                 for (int s = 0; s < nu; ++s) {
                     if (a.smoother == 0) tail_jacobi(L, inv_omega);
-                    else tail_gmres(L, a.breakdown);
+                    else tail_gmres(L, a.breakdown, fresh && s == 0);
                 }
             }
             if (!up) {
                 tail_residual_restrict(tail_level(a, q, lds), tail_level(a, q + 1, lds), bez);
                 visits = (visits & ~(3u << (2 * q))) | (unsigned(a.gamma) << (2 * q));
                 q += 1;
+                fresh = true;
             } else {
                 if (q == 0) break;
                 q -= 1;
