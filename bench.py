@@ -48,8 +48,8 @@ KERNEL_CLASSES = {
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
-    "sources_sha256": "c64b008c6440533b1379ddb7049bedebabd10a61eaa5ffe4ca647e10abc52e61",
-    "fetch_bytes": 50445306,  # FETCH_SIZE x 1.9998 (copy-calibrated)
+    "sources_sha256": "87701874b2647dd260eaeef8ef8ba2522a6d49bead98693274ae8c09dc91ac94",
+    "fetch_bytes": 50393511,  # FETCH_SIZE x 1.9998 (copy-calibrated)
     "write_bytes": 12684816,  # WRITE_SIZE x 1.0000
     "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
 }
