@@ -132,9 +132,12 @@ __device__ void tail_jacobi(const TLv<T>& L, double inv_omega) {
 // unnormalised vectors z_j with scale s_j = 1 / ||z_j||, the same recurrences
 // as the multi-kernel path, reductions inside the block. u_zero: u holds
 // zeros (the level was just entered by restriction), so the first residual
-// is f itself and is read in place.
+// is f itself and is read in place. res (only with u_zero): the plane of w_0
+// receives the residual f - A u' of the updated iterate, formed by recurrence
+// as z_0 - sum_i c_i w_i (w_2 is kept in the first scratch plane, which z_0
+// does not use); returns whether it was formed.
 template <typename T>
-__device__ void tail_gmres(const TLv<T>& L, double breakdown, bool u_zero) {
+__device__ bool tail_gmres(const TLv<T>& L, double breakdown, bool u_zero, cplx<T>* res) {
     cplx<T>* u = L.u();
     const cplx<T>* f = L.f();
     cplx<T>* z0w = L.s(0);
@@ -236,6 +239,7 @@ __device__ void tail_gmres(const TLv<T>& L, double breakdown, bool u_zero) {
         double a7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t7[7];
         tnodes(L, [&](int, int, int li, long long gp) {
             const cplx<T> w = tapply<T, R>(L, z2, li, gp);
+            if (res) z0w[li] = w;
             tdot(a7[0], a7[1], z0[li], w);
             tdot(a7[2], a7[3], z1[li], w);
             tdot(a7[4], a7[5], z2[li], w);
@@ -251,34 +255,46 @@ __device__ void tail_gmres(const TLv<T>& L, double breakdown, bool u_zero) {
         hr[3][2] = sqrt(fmax(sq, 0.0));
         hi[3][2] = 0.0;
     });
-    if (k == 0) return;
+    if (k == 0) return false;
     // every thread holds the same H (block sums are identical in all
     // threads) and solves the least-squares problem in registers
     double yr[3], yi[3];
     gm_least_squares_regs(hr, hi, s, beta, k, yr, yi);
     cplx<T> c[3];
     for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
+    const cplx<T> m0 = {-c[0].re, -c[0].im}, m1 = {-c[1].re, -c[1].im}, m2 = {-c[2].re, -c[2].im};
+    const cplx<T>* w2 = z0w;
     tnodes(L, [&](int, int, int li, long long) {
         cplx<T> x = u[li];
         x = cfma(x, c[0], z0[li]);
         if (k > 1) x = cfma(x, c[1], z1[li]);
         if (k > 2) x = cfma(x, c[2], z2[li]);
         u[li] = x;
+        if (res) {  // read before the store: res is the plane of w_0
+            cplx<T> r = cfma(z0[li], m0, wa[li]);
+            if (k > 1) r = cfma(r, m1, wb[li]);
+            if (k > 2) r = cfma(r, m2, w2[li]);
+            res[li] = r;
+        }
     });
     __syncthreads();
+    return res != nullptr;
 }
 
 // f_c = R (f - A u) (§4 transfers, R = P^T / 4) and u_c = 0. The residual
-// goes to scratch plane wa of the fine level; the LDS frame supplies the zero
-// ghosts that truncate the mask at the boundary.
+// goes to scratch plane wa of the fine level (r_ready: the last smoothing
+// step already put it there); the LDS frame supplies the zero ghosts that
+// truncate the mask at the boundary.
 template <typename T>
-__device__ void tail_residual_restrict(const TLv<T>& L, const TLv<T>& C, bool bez) {
+__device__ void tail_residual_restrict(const TLv<T>& L, const TLv<T>& C, bool bez, bool r_ready) {
     cplx<T>* w = L.s(3);
-    with_radius(L, [&](auto Rc) {
-        constexpr int R = decltype(Rc)::value;
-        tnodes(L, [&](int, int, int li, long long gp) { w[li] = L.f()[li] - tapply<T, R>(L, L.u(), li, gp); });
-    });
-    __syncthreads();
+    if (!r_ready) {
+        with_radius(L, [&](auto Rc) {
+            constexpr int R = decltype(Rc)::value;
+            tnodes(L, [&](int, int, int li, long long gp) { w[li] = L.f()[li] - tapply<T, R>(L, L.u(), li, gp); });
+        });
+        __syncthreads();
+    }
     const T w5[5] = {T(1), T(4), T(6), T(4), T(1)};
     const T w3[5] = {T(0), T(1), T(2), T(1), T(0)};
     const T* mw = bez ? w5 : w3;
@@ -415,15 +431,21 @@ __global__ __launch_bounds__(kTailThreads<T>) void k_tail(TailArgs<T> a, const i
                 tail_prolong(tail_level(a, q + 1, lds), tail_level(a, q, lds), bez);
                 nu = a.nu2;
             }
+            bool r_ready = false;  // the last step left f - A u in the restriction's plane
             {
                 const TLv<T> L = tail_level(a, q, lds);
                 for (int s = 0; s < nu; ++s) {
-                    if (a.smoother == 0) tail_jacobi(L, inv_omega);
-                    else tail_gmres(L, a.breakdown, fresh && s == 0);
+                    if (a.smoother == 0) {
+                        tail_jacobi(L, inv_omega);
+                    } else {
+                        // a single pre-smoothing step from u = 0 also forms the residual to restrict
+                        const bool zero = fresh && s == 0;
+                        r_ready = tail_gmres(L, a.breakdown, zero, zero && !up && s + 1 == nu ? L.s(3) : nullptr);
+                    }
                 }
             }
             if (!up) {
-                tail_residual_restrict(tail_level(a, q, lds), tail_level(a, q + 1, lds), bez);
+                tail_residual_restrict(tail_level(a, q, lds), tail_level(a, q + 1, lds), bez, r_ready);
                 visits = (visits & ~(3u << (2 * q))) | (unsigned(a.gamma) << (2 * q));
                 q += 1;
                 fresh = true;
