@@ -170,8 +170,12 @@ mg_status mg_tune(mg_handle h, const void* rhs, int nrhs, int cycle, int smoothe
  * z_j = one cycle (cycle, smoother, opts->nu_pre / nu_post / omega) on
  * A_s z = v_j from z = 0, an FP64 cycle, or the FP32 cycle when
  * opts->precision is MG_FP32_REFINED; modified Gram-Schmidt Arnoldi; the
- * least-squares problem by Givens rotations on the host (one stream
- * synchronisation per iteration).
+ * least-squares problem by Givens rotations on the host, which reads each
+ * Hessenberg column while the next iteration already runs (so a solve that
+ * stops inside a restart cycle computes one iteration it does not use). The
+ * first call on a handle allocates a small pinned host buffer for the
+ * columns (up to 2 * max_batch * 65 complex values), kept until mg_destroy;
+ * MG_E_HIP if that fails.
  *  rhs, x, nrhs as in mg_solve; m restart length in [1, 64].
  *  krylov [dev] caller's buffer of at least mg_fgmres_workspace_bytes(h, m)
  *         bytes, 256-byte aligned (basis V, directions Z, x, f, w, H, y);

@@ -90,6 +90,10 @@ struct mg_ctx {
     double* h_limits = nullptr;
     RhsReport* h_ring = nullptr;  // stop-test reports, written by the device
     hipEvent_t cycle_done[2] = {nullptr, nullptr};
+    // FGMRES: two slots of Hessenberg columns read back while the next
+    // iteration runs (allocated by the first FGMRES solve), and their events
+    cplx<double>* h_hcol = nullptr;
+    hipEvent_t hcol_done[2] = {nullptr, nullptr};
     std::string err;
     // kernel timing hook: event pairs of eager launches, and of the graph run last
     int timing_class = 0;
@@ -1301,6 +1305,16 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
         c->err = "krylov buffer too small: need " + std::to_string(K.bytes) + " bytes";
         return MG_E_WORKSPACE;
     }
+    if (!c->h_hcol) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->h_hcol),
+                          sizeof(cplx<double>) * 2 * c->max_batch * (kMaxRestart + 1), hipHostMallocDefault) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&c->hcol_done[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->hcol_done[1], hipEventDisableTiming) != hipSuccess) {
+            c->err = "pinned host buffer or event for the Hessenberg columns could not be created";
+            return MG_E_HIP;
+        }
+    }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = static_cast<hipStream_t>(stream);
     LevelBuf& l0 = c->lv[0];
@@ -1342,7 +1356,7 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
             cycle<double>(c, l2, 0, cp);
         }
     };
-    std::vector<cplx<double>> hcol(size_t(nrhs) * (m + 1)), yh(size_t(nrhs) * m);
+    std::vector<cplx<double>> yh(size_t(nrhs) * m);
     // per right-hand side: Hessenberg columns rotated to upper triangular, rotations, g
     std::vector<std::vector<std::complex<double>>> R(nrhs), gvec(nrhs), sn(nrhs);
     std::vector<std::vector<double>> cs(nrhs);
@@ -1388,8 +1402,10 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
         launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms);
         std::vector<int> in_cycle = act;  // right-hand sides updated at the end of this cycle
         std::vector<int> stopped(nrhs, 0);
-        for (int j = 0; j < m; ++j) {
-            // z_j = M(v_j): one cycle from zero on A_s z = v_j
+        // iteration j on the stream: z_j = M(v_j), one cycle from zero on
+        // A_s z = v_j; w = A_s z_j orthogonalised into column j of H and
+        // v_{j+1}; the column copied to host slot j % 2
+        auto enqueue = [&](int j) -> mg_status {
             cplx<double>* vj = K.V + j * K.vstride;
             cplx<double>* zj = K.Z + j * K.vstride;
             if (fp32) launch_kry_cast_down(lc, g0, vj, l0.f32, pl);
@@ -1397,14 +1413,26 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
             if (mg_status st = run_cycle_graph(c, s, key, precond_body)) return st;
             if (fp32) launch_kry_cast_up(lc, g0, l0.u32, zj, pl);
             else HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
-            // w = A_s z_j, orthogonalised into column j of H and v_{j+1}
             launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
             launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl);
             if (mg_status st = check_launch(c)) return st;
-            HM_HIP(hipMemcpyAsync(hcol.data(), K.H, sizeof(cplx<double>) * nrhs * (m + 1), hipMemcpyDeviceToHost,
-                                  s));
-            HM_HIP(hipStreamSynchronize(s));
-            bool any = false;
+            HM_HIP(hipMemcpyAsync(c->h_hcol + size_t(j & 1) * nrhs * (m + 1), K.H,
+                                  sizeof(cplx<double>) * nrhs * (m + 1), hipMemcpyDeviceToHost, s));
+            HM_HIP(hipEventRecord(c->hcol_done[j & 1], s));
+            return MG_OK;
+        };
+        if (mg_status st = enqueue(0)) return st;
+        for (int j = 0; j < m; ++j) {
+            // iteration j + 1 needs device data only, so it is queued before
+            // column j is read; when column j stops a right-hand side, its
+            // share of iteration j + 1 is computed but never used (columns
+            // beyond kdir are not read), and when it stops all of them the
+            // whole iteration is
+            if (j + 1 < m)
+                if (mg_status st = enqueue(j + 1)) return st;
+            HM_HIP(hipEventSynchronize(c->hcol_done[j & 1]));
+            const cplx<double>* hcol = c->h_hcol + size_t(j & 1) * nrhs * (m + 1);
+            bool any = false, changed = false;
             for (int b = 0; b < nrhs; ++b) {
                 if (!act[b]) continue;
                 std::vector<std::complex<double>> h(j + 2);
@@ -1445,13 +1473,16 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
                 const bool subzero = hcol[size_t(b) * (m + 1) + j + 1].re == 0.0;
                 if (est <= tol || its[b] >= o.max_cycles || subzero) {
                     act[b] = 0;
+                    changed = true;
                     if (est <= tol) stopped[b] = 1;
                 } else {
                     any = true;
                 }
             }
             if (!any || j == m - 1) break;
-            if (mg_status st = set_active(act)) return st;
+            // takes effect from iteration j + 2 (j + 1 is already queued)
+            if (changed)
+                if (mg_status st = set_active(act)) return st;
         }
         // x += Z y for every right-hand side of this cycle (R y = g by back substitution)
         for (int b = 0; b < nrhs; ++b) {
@@ -1628,7 +1659,10 @@ mg_status mg_destroy(mg_handle c) {
     if (c->h_active) (void)hipHostFree(c->h_active);
     if (c->h_limits) (void)hipHostFree(c->h_limits);
     if (c->h_ring) (void)hipHostFree(c->h_ring);
+    if (c->h_hcol) (void)hipHostFree(c->h_hcol);
     for (hipEvent_t e : c->cycle_done)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->hcol_done)
         if (e) (void)hipEventDestroy(e);
     delete c;
     return MG_OK;
