@@ -10,10 +10,12 @@
 namespace hm {
 namespace {
 
-// Wavefronts of the tail workgroup: 8 in FP32; 4 in FP64, whose larger
-// registers would spill at 8 (measured faster: 4 wavefronts in FP64, 8 in FP32).
+// Wavefronts of the tail workgroup: 5 in FP32, the fewest that give each of
+// the 289 nodes of a 16-interval level its own thread (fewer wavefronts per
+// barrier and block sum; 5 measured faster than 8, and 8 than 4); 4 in FP64,
+// whose larger registers spill when a SIMD holds two of its wavefronts.
 template <typename T>
-constexpr int kTailBY = sizeof(T) == 8 ? 4 : 8;
+constexpr int kTailBY = sizeof(T) == 8 ? 4 : 5;
 template <typename T>
 constexpr int kTailThreads = kBX * kTailBY<T>;
 
