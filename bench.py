@@ -167,9 +167,15 @@ def cpu_baseline(n, k, cycles):
         t0 = time.perf_counter()
         O.solve(H, fs, opts, tol=1e-30, max_cycles=cycles)
         dt = time.perf_counter() - t0
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
     return {"value": (n + 1) ** 2 * cycles / dt, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "host_cpus_usable": usable,
             "sample": f"{cycles} FP64 GMRES(3) V(1,1) cycles of the same n={n}, k={k:g} problem "
-                      f"(oracle setup excluded), {dt:.1f} s on one host thread"}
+                      f"(oracle setup excluded), {dt:.1f} s on one host thread (SciPy sparse products and "
+                      f"the cycle recursion are single-threaded; BLAS pinned to one thread)"}
 
 
 def fgmres_workload(args):

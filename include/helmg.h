@@ -81,7 +81,10 @@ typedef struct {
 typedef struct {
     int* cycles;         /* [host] nrhs entries or NULL: cycles run per right-hand side */
     double* relres;      /* [host] nrhs entries or NULL: final relative residuals       */
-    double* history;     /* [host] max_cycles x nrhs or NULL: relres after every cycle  */
+    double* history;     /* [host] history_len entries or NULL: relres after every
+                            cycle, entry [it * nrhs + b] for cycle it + 1 of b       */
+    int history_len;     /* entries of history; with history set it must be at least
+                            opts->max_cycles * nrhs, else the call returns MG_E_ARG  */
     double seconds;      /* wall time of the call (host clock, stream synchronised)     */
 } mg_solve_stats;
 
@@ -91,7 +94,11 @@ typedef struct {
 size_t mg_workspace_bytes(int n, int levels, int transfer, const mg_setup_opts* opts);
 
 /* Builds the multigrid hierarchy (§3, §4) on the device.
- *  k2        [dev] double, (n+1)^2 values of k(x,y)^2 >= 0 (k > 0 on the boundary).
+ *  k2        [dev] double, (n+1)^2 values of k(x,y)^2: finite, >= 0, and > 0 on
+ *            the boundary nodes (the absorbing condition of §2 uses k there).
+ *            The field is checked on the device before anything is built (the
+ *            only argument check that needs the GPU): MG_E_ARG, with the first
+ *            offending node in mg_last_error, if any value violates this.
  *  n         intervals per side (>= 4, divisible by 2^(levels-1)).
  *  h         mesh width (> 0; 1/n for the unit square).
  *  shift     beta2 >= 0, the complex shift of the coarsening operator (§4, §5).
@@ -107,7 +114,9 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
                    const mg_setup_opts* opts, void* workspace, size_t ws_bytes, void* stream,
                    mg_handle* out);
 
-/* Rebuilds the hierarchy for a new k^2 field on the same grid (same workspace). */
+/* Rebuilds the hierarchy for a new k^2 field on the same grid (same workspace).
+ * The field is checked as in mg_setup first; on MG_E_ARG the handle keeps its
+ * previous hierarchy. */
 mg_status mg_update_k2(mg_handle h, const double* k2, void* stream);
 
 /* Solves A_s x = W rhs for nrhs right-hand sides sharing the operator (§5).

@@ -39,7 +39,8 @@ class SolveOpts(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("cycles", ctypes.POINTER(ctypes.c_int)), ("relres", ctypes.POINTER(ctypes.c_double)),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("seconds", ctypes.c_double)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("seconds", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):

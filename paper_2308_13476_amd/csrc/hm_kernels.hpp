@@ -228,6 +228,10 @@ void launch_kry_cast_down(const LaunchCtx&, Grid g, const cplx<double>* src, cpl
 void launch_kry_cast_up(const LaunchCtx&, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane);
 
 // ---- setup ----
+// Validity of the caller's dense k^2 array (n+1)^2: flags[0] |= 1 (non-finite),
+// 2 (negative), 4 (zero on the boundary); flags[1] = min offending index.
+// The caller sets flags to {0, INT_MAX} first.
+void launch_check_k2(hipStream_t, int n, const double* k2_dense, int* flags);
 // Padded k^2 planes from the caller's dense array (FP64 and optionally FP32).
 void launch_k2_in(hipStream_t, Grid g, const double* k2_dense, double* k2_64, float* k2_32);
 // Galerkin product of level l (fine) into level l+1 (coarse) in FP64.

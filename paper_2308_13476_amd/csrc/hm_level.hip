@@ -1176,7 +1176,10 @@ __global__ __launch_bounds__(kThreads) void k_grad_k2(Grid g, double h, const do
         const int n = g.n;
         const double W = line_w<double>(i, n) * line_w<double>(j, n);
         const int s = (i == 0 || i == n) + (j == 0 || j == n);
-        const double bi = s ? double(s) / (h * sqrt(k2[p])) : 0.0;  // imaginary part of 1 + i s/(h k)
+        // imaginary part of 1 + i s/(h k); zero where k = 0 (as 1/(h k) -> 0
+        // is taken there; setup rejects k = 0 on the boundary anyway)
+        const double kk = k2[p];
+        const double bi = (s && kk > 0.0) ? double(s) / (h * sqrt(kk)) : 0.0;
         double acc = 0.0;
         for (int b = 0; b < nrhs; ++b) {
             const cplx<double> t = mu.rhs(b)[p] * u.rhs(b)[p];

@@ -82,6 +82,7 @@ struct mg_ctx {
     int* stop_count = nullptr;      // [max_batch] stop tests taken per right-hand side
     double* stop_limits = nullptr;  // [max_batch][2] tolerance, divergence limit
     double* partials = nullptr;
+    int* k2_flags = nullptr;  // [2] result of the k^2 check
     char* ws = nullptr;
     size_t ws_bytes = 0;
     // host mirrors (pinned)
@@ -210,7 +211,9 @@ size_t carve(mg_ctx* c, char* base, int n, int L, int transfer, int max_batch, i
     int* stop_count = cv.take<int>(B * 4);
     double* stop_limits = cv.take<double>(B * 16);
     double* partials = cv.take<double>(2 * B * size_t(kPartStride) * 8);
+    int* k2_flags = cv.take<int>(2 * 4);
     if (c) {
+        c->k2_flags = k2_flags;
         c->k2_64 = k64;
         c->k2_32 = k32;
         c->dense = dense;
@@ -573,6 +576,36 @@ mg_status zero_workspace(mg_ctx* c, hipStream_t s) {
     return check_launch(c);
 }
 
+// The k^2 field must be finite, non-negative, and positive on the boundary
+// (§2: the absorbing condition takes k = sqrt(k^2) there). Checked on the
+// device before the hierarchy is touched; MG_E_ARG with the first offending
+// node in *why otherwise.
+mg_status check_k2(mg_ctx* c, const double* k2, hipStream_t s, std::string* why) {
+    launch_fill_words(s, c->k2_flags, 4, 0u);
+    launch_fill_words(s, c->k2_flags + 1, 4, 0x7fffffffu);
+    launch_check_k2(s, c->n, k2, c->k2_flags);
+    if (mg_status st = check_launch(c)) {
+        *why = c->err;
+        return st;
+    }
+    int flags[2] = {0, 0};
+    if (hipMemcpyAsync(flags, c->k2_flags, sizeof(flags), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        *why = "k2 check: copy of its result failed";
+        return MG_E_HIP;
+    }
+    if (flags[0] == 0) return MG_OK;
+    const int m = c->n + 1;
+    const int i = flags[1] % m, j = flags[1] / m;
+    std::string what;
+    if (flags[0] & 1) what += " non-finite values;";
+    if (flags[0] & 2) what += " negative values;";
+    if (flags[0] & 4) what += " zeros on the boundary;";
+    *why = "k2 must be finite, >= 0 and > 0 on the boundary: found" + what + " first at node (i, j) = (" +
+           std::to_string(i) + ", " + std::to_string(j) + ")";
+    return MG_E_ARG;
+}
+
 mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s) {
     const Grid g0 = c->lv[0].g;
     launch_k2_in(s, g0, k2, c->k2_64, c->k2_32);
@@ -627,6 +660,16 @@ mg_solve_opts default_solve_opts() {
     o.precision = MG_FP64;
     o.divergence = 1e8;
     return o;
+}
+
+// A caller's history buffer must hold max_cycles entries per right-hand side.
+mg_status check_stats(mg_ctx* c, const mg_solve_stats* stats, int nrhs, int max_cycles) {
+    if (stats && stats->history && (long long)stats->history_len < (long long)max_cycles * nrhs) {
+        c->err = "stats->history_len (" + std::to_string(stats->history_len) + ") < max_cycles * nrhs (" +
+                 std::to_string((long long)max_cycles * nrhs) + ")";
+        return MG_E_ARG;
+    }
+    return MG_OK;
 }
 
 mg_status check_solve_args(mg_ctx* c, int nrhs, double tol, int cyc, int smoother, const mg_solve_opts& o) {
@@ -1023,6 +1066,15 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
         return MG_E_HIP;
     }
     mg_status st = zero_workspace(c, s);
+    if (st == MG_OK) {
+        std::string why;
+        st = check_k2(c, k2, s, &why);
+        if (st != MG_OK) {
+            g_setup_error = why;
+            mg_destroy(c);
+            return st;
+        }
+    }
     if (st == MG_OK) st = build_hierarchy(c, k2, s);
     if (st == MG_OK && hipStreamSynchronize(s) != hipSuccess) {
         c->err = "setup synchronisation failed";
@@ -1041,6 +1093,13 @@ mg_status mg_update_k2(mg_handle c, const double* k2, void* stream) {
     if (!c) return MG_E_ARG;
     if (!is_dev_ptr_ok(k2)) { c->err = "k2 is NULL or misaligned"; return MG_E_ARG; }
     hipStream_t s = static_cast<hipStream_t>(stream);
+    {
+        std::string why;
+        if (mg_status st = check_k2(c, k2, s, &why)) {
+            c->err = why;
+            return st;
+        }
+    }
     if (mg_status st = build_hierarchy(c, k2, s)) return st;
     HM_HIP(hipStreamSynchronize(s));
     return MG_OK;
@@ -1051,6 +1110,7 @@ mg_status mg_solve(mg_handle c, const void* rhs, void* x, int nrhs, double tol, 
     if (!c) return MG_E_ARG;
     const mg_solve_opts o = opts ? *opts : default_solve_opts();
     if (mg_status st = check_solve_args(c, nrhs, tol, cyc, smoother, o)) return st;
+    if (mg_status st = check_stats(c, stats, nrhs, o.max_cycles)) return st;
     if (!is_dev_ptr_ok(rhs) || !is_dev_ptr_ok(x)) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
     hipStream_t s = static_cast<hipStream_t>(stream);
     LevelBuf& l0 = c->lv[0];
@@ -1122,6 +1182,7 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
         for (int q = 0; q < p; ++q)
             if (handles[q] == c) { g_setup_error = "handles must be distinct"; return MG_E_ARG; }
         if (mg_status st = check_solve_args(c, nrhs[p], tol, cyc, smoother, o)) return st;
+        if (mg_status st = check_stats(c, stats ? stats + p : nullptr, nrhs[p], o.max_cycles)) return st;
         if (!is_dev_ptr_ok(rhs[p]) || !is_dev_ptr_ok(x[p])) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1295,6 +1356,7 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
     const mg_solve_opts o = opts ? *opts : default_solve_opts();
     if (mg_status st = check_solve_args(c, nrhs, tol, cyc, smoother, o)) return st;
     if (m < 1 || m > kMaxRestart) { c->err = "restart length m must be in [1, 64]"; return MG_E_ARG; }
+    if (mg_status st = check_stats(c, stats, nrhs, o.max_cycles)) return st;
     if (!is_dev_ptr_ok(rhs) || !is_dev_ptr_ok(x)) { c->err = "rhs / x NULL or misaligned"; return MG_E_ARG; }
     if (!krylov || (reinterpret_cast<uintptr_t>(krylov) % kAlign) != 0) {
         c->err = "krylov buffer NULL or not 256-byte aligned";
@@ -1623,6 +1685,7 @@ mg_status mg_grad(mg_handle c, const void* u, const void* grad_u, int nsrc, doub
     if (!c) return MG_E_ARG;
     const mg_solve_opts o = opts ? *opts : default_solve_opts();
     if (mg_status st = check_solve_args(c, nsrc, tol, cyc, smoother, o)) return st;
+    if (mg_status st = check_stats(c, stats, nsrc, o.max_cycles)) return st;
     if (!is_dev_ptr_ok(u) || !is_dev_ptr_ok(grad_u) || !is_dev_ptr_ok(grad_k2)) {
         c->err = "u / grad_u / grad_k2 NULL or misaligned";
         return MG_E_ARG;

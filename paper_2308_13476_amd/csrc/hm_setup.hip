@@ -28,6 +28,25 @@ __global__ __launch_bounds__(kThreads) void k_k2_in(Grid g, const double* src, d
     }
 }
 
+// Checks the caller's k^2 field against the problem statement of §2 (k > 0
+// on the absorbing boundary, whose condition uses k = sqrt(k^2); k^2 >= 0
+// inside): flags[0] collects 1 for a non-finite value, 2 for a negative one
+// and 4 for a zero on the boundary, flags[1] the smallest offending index
+// (flags start as {0, INT_MAX}).
+__global__ __launch_bounds__(kThreads) void k_check_k2(int n, const double* src, int* flags) {
+    const long long m = n + 1;
+    for (long long q = blockIdx.x * (long long)kThreads + threadIdx.x; q < m * m; q += (long long)gridDim.x * kThreads) {
+        const int i = int(q % m), j = int(q / m);
+        const double v = src[q];
+        const bool edge = i == 0 || i == n || j == 0 || j == n;
+        const int bits = !isfinite(v) ? 1 : (v < 0.0 ? 2 : ((edge && v == 0.0) ? 4 : 0));
+        if (bits) {
+            atomicOr(flags, bits);
+            atomicMin(flags + 1, int(q));
+        }
+    }
+}
+
 // Coupling A(p, p + e) of the fine operator of a Galerkin product.
 // Level 0: the shifted Laplacian C_s = A_s - i beta2 W K^2, i.e. the scaled
 // 5-point operator of §2 with k^2 replaced by (1 + i beta2) k^2 (§4, §5).
@@ -492,6 +511,11 @@ unsigned blocks_for(long long work) {
 }
 
 }  // namespace
+
+void launch_check_k2(hipStream_t s, int n, const double* k2_dense, int* flags) {
+    const long long m = n + 1;
+    hipLaunchKernelGGL(k_check_k2, dim3(blocks_for(m * m)), dim3(kThreads), 0, s, n, k2_dense, flags);
+}
 
 void launch_k2_in(hipStream_t s, Grid g, const double* k2_dense, double* k2_64, float* k2_32) {
     const long long m = g.n + 1;

@@ -32,6 +32,14 @@ def _check(status: int, handle=None, ok=(B.MG_OK,)):
     return status
 
 
+def _stats(cycles, rel, hist=None) -> B.SolveStats:
+    """mg_solve_stats over ctypes arrays (hist may be None)."""
+    return B.SolveStats(ctypes.cast(cycles, ctypes.POINTER(ctypes.c_int)),
+                        ctypes.cast(rel, ctypes.POINTER(ctypes.c_double)),
+                        ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None,
+                        len(hist) if hist is not None else 0, 0.0)
+
+
 def _batched(t: torch.Tensor, n: int, dtype) -> torch.Tensor:
     if t.dim() == 2:
         t = t.unsqueeze(0)
@@ -115,9 +123,7 @@ class Solver:
         cycles = (ctypes.c_int * nb)()
         rel = (ctypes.c_double * nb)()
         hist = (ctypes.c_double * (nb * max_cycles))() if history else None
-        stats = B.SolveStats(ctypes.cast(cycles, ctypes.POINTER(ctypes.c_int)),
-                             ctypes.cast(rel, ctypes.POINTER(ctypes.c_double)),
-                             ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None, 0.0)
+        stats = _stats(cycles, rel, hist)
         st = B.lib().mg_solve(self.handle, _ptr(f), _ptr(x), nb, float(tol), _CYCLE[cycle], _SMOOTHER[smoother],
                               ctypes.byref(opts), ctypes.byref(stats), _stream())
         info = {"status": st, "status_name": B.status_string(st), "cycles": list(cycles), "relres": list(rel),
@@ -145,9 +151,7 @@ class Solver:
         cycles = (ctypes.c_int * nb)()
         rel = (ctypes.c_double * nb)()
         hist = (ctypes.c_double * (nb * max_iter))() if history else None
-        stats = B.SolveStats(ctypes.cast(cycles, ctypes.POINTER(ctypes.c_int)),
-                             ctypes.cast(rel, ctypes.POINTER(ctypes.c_double)),
-                             ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)) if hist is not None else None, 0.0)
+        stats = _stats(cycles, rel, hist)
         st = B.lib().mg_solve_fgmres(self.handle, _ptr(f), _ptr(x), nb, float(tol), int(m), _CYCLE[cycle],
                                      _SMOOTHER[smoother], ctypes.byref(opts), _ptr(kry), nbytes,
                                      ctypes.byref(stats), _stream())
@@ -189,9 +193,7 @@ class Solver:
         opts = Solver.solve_options(nu_pre, nu_post, omega, max_cycles, precision, divergence)
         cyc = [(ctypes.c_int * nb)() for nb in nbs]
         rel = [(ctypes.c_double * nb)() for nb in nbs]
-        stats = (B.SolveStats * npb)(*[B.SolveStats(ctypes.cast(c, ctypes.POINTER(ctypes.c_int)),
-                                                    ctypes.cast(r, ctypes.POINTER(ctypes.c_double)), None, 0.0)
-                                       for c, r in zip(cyc, rel)])
+        stats = (B.SolveStats * npb)(*[_stats(c, r) for c, r in zip(cyc, rel)])
         handles = (ctypes.c_void_p * npb)(*[S.handle for S in solvers])
         rp = (ctypes.c_void_p * npb)(*[_ptr(f) for f in fs])
         xp = (ctypes.c_void_p * npb)(*[_ptr(x) for x in xs])
@@ -219,8 +221,7 @@ class Solver:
         opts = self.solve_options(nu_pre, nu_post, omega, max_cycles, precision)
         cycles = (ctypes.c_int * nb)()
         rel = (ctypes.c_double * nb)()
-        stats = B.SolveStats(ctypes.cast(cycles, ctypes.POINTER(ctypes.c_int)),
-                             ctypes.cast(rel, ctypes.POINTER(ctypes.c_double)), None, 0.0)
+        stats = _stats(cycles, rel)
         st = B.lib().mg_grad(self.handle, _ptr(uu), _ptr(gu), nb, float(tol), _CYCLE[cycle], _SMOOTHER[smoother],
                              ctypes.byref(opts), _ptr(gk2), _ptr(grhs) if grhs is not None else None,
                              ctypes.byref(stats), _stream())

@@ -43,9 +43,19 @@ def stencil_to_csr(st: np.ndarray) -> sp.csr_matrix:
 
 
 def rel(a, b):
+    """Normwise relative difference ||a - b||_2 / ||b||_2."""
     a = np.asarray(a).ravel()
     b = np.asarray(b).ravel()
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def node_rel(a, b):
+    """Largest difference at any single node relative to the largest value,
+    max_p |a_p - b_p| / max_p |b_p|: a wrong boundary row or corner, which the
+    2-norm over a million nodes could hide, shows here at full size."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
 def level_shape(n_l):

@@ -61,3 +61,31 @@ def test_workspace_size_and_argument_checks_without_gpu():
                       ctypes.byref(h)) == B.MG_E_WORKSPACE
     assert L.mg_solve(None, fake, fake, 1, 1e-6, 1, 1, None, None, None) == B.MG_E_ARG
     assert L.mg_status_string(B.MG_E_DIVERGED) == b"MG_E_DIVERGED"
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets that a
+    C compiler gives the structs of include/helmg.h."""
+    import shutil
+    import subprocess
+    from paper_2308_13476_amd import _binding as B
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {"mg_setup_opts": B.SetupOpts, "mg_solve_opts": B.SolveOpts, "mg_solve_stats": B.SolveStats,
+             "mg_tune_result": B.TuneResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "helmg.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -3,6 +3,7 @@ adjoint-state gradient, finite differences and torch.autograd.gradcheck."""
 import numpy as np
 import pytest
 
+import oracle as O
 from oracle import adjoint
 from paper_2308_13476_amd import workloads as W
 from tests.gpu_common import require_gpu, to_gpu, to_np
@@ -94,8 +95,9 @@ def test_config5_gradient_n1024_16_sources():
     max kh 0.3), model k^2_0 = k^2_true Gaussian-smoothed (sigma 0.05), 16
     sources on the first interior row below the top, receivers on row
     round(0.1 n), data from FP64 solves at 1e-12. The adjoint gradient in FP64
-    and FP32-refined agree, and match central differences of the misfit at 20
-    seeded interior nodes (perturbed solves start from the unperturbed field)."""
+    and FP32-refined agree, and match central differences of the misfit
+    (step 1e-4 k^2) at 20 seeded interior nodes to 1e-5 per node, relative to
+    max(|fd|, 1e-3 max|g|)."""
     require_gpu()
     import torch
     from paper_2308_13476_amd.solver import Solver
@@ -125,27 +127,52 @@ def test_config5_gradient_n1024_16_sources():
     g32 = to_np(g32)
     assert np.linalg.norm(g32 - g64) / np.linalg.norm(g64) <= 1e-6
 
-    def misfit(k2v):
-        S.update_k2(to_gpu(k2v))
-        u, inf = S.solve(f, x0=u0, **kw)
+    # Central differences of the misfit with the contract's step eps = 1e-4 k^2
+    # at 20 seeded interior nodes. J(k2 +- eps e_p) is evaluated as
+    # 1/2 ||e0 + S delta||^2 with e0 = S u0 - d and u = u0 + delta, where delta
+    # solves the perturbed system A_s(k2 +- eps e_p) delta = W f - A_s(k2 +- eps e_p) u0
+    # (an exact rewriting of u = A_s^{-1} W f), so that
+    #   J+ - J- = Re <e0, S (delta+ - delta-)> + (||S delta+||^2 - ||S delta-||^2) / 2
+    # carries no cancellation: forming J+ and J- separately and subtracting
+    # them loses about ten of FP64's sixteen digits here (their difference is
+    # ~1e-10 of J), which is the noise floor measured below.
+    def misfit_direct(x0):
+        u, inf = S.solve(f, x0=x0, **kw)
         assert inf["status"] == 0
         return 0.5 * float(torch.sum(torch.abs(u[:, row, :] - d) ** 2))
 
-    # Central differences with a step of 1% of k^2 at the node: the misfit
-    # differences are then well above the noise that solves to relres 1e-12
-    # leave in the misfit (smaller steps were noise-dominated; a fourth-order
-    # formula gave the same values, so truncation is not what limits it).
+    e0 = u0[:, row, :] - d
+    Wt = to_gpu(O.node_weights(n))
+
+    def delta_difference(kp, km):
+        out = []
+        for kv in (kp, km):
+            S.update_k2(to_gpu(kv))
+            r = S.residual(0, u0, Wt * f)  # W f - A_s(k2') u0
+            dlt, inf = S.solve(r / Wt, tol=1e-12, max_cycles=600)
+            assert inf["status"] == 0
+            out.append(dlt[:, row, :])
+        dp, dm = out
+        lin = float(torch.sum((e0.conj() * (dp - dm)).real))
+        quad = 0.5 * float(torch.sum(torch.abs(dp) ** 2) - torch.sum(torch.abs(dm) ** 2))
+        return lin + quad
+
+    J0 = misfit_direct(None)
+    J1 = misfit_direct(0.5 * u0)  # the same solve from another start
     scale = np.abs(g64).max()
     errs = []
     for (i, j) in W.seeded_interior_nodes(n, 20, 5):
-        eps = 1e-2 * k2[j, i]
+        eps = 1e-4 * k2[j, i]
         kp = k2.copy()
         kp[j, i] += eps
         km = k2.copy()
         km[j, i] -= eps
-        fd = (misfit(kp) - misfit(km)) / (2 * eps)
-        errs.append((abs(fd - g64[j, i]), abs(fd - g64[j, i]) / abs(fd), (i, j), fd, g64[j, i]))
-    print("config 5 finite differences: max |fd - g| / max|g| =", max(e[0] for e in errs) / scale,
-          "max per-node relative error =", max(e[1] for e in errs))
-    assert max(e[0] for e in errs) <= 1e-5 * scale, sorted(errs)[-3:]
-    assert max(e[1] for e in errs) <= 1e-4, sorted(errs, key=lambda e: e[1])[-3:]
+        dJ = delta_difference(kp, km)
+        fd = dJ / (2 * eps)
+        errs.append((abs(fd - g64[j, i]) / max(abs(fd), 1e-3 * scale), (i, j), fd, g64[j, i], dJ))
+    S.update_k2(to_gpu(k2))
+    typical = float(np.median([abs(e[4]) for e in errs]))
+    print(f"config 5: misfit J = {J0:.6e}; two FP64 solves to 1e-12 from different starts differ in J by "
+          f"{abs(J0 - J1):.2e}, against a median |J+ - J-| = {typical:.2e} at eps = 1e-4 k^2; largest "
+          f"|fd - g| / max(|fd|, 1e-3 max|g|) = {max(e[0] for e in errs):.2e}")
+    assert max(e[0] for e in errs) <= 1e-5, sorted(errs)[-3:]

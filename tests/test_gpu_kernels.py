@@ -9,7 +9,7 @@ import scipy.linalg as sla
 
 import oracle as O
 from paper_2308_13476_amd import workloads as W
-from tests.gpu_common import rel, require_gpu, stencil_to_csr, to_gpu, to_np
+from tests.gpu_common import node_rel, rel, require_gpu, stencil_to_csr, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -77,6 +77,7 @@ def test_operator_apply_and_residual(case):
         for b in range(3):
             yr = H.A[l] @ x[b].ravel()
             assert rel(y[b], yr) <= 1e-13, (l, b)
+            assert node_rel(y[b], yr) <= 1e-13, (l, b, node_rel(y[b], yr))
             assert rel(r[b], f[b].ravel() - yr) <= 1e-13
         y32 = to_np(S.apply(l, to_gpu(x.astype(np.complex64)), precision="fp32_refined"))
         assert y32.dtype == np.complex64
@@ -93,6 +94,7 @@ def test_restriction_and_prolongation(case):
         pf = to_np(S.prolong_add(l, to_gpu(coarse), to_gpu(fine)))
         for b in range(2):
             assert rel(rc[b], H.R[l] @ fine[b].ravel()) <= 1e-14
+            assert node_rel(rc[b], H.R[l] @ fine[b].ravel()) <= 1e-14
             assert rel(pf[b], fine[b].ravel() + H.P[l] @ coarse[b].ravel()) <= 1e-14
 
 
@@ -109,10 +111,12 @@ def test_jacobi_and_gmres_smoothing(case):
             for _ in range(3):
                 ref = O.jacobi_step(H.A[l], ref, f[b].ravel(), 4.5)
             assert rel(uj[b], ref) <= 1e-12, (l, b)
+            assert node_rel(uj[b], ref) <= 1e-12, (l, b)
             ref = u[b].ravel()
             for _ in range(2):
                 ref = O.gmres_step(H.A[l], ref, f[b].ravel())
             assert rel(ug[b], ref) <= 1e-10, (l, b, rel(ug[b], ref))
+            assert node_rel(ug[b], ref) <= 1e-10, (l, b, node_rel(ug[b], ref))
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])

@@ -8,7 +8,7 @@ import pytest
 
 import oracle as O
 from paper_2308_13476_amd import workloads as W
-from tests.gpu_common import rel, require_gpu, to_gpu, to_np
+from tests.gpu_common import node_rel, rel, require_gpu, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -45,6 +45,7 @@ def test_solve_matches_oracle(smoother, beta, cyc, nu):
     assert abs(info["cycles"][0] - ref.cycles) <= 1
     same = O.solve(H, fs, opts, tol=1e-30, max_cycles=info["cycles"][0])
     assert rel(to_np(x)[0], same.x) <= 1e-10
+    assert node_rel(to_np(x)[0], same.x) <= 1e-10
     assert np.linalg.norm(fs - H.A[0] @ to_np(x)[0].ravel()) / np.linalg.norm(fs) <= 1e-6
 
 

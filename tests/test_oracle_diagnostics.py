@@ -97,3 +97,32 @@ def test_table2_trends_at_omega_4_5():
     for vals in (paper1, paper2, v1, v2):
         assert all(a > b for a, b in zip(vals, vals[1:]))
     assert all(b > a for a, b in zip(paper1, paper2)) and all(b > a for a, b in zip(v1, v2))
+
+
+def test_optimality_value_against_explicit_norms_and_a_hand_worked_case():
+    # ||B||_1 / kappa_1(B) with kappa_1 = ||B||_1 ||B^{-1}||_1 from an explicit
+    # inverse (column sums of moduli), on a Hermitian positive definite matrix
+    rng = np.random.default_rng(11)
+    Z = rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9))
+    B = Z @ Z.conj().T + 0.5 * np.eye(9)
+    Binv = np.linalg.inv(B)
+    n1 = np.abs(B).sum(axis=0).max()
+    kappa = n1 * np.abs(Binv).sum(axis=0).max()
+    assert TG.optimality_value(B) == pytest.approx(n1 / kappa, rel=1e-12)
+    # by hand: B = [[2, i], [-i, 2]] has B^{-1} = [[2, -i], [i, 2]] / 3, so
+    # ||B||_1 = 3, ||B^{-1}||_1 = 1, kappa_1 = 3 and the value is 3 / 3 = 1
+    B2 = np.array([[2.0, 1j], [-1j, 2.0]])
+    assert TG.optimality_value(B2) == pytest.approx(1.0, rel=1e-14)
+    # diag(1, 4): ||B||_1 = 4, kappa_1 = 4, value 1 = the smallest eigenvalue
+    assert TG.optimality_value(np.diag([1.0, 4.0])) == pytest.approx(1.0, rel=1e-14)
+
+
+def test_two_smoothing_steps_give_the_expanded_approximate_inverse():
+    # nu = 2: (I - S^2) A^{-1} with S = I - X^{-1} A expands to
+    # 2 X^{-1} - X^{-1} A X^{-1}, which needs no inverse of A
+    A, M, Q = TG.two_grid_parts(5, 8, nu=2, omega=4.5)
+    Xi = np.diag(1.0 / (4.5 * np.diag(A)))
+    np.testing.assert_allclose(M, 2 * Xi - Xi @ A @ Xi, atol=1e-12 * np.abs(M).max())
+    # the coarse part is a projection-like map: Q A Q = Q when A_c = R A P
+    A2, M2, Q2 = TG.two_grid_parts(5, 8, coarse_on="A")
+    np.testing.assert_allclose(Q2 @ A2 @ Q2, Q2, atol=1e-9 * np.abs(Q2).max())
