@@ -245,6 +245,22 @@ mg_status mg_apply(mg_handle h, int level, const void* x, void* y, int nvec, int
 mg_status mg_residual(mg_handle h, int level, const void* x, const void* f, void* r, int nvec, int precision,
                       void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid allocation): the same r = f - A_l x as
+ * mg_residual, bit for bit, but x, f and r are staged through a static device
+ * scratch array of the library (64 MiB per GPU, held from the first mg_setup
+ * on a device until the process ends) instead of the handle's level buffers,
+ * which stay untouched. It calls no allocating routine, copies nothing through
+ * the host and does not synchronise: the kernels are enqueued on stream and r
+ * is ready when the stream reaches them. 3 * nvec padded planes of the level
+ * (about 3 * nvec * 18 MB for complex128 at n = 1024) must fit the 64 MiB,
+ * else MG_E_ARG; nvec need not respect max_batch. The handle's device must be
+ * current. Every call on one GPU shares its scratch: calls that overlap on
+ * that GPU (other streams, other threads, other handles) race and must be
+ * ordered by the caller. */
+mg_status mg_residual_noalloc(mg_handle h, int level, const void* x, const void* f, void* r, int nvec,
+                              int precision, void* stream);
+
 /* nsteps smoothing steps on A_l u = f in place: MG_JACOBI with parameter omega
  * (§3) or MG_GMRES3 (§5.3, omega ignored). */
 mg_status mg_smooth(mg_handle h, int level, int smoother, int nsteps, double omega, void* u, const void* f,

@@ -23,6 +23,7 @@ EXPORTED = [
     "mg_workspace_bytes", "mg_setup", "mg_update_k2", "mg_solve", "mg_solve_multi", "mg_tune",
     "mg_fgmres_workspace_bytes", "mg_solve_fgmres", "mg_grad", "mg_destroy",
     "mg_status_string", "mg_last_error", "mg_level_info", "mg_get_stencil", "mg_apply", "mg_residual",
+    "mg_residual_noalloc",
     "mg_smooth", "mg_restrict", "mg_prolong_add", "mg_coarse_solve", "mg_cycle", "mg_set_timing",
     "mg_get_timing",
 ]
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
         "mg_get_stencil": (ci, [vp, ci, vp, vp]),
         "mg_apply": (ci, [vp, ci, vp, vp, ci, ci, vp]),
         "mg_residual": (ci, [vp, ci, vp, vp, vp, ci, ci, vp]),
+        "mg_residual_noalloc": (ci, [vp, ci, vp, vp, vp, ci, ci, vp]),
         "mg_smooth": (ci, [vp, ci, ci, ci, cd, vp, vp, ci, ci, vp]),
         "mg_restrict": (ci, [vp, ci, vp, vp, ci, ci, vp]),
         "mg_prolong_add": (ci, [vp, ci, vp, vp, ci, ci, vp]),

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,33 @@ using namespace hm;
 namespace {
 
 thread_local std::string g_setup_error;
+
+// Device scratch of mg_residual_noalloc: a file-scope array that every GPU the
+// library runs on holds until the process ends. Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (with that device current), and is
+// kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch address on the current device, looked up on the first call per
+// device.
+hipError_t static_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxCoarseNodes = 1089;
@@ -69,6 +97,7 @@ struct Carver {
 
 struct mg_ctx {
     int n = 0, L = 0, transfer = 0, max_batch = 1, has32 = 0, coarsest_n = 4;
+    int device = -1;  // HIP device current at mg_setup (the workspace's device)
     double h = 0.0, shift = 0.0;
     std::vector<LevelBuf> lv;
     double* k2_64 = nullptr;
@@ -1049,6 +1078,18 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
         pick_tail_levels(c, tail_n);
     }
     tail_init();
+    {
+        // the device and, once per device, the address of the static scratch
+        // of mg_residual_noalloc (looked up here, at set-up, with the device current)
+        void* scr = nullptr;
+        hipError_t e = hipGetDevice(&c->device);
+        if (e == hipSuccess) e = static_scratch(c->device, &scr);
+        if (e != hipSuccess) {
+            g_setup_error = std::string("device scratch lookup: ") + hipGetErrorString(e);
+            delete c;
+            return MG_E_HIP;
+        }
+    }
     carve(c, c->ws, n, L, transfer, max_batch, has32);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_norms), sizeof(RhsNorms) * max_batch, hipHostMallocDefault) !=
@@ -1835,6 +1876,28 @@ mg_status level_op_run(mg_ctx* c, int kind, int level, const void* a, const void
     return MG_OK;
 }
 
+// r = f - A_l x with x, f and r staged through the static device scratch
+// (nvec planes each, x's planes zeroed first so that its ghost frame reads
+// zero): the kernels of mg_residual, enqueued only.
+template <typename T>
+mg_status residual_static(mg_ctx* c, int level, const void* x, const void* f, void* r, int nvec, char* scr,
+                          hipStream_t s) {
+    const LevelBuf& lb = c->lv[level];
+    const bool f32 = sizeof(T) == 4;
+    const size_t pbytes = align_up(size_t(lb.g.plane) * sizeof(cplx<T>) * size_t(nvec), kAlign);
+    cplx<T>* X = reinterpret_cast<cplx<T>*>(scr);
+    cplx<T>* F = reinterpret_cast<cplx<T>*>(scr + pbytes);
+    cplx<T>* Rr = reinterpret_cast<cplx<T>*>(scr + 2 * pbytes);
+    LaunchCtx lc = launch_ctx(c, s, nvec);
+    lc.active = nullptr;
+    launch_fill_words(s, X, (long long)pbytes, 0u);
+    launch_copy_in<T>(lc, lb.g, x, f32, vec<T>(X, lb), false, false);
+    launch_copy_in<T>(lc, lb.g, f, f32, vec<T>(F, lb), false, false);
+    launch_residual<T>(lc, level_op<T>(c, level), vec<T>(X, lb), vec<T>(F, lb), vec<T>(Rr, lb));
+    launch_copy_out<T>(lc, lb.g, vec<T>(Rr, lb), r, f32, false, false);
+    return check_launch(c);
+}
+
 mg_status level_entry(mg_ctx* c, int kind, int level, const void* a, const void* b, void* out, int nvec,
                       int precision, int smoother, int nsteps, double omega, void* stream) {
     if (nvec < 1 || nvec > c->max_batch) { c->err = "nvec must be in [1, max_batch]"; return MG_E_ARG; }
@@ -1861,6 +1924,35 @@ mg_status mg_residual(mg_handle c, int level, const void* x, const void* f, void
     if (mg_status st = check_level(c, level, precision, true)) return st;
     if (!is_dev_ptr_ok(x) || !is_dev_ptr_ok(f) || !is_dev_ptr_ok(r)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
     return level_entry(c, 1, level, x, f, r, nvec, precision, 0, 0, 0.0, stream);
+}
+
+mg_status mg_residual_noalloc(mg_handle c, int level, const void* x, const void* f, void* r, int nvec, int precision,
+                              void* stream) {
+    if (!c) return MG_E_ARG;
+    if (mg_status st = check_level(c, level, precision, true)) return st;
+    if (!is_dev_ptr_ok(x) || !is_dev_ptr_ok(f) || !is_dev_ptr_ok(r)) { c->err = "NULL or misaligned vector"; return MG_E_ARG; }
+    if (nvec < 1) { c->err = "nvec must be >= 1"; return MG_E_ARG; }
+    const size_t elem = precision == MG_FP64 ? 16 : 8;
+    const size_t need = 3 * align_up(size_t(c->lv[level].g.plane) * elem * size_t(nvec), kAlign);
+    if (need > kStaticScratchBytes) {
+        c->err = "mg_residual_noalloc: 3 x nvec padded planes of level " + std::to_string(level) + " need " +
+                 std::to_string(need) + " bytes, beyond the " + std::to_string(kStaticScratchBytes) +
+                 "-byte static scratch";
+        return MG_E_ARG;
+    }
+    int dev = -1;
+    HM_HIP(hipGetDevice(&dev));
+    if (dev != c->device) {
+        c->err = "mg_residual_noalloc: the handle's device (set up on " + std::to_string(c->device) +
+                 ") must be current";
+        return MG_E_ARG;
+    }
+    void* scr = nullptr;
+    HM_HIP(static_scratch(dev, &scr));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(scr);
+    if (precision == MG_FP64) return residual_static<double>(c, level, x, f, r, nvec, base, s);
+    return residual_static<float>(c, level, x, f, r, nvec, base, s);
 }
 
 mg_status mg_smooth(mg_handle c, int level, int smoother, int nsteps, double omega, void* u, const void* f, int nvec,

@@ -257,6 +257,17 @@ class Solver:
                                    _stream()), self.handle)
         return r
 
+    def residual_noalloc(self, level: int, x: torch.Tensor, f: torch.Tensor, r: torch.Tensor, precision="fp64"):
+        """mg_residual_noalloc into the caller's r (nothing allocated, nothing
+        synchronised: r is ready when the current stream reaches the kernels).
+        Returns the status; raises on an error status."""
+        xv = self._lvl_vec(x, level, precision)
+        fv = self._lvl_vec(f, level, precision)
+        if r.shape != xv.shape or r.dtype != xv.dtype or not r.is_contiguous():
+            raise ValueError("r must be a contiguous tensor of x's shape and dtype")
+        return _check(B.lib().mg_residual_noalloc(self.handle, level, _ptr(xv), _ptr(fv), _ptr(r), xv.shape[0],
+                                                  _PREC[precision], _stream()), self.handle)
+
     def smooth(self, level: int, u: torch.Tensor, f: torch.Tensor, smoother="jacobi", nsteps=1, omega=4.5,
                precision="fp64") -> torch.Tensor:
         uv = self._lvl_vec(u, level, precision).clone()
