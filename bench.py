@@ -39,6 +39,13 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = {
     1: {"name": "level-0 GMRES(3) orthogonalise + apply pass (complex64)", "bytes_per_node": 40.0},
 }
+# The same pass on complex128 data with an 8-byte k^2: 3*16 + 8 + 16 = 72 B,
+# plus 16 B for w_2 in one of the two launches per cycle, 80 B on average.
+CLASS1_FP64_BYTES_PER_NODE = 80.0
+# In a batch the k^2 plane (4 B per node, complex64 cycle) is one input shared
+# by every right-hand side: 36 B per node and right-hand side without it.
+CLASS1_FP32_VECTOR_BYTES = 36.0
+CLASS1_FP32_K2_BYTES = 4.0
 
 # HBM traffic of the class-1 kernel per launch from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE; profiles/ holds the summary and the commands), each
@@ -64,6 +71,53 @@ def sources_sha256():
     return h.hexdigest()
 
 
+def class1_roofline(S, run, bytes_of, what):
+    """Times every launch of the level-0 orthogonalise + apply pass (kernel
+    class 1, start/stop events recorded by its own dispatch) over run();
+    bytes_of(nodes_per_launch) gives its algorithmic bytes per launch."""
+    import torch
+    S.set_timing(1)
+    torch.cuda.synchronize()
+    run()
+    torch.cuda.synchronize()
+    launches, kms, knodes = S.get_timing()
+    S.set_timing(0)
+    if launches == 0:
+        return None
+    avg_ms = kms / launches
+    nbytes = bytes_of(knodes)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": what, "avg_launch_us": avg_ms * 1e3,
+            "launches": launches, "algorithmic_bytes_per_launch": nbytes}
+
+
+def beyond_cache_roofline(steps):
+    """The roofline kernel on a working set far beyond the 256 MB Infinity
+    Cache: MP 2-A at n = 2048 (4,198,401 unknowns, k = 400, kh ~ 0.2), FP64
+    GMRES(3) V(1,1) cycles, where one complex128 plane is ~70 MB and the
+    level-0 pass touches six of them."""
+    import torch
+
+    from paper_2308_13476_amd import workloads as W
+    from paper_2308_13476_amd.solver import Solver
+
+    dev = torch.device("cuda:0")
+    n, k = 2048, 400.0
+    S = Solver(torch.from_numpy(W.constant_k2(n, k)).to(dev), 1.0 / n, 1.0 / k)
+    f = torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev)
+    S.solve(f, tol=1e-30, max_cycles=1)  # warm-up: captures nothing while timing is on
+    r = class1_roofline(S, lambda: S.solve(f, tol=1e-30, max_cycles=steps),
+                        lambda nodes: CLASS1_FP64_BYTES_PER_NODE * nodes,
+                        "level-0 GMRES(3) orthogonalise + apply pass (complex128), n=2048")
+    del S
+    torch.cuda.empty_cache()
+    if r is not None:
+        r["workload"] = (f"MP 2-A n={n} ({(n + 1) ** 2} unknowns), k={k:g}, FP64 GMRES(3) V(1,1), {steps} cycles; "
+                         f"working set beyond the Infinity Cache")
+    return r
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,13 +126,18 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--k", type=float, default=200.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-settings", action="store_true",
+                    help="skip the W(1,1) and Jacobi V(4,4) time-to-tolerance measurements")
+    ap.add_argument("--no-beyond-cache", action="store_true",
+                    help="skip the n=2048 FP64 roofline measurement beyond the Infinity Cache")
     ap.add_argument("--cpu-cycles", type=int, default=36, help="oracle cycles in the CPU sample")
     ap.add_argument("--kernel-class", type=int, default=1)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run a plain elementwise copy of this many MiB (reference for HBM counters)")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (mg_tune) on the FP32-refined cycle before timing")
-    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres", "media2048", "mp2b"], default="mp2a",
+    ap.add_argument("--workload", choices=["mp2a", "batch64", "mixed32", "fgmres", "media2048", "mp2b", "roofline2048"],
+                    default="mp2a",
                     help="mp2a: the headline n=1024 solve (default); batch64: 64 sources on n=512 in one "
                          "batched solve; mixed32: 32 problems n=128..1024 solved together")
     return ap.parse_args()
@@ -108,6 +167,11 @@ def batch_workloads(args):
         sizes = [n]
         config = {"workload": "64 point sources at seeded interior nodes, n=512, k=100, shift 1/k, GMRES(3) V(1,1), "
                               "FP32-refined, tol 1e-6, one batched solve", "n": n, "k": k, "batch": 64}
+        nb = 64
+        roof = lambda: class1_roofline(  # noqa: E731
+            S, lambda: S.solve(f, tol=1e-30, max_cycles=3, cycle="V", smoother="gmres", precision="fp32_refined"),
+            lambda nodes: CLASS1_FP32_VECTOR_BYTES * nodes + CLASS1_FP32_K2_BYTES * nodes / nb,
+            "level-0 GMRES(3) orthogonalise + apply pass (complex64), 64 right-hand sides per launch")
     else:
         order = np.random.default_rng(4).permutation(np.repeat([128, 256, 512, 1024], 8))
         solvers, rhs = [], []
@@ -118,6 +182,7 @@ def batch_workloads(args):
                                   precision="fp32_refined"))
             rhs.append(torch.from_numpy(W.point_source_rhs(n, [W.center_node(n)])).to(dev))
         run = lambda: [info for _, info in Solver.solve_multi(solvers, rhs, **kw)]  # noqa: E731
+        roof = None
         sizes = [int(n) for n in order]
         config = {"workload": "32 problems, n in {128,256,512,1024} x 8 (seeded order), k=0.3n, centre source, "
                               "shift 1/k, GMRES(3) V(1,1), FP32-refined, tol 1e-6, solved together",
@@ -135,7 +200,8 @@ def batch_workloads(args):
            "unit": "DOF/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64 cycle in c128 refinement",
            "data": "synthetic", "config": config,
-           "cycles": [c for info in infos for c in info["cycles"]], "roofline": None, "cpu_baseline": None}
+           "cycles": [c for info in infos for c in info["cycles"]], "roofline": roof() if roof else None,
+           "cpu_baseline": None}
     if args.workload == "mixed32":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -317,6 +383,16 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration_mib > 0:
+        # reads and writes exactly copy_calibration_mib MiB per launch: the reference
+        # against which FETCH_SIZE / WRITE_SIZE of the solver kernels are scaled
+        import torch
+        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "fgmres":
         fgmres_workload(args)
         return
@@ -325,6 +401,10 @@ def main():
         return
     if args.workload == "mp2b":
         mp2b_workload(args)
+        return
+    if args.workload == "roofline2048":
+        # only the beyond-cache roofline measurement (for the HBM counter runs)
+        print(json.dumps({"roofline_beyond_cache": beyond_cache_roofline(args.steps)}))
         return
     if args.workload != "mp2a":
         batch_workloads(args)
@@ -336,15 +416,6 @@ def main():
     from paper_2308_13476_amd.solver import Solver
 
     dev = torch.device("cuda:0")
-    if args.copy_calibration_mib > 0:
-        # reads and writes exactly copy_calibration_mib MiB per launch: the reference
-        # against which FETCH_SIZE / WRITE_SIZE of the solver kernels are scaled
-        src = torch.ones(args.copy_calibration_mib << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.add(src, 0.0, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
     n, k = args.n, args.k
     beta = 1.0 / k
     nodes = (n + 1) ** 2
@@ -392,6 +463,29 @@ def main():
     print(f"bench: fp64 {r64['ms_per_step']:.2f} ms/step, {r64['cycles_per_solve']:.0f} cycles", file=sys.stderr,
           flush=True)
 
+    # the other cycle / smoother settings of the same workload (§5.1 Table 4:
+    # weighted Jacobi V(4,4) with shift 0.7; §5.3.1 Table 8: GMRES(3) W(1,1)),
+    # time to tolerance with the hierarchy set up beforehand
+    settings = {}
+    if not args.no_other_settings:
+        def solve_time(solver, precision, reps=2, **kw):
+            kw = dict(solve_kw, **kw)
+            solver.solve(f, precision=precision, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, info = solver.solve(f, precision=precision, **kw)
+                assert info["status"] == 0, info
+            torch.cuda.synchronize()
+            return {"ms": (time.perf_counter() - t0) / reps * 1e3, "cycles": info["cycles"][0]}
+        settings["gmres_W11_shift_1_over_k"] = {"fp32_refined": solve_time(S, "fp32_refined", cycle="W"),
+                                                "fp64": solve_time(S, "fp64", cycle="W")}
+        S07 = Solver(k2, 1.0 / n, 0.7)
+        settings["jacobi_V44_shift_0.7"] = {"fp64": solve_time(S07, "fp64", reps=1, smoother="jacobi", nu_pre=4,
+                                                               nu_post=4, max_cycles=1000)}
+        del S07
+        print(f"bench: other settings {settings}", file=sys.stderr, flush=True)
+
     value = nodes * r32["cycles_per_solve"] * args.steps / (r32["ms_total"] * 1e-3)
     out = {
         "metric": METRIC,
@@ -416,6 +510,7 @@ def main():
         "vcycle_dof_per_s": {"fp32_refined": value,
                              "fp64": nodes * r64["cycles_per_solve"] / (r64["ms_per_step"] * 1e-3)},
         "fp32_refined_speedup_vs_fp64": r64["ms_per_step"] / r32["ms_per_step"],
+        "other_settings_solve_ms": settings or None,
     }
     if tuned is not None:
         out["tuned_settings"] = tuned
@@ -446,6 +541,9 @@ def main():
                            "avg_launch_us": avg_ms * 1e3, "launches": launches,
                            "timed_in": "repeat of the timed steps; HIP start/stop events recorded by each "
                                        "launch's own dispatch (hipExtLaunchKernelGGL), no graphs"}
+    if not args.no_beyond_cache:
+        print("bench: roofline kernel beyond the Infinity Cache (n=2048, FP64)", file=sys.stderr, flush=True)
+        out["roofline_beyond_cache"] = beyond_cache_roofline(max(2, args.steps // 2))
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, k, args.cpu_cycles)

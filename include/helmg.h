@@ -67,6 +67,13 @@ typedef struct {
     int precision;   /* MG_FP32_REFINED also builds complex64 copies of the hierarchy */
     int max_batch;   /* largest nrhs / nsrc used with this handle (>= 1)              */
     int coarsest_n;  /* intervals per side of the coarsest grid when levels = 0 (4)   */
+    int use_graph;   /* 0 or 1: cycles are captured as HIP graphs and replayed (the
+                        default); -1: kernels are launched one by one             */
+    const char* tune_cache; /* NULL, or a JSON file of autotuned launch settings:
+                        mg_tune takes its settings from a matching entry there
+                        instead of timing, and records new ones (the path is
+                        copied; the file is rewritten whole, so concurrent
+                        writers may lose entries)                                */
 } mg_setup_opts;
 
 typedef struct {
@@ -159,17 +166,26 @@ typedef struct {
                             single-workgroup LDS tail (0: none)                 */
     int level1_product;  /* level 1 as R C_s P: 0 never, 1 in FP32 cycles, 2 both */
     double ms_per_cycle; /* measured time of one cycle with these settings      */
-    int candidates;      /* settings timed                                      */
+    int candidates;      /* settings timed (0 when taken from the cache)        */
+    int tall_rows;       /* tile shape: block height (wavefronts) of light
+                            kernels on grids of >= 256 intervals (4 or 8)       */
+    int small_rows;      /* block height on grids of <= 128 intervals (2 or 4)  */
+    int from_cache;      /* 1 when the settings came from the tuning cache      */
 } mg_tune_result;
 
 /* Autotuner (a launch-setting search; the method is unchanged): times three
  * captured cycles of the given problem (rhs [dev] complex128 [nrhs][n+1][n+1]
  * as in mg_solve, zero initial guess) for each combination of block cap
- * {320, 640, 1280}, tail size {0, 16, 32} and level-1 operator {stored,
- * product}, keeps the fastest on the handle for later solves and reports it
- * in *out (may be NULL). Overwrites the handle's iterates; results of later
- * solves are those of the chosen settings (equal to any other setting up to
- * rounding). MG_E_STATE while the timing hook is on. */
+ * {320, 640, 1280}, tail size {0, 16, 32}, level-1 operator {stored,
+ * product} and tile shape (block heights {4, 8} on grids of >= 256 intervals
+ * and {2, 4} on grids of <= 128), keeps the fastest on the handle for later
+ * solves and reports it in *out (may be NULL). With a tune_cache file (see
+ * mg_setup_opts) a matching entry (same grid, levels, transfer, nrhs, cycle,
+ * smoother, nu, precision and GPU architecture) is applied without timing,
+ * and a new result is added to the file. Overwrites the handle's iterates;
+ * results of later solves are those of the chosen settings (equal to any
+ * other setting up to rounding). MG_E_STATE while the timing hook is on;
+ * MG_E_ARG if the cache file cannot be written. */
 mg_status mg_tune(mg_handle h, const void* rhs, int nrhs, int cycle, int smoother, const mg_solve_opts* opts,
                   mg_tune_result* out, void* stream);
 

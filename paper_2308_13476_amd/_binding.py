@@ -30,7 +30,8 @@ EXPORTED = [
 
 
 class SetupOpts(ctypes.Structure):
-    _fields_ = [("precision", ctypes.c_int), ("max_batch", ctypes.c_int), ("coarsest_n", ctypes.c_int)]
+    _fields_ = [("precision", ctypes.c_int), ("max_batch", ctypes.c_int), ("coarsest_n", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -46,7 +47,8 @@ class SolveStats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("block_cap", ctypes.c_int), ("tail_n", ctypes.c_int), ("level1_product", ctypes.c_int),
-                ("ms_per_cycle", ctypes.c_double), ("candidates", ctypes.c_int)]
+                ("ms_per_cycle", ctypes.c_double), ("candidates", ctypes.c_int), ("tall_rows", ctypes.c_int),
+                ("small_rows", ctypes.c_int), ("from_cache", ctypes.c_int)]
 
 
 class MGError(RuntimeError):

@@ -57,6 +57,8 @@ struct LaunchCtx {
     int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
     int fuse_correction = 1;  // 0: the coarse grid correction always runs as its own pass
     StopTest stop{};          // taken by the residual-norm pass when stop.ring is set
+    int tall_rows = 4;        // block height of light kernels on grids of >= 256 intervals (4, 8, 16)
+    int small_rows = 2;       // block height on grids of <= 128 intervals (2 or 4)
 };
 
 // The operator of one level: analytic on level 0 (from k^2), stored Galerkin

@@ -11,36 +11,19 @@ namespace hm {
 namespace {
 
 constexpr int kThreads = kBX * kBY;
-constexpr int kTallDefault = 4;
 
-// Block height: 64 x 4 for register-heavy Galerkin stencils and small grids;
-// light kernels on grids of 256 or more intervals use tall_rows() rows
-// (HELMG_TALL_BLOCKS = 4, 8 or 16; default below).
-int tall_rows() {
-    static const int v = [] {
-        int r = kTallDefault;
-        if (const char* e = std::getenv("HELMG_TALL_BLOCKS")) r = std::atoi(e);
-        return (r == 8 || r == 16) ? r : kBY;
-    }();
-    return v;
-}
-// Grids of at most 128 intervals: small_rows() rows (HELMG_SMALL_ROWS = 2 or
-// 4; default 2). Their passes are latency-bound, and two wavefronts per block
-// shorten each block's reductions and spread a pass over twice the compute
-// units. Tiles keep an even first row, which the staging of the coarse grid
-// correction relies on (it takes coarse row r0 / 2 as its reference).
-constexpr int kSmallDefault = 2;
-int small_rows() {
-    static const int v = [] {
-        int r = kSmallDefault;
-        if (const char* e = std::getenv("HELMG_SMALL_ROWS")) r = std::atoi(e);
-        return r == 4 ? kBY : kSmallDefault;
-    }();
-    return v;
-}
-int block_rows(const Grid& g, bool heavy) {
-    if (g.n <= 128) return small_rows();
-    return (!heavy && g.n >= 256) ? tall_rows() : kBY;
+// Block height: 64 x 4 for register-heavy Galerkin stencils; light kernels
+// on grids of 256 or more intervals use ctx.tall_rows rows (4, 8 or 16), and
+// grids of at most 128 intervals ctx.small_rows (2 or 4): their passes are
+// latency-bound, and two wavefronts per block shorten each block's
+// reductions and spread a pass over twice the compute units. Tiles keep an
+// even first row, which the staging of the coarse grid correction relies on
+// (it takes coarse row r0 / 2 as its reference). The handle's settings come
+// from the environment at set-up or from the autotuner.
+int block_rows(const Grid& g, bool heavy, const LaunchCtx& ctx) {
+    if (g.n <= 128) return ctx.small_rows == 4 ? kBY : 2;
+    if (heavy || g.n < 256) return kBY;
+    return (ctx.tall_rows == 8 || ctx.tall_rows == 16) ? ctx.tall_rows : kBY;
 }
 
 // Rows per thread: enough that a level grid has at most `cap` blocks (the
@@ -62,11 +45,11 @@ struct Geom {
     dim3 grid, block;
 };
 
-Geom geom(const Grid& g, bool heavy, int nrhs, int cap) {
+Geom geom(const Grid& g, bool heavy, const LaunchCtx& ctx) {
     Geom q;
-    q.by = block_rows(g, heavy);
-    q.rpt = level_rpt(g, q.by, cap);
-    q.grid = level_grid(g, q.rpt, nrhs, q.by);
+    q.by = block_rows(g, heavy, ctx);
+    q.rpt = level_rpt(g, q.by, ctx.block_cap);
+    q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by);
     q.block = dim3(kBX, q.by);
     q.nblk = int(q.grid.x * q.grid.y);
     return q;
@@ -78,11 +61,11 @@ constexpr size_t kMaxTileBytes = 64 * 1024;
 template <typename Op, typename T>
 __host__ __device__ size_t tile_bytes(int by, int rpt);
 template <typename Op, typename T>
-Geom geom_op(const Grid& g, int nrhs, int cap) {
-    Geom q = geom(g, Op::kHeavy, nrhs, cap);
+Geom geom_op(const Grid& g, const LaunchCtx& ctx) {
+    Geom q = geom(g, Op::kHeavy, ctx);
     if (tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) {
         while (q.rpt > 1 && tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) --q.rpt;
-        q.grid = level_grid(g, q.rpt, nrhs, q.by);
+        q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by);
         q.nblk = int(q.grid.x * q.grid.y);
     }
     return q;
@@ -298,7 +281,7 @@ __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, con
     });
 }
 
-template <typename Op, typename T, typename PGet, typename F>
+template <typename Op, typename T, bool kXcd = false, typename PGet, typename F>
 __device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Tile<op_radius<Op>::value>& tl,
                                                 cplx<T>* lds, PGet&& pget, F&& f);
 
@@ -320,10 +303,11 @@ __device__ __forceinline__ void for_nodes_applied_pre(const Op& op, int rpt, XLo
 
 // The second half of for_nodes_applied_pre: x of the block tile plus halo is
 // in LDS (after a barrier); runs f(i, j, p, pget(p), x at p, A x at p).
-template <typename Op, typename T, typename PGet, typename F>
+template <typename Op, typename T, bool kXcd, typename PGet, typename F>
 __device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Tile<op_radius<Op>::value>& tl,
                                                 cplx<T>* lds, PGet&& pget, F&& f) {
     if constexpr (is_product<Op>::value) {
+        static_assert(!kXcd, "the XCD tile map is used by level-0 passes only");
         product_stages(op, tl, lds, pget, f);
     } else if constexpr (std::is_same<Op, FineOp<T>>::value) {
         // tiles whose nodes all lie strictly inside the grid skip the boundary
@@ -335,7 +319,7 @@ __device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Til
         decltype(pget(0LL)) pv[NB];
         T kk[NB];
         auto rows = [&](auto inner) {
-            for_nodes_batched<NB>(
+            for_nodes_batched<NB, kXcd>(
                 op.g, rpt,
                 [&](int u, long long p) {
                     pv[u] = pget(p);
@@ -359,7 +343,7 @@ __device__ __forceinline__ void apply_from_tile(const Op& op, int rpt, const Til
         constexpr int NB = is_stencil<Op>::value ? (sizeof(T) == 4 ? 2 : 1) : (sizeof(T) == 4 ? 8 : 4);
         decltype(pget(0LL)) pv[NB];
         typename OpPre<Op>::type ov[NB];
-        for_nodes_batched<NB>(
+        for_nodes_batched<NB, kXcd>(
             op.g, rpt,
             [&](int u, long long p) {
                 pv[u] = pget(p);
@@ -396,7 +380,9 @@ __global__ __launch_bounds__(kBX * BY) void k_apply(Op op, Vec<T> x, Vec<T> y, c
     const cplx<T>* xb = x.rhs(b);
     cplx<T>* yb = y.rhs(b);
     for_nodes_applied<Op, T>(op, rpt, [xb](long long q) { return xb[q]; },
-                             [&](int, int, long long p, cplx<T>, cplx<T> ax) { yb[p] = ax; });
+                             [&](int, int, long long p, cplx<T>, cplx<T> ax) {
+                                 yb[p] = ax;
+                             });
 }
 
 template <typename Op, typename T, int BY>
@@ -409,7 +395,9 @@ __global__ __launch_bounds__(kBX * BY) void k_residual(Op op, Vec<T> x, Vec<T> f
     cplx<T>* rb = r.rhs(b);
     for_nodes_applied_pre<Op, T>(op, rpt, [xb](long long q) { return xb[q]; }, Ident{},
                                  [fb](long long q) { return fb[q]; },
-                                 [&](int, int, long long p, cplx<T> fp, cplx<T>, cplx<T> ax) { rb[p] = fp - ax; });
+                                 [&](int, int, long long p, cplx<T> fp, cplx<T>, cplx<T> ax) {
+                                     rb[p] = fp - ax;
+                                 });
 }
 
 // Weighted Jacobi of §3: y = x + (omega diag(A))^{-1} (f - A x).
@@ -693,34 +681,42 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
 }
 
 // Pass 2: beta = ||z0|| from pass 1; w0 = A z0 (unnormalised); partials <z0, w0>.
-template <typename Op, typename T, int BY>
+// The loads of pass 1's partial sums and of the first batch of the z0 tile
+// are in flight together; the reduction runs while the tile loads return.
+template <typename Op, typename T, int BY, bool kOv>
 __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout, GmState* st, const double* pin,
                                                     int nblk_in, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
-    // flag and partial sums are loaded together; the block leaves after the
-    // reduction if its right-hand side is inactive (uniform in the block)
     const bool act = rhs_active(active, b);
-    double t[1];
-    reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
-    if (!act) return;
-    const double beta = sqrt(t[0]);
-    const bool go = beta > 0.0;  // false for a zero or non-finite residual
-    if (lead_thread()) {
-        GmState& S = st[b];
-        S.beta = beta;
-        S.s[0] = go ? 1.0 / beta : 0.0;
-        S.k = go ? 3 : 0;
-        S.arnoldi_done = go ? 0 : 1;
-    }
-    if (!go) return;
     const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
     cplx<T>* wb = Wout.rhs(b);
+    // the block leaves after the reduction if its right-hand side is inactive
+    // or has a zero (or non-finite) residual (uniform in the block)
+    auto mid = [&](const double (&t)[1]) -> bool {
+        if (!act) return false;
+        const double beta = sqrt(t[0]);
+        const bool go = beta > 0.0;
+        if (lead_thread()) {
+            GmState& S = st[b];
+            S.beta = beta;
+            S.s[0] = go ? 1.0 / beta : 0.0;
+            S.k = go ? 3 : 0;
+            S.arnoldi_done = go ? 0 : 1;
+        }
+        return go;
+    };
+    constexpr int R = op_radius<Op>::value;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<R> tl = block_tile<R>(rpt);
+    if (!reduce_and_fill<1, kOv, T, R>(pin + b * kPartStride, nblk_in, lds, tl, op.g,
+                                        [z0](long long q) { return z0[q]; }, Ident{}, mid))
+        return;
     double acc[2] = {0.0, 0.0};
-    for_nodes_applied<Op, T>(op, rpt, [z0](long long q) { return z0[q]; },
-                             [&](int, int, long long p, cplx<T> zp, cplx<T> w) {
-                                 wb[p] = w;
-                                 acc_dot(acc[0], acc[1], zp, w);
-                             });
+    apply_from_tile<Op, T>(op, rpt, tl, lds, [](long long) { return NoVals{}; },
+                           [&](int, int, long long p, NoVals, cplx<T> zp, cplx<T> w) {
+                               wb[p] = w;
+                               acc_dot(acc[0], acc[1], zp, w);
+                           });
     block_partials<2>(acc, pout + b * kPartStride);
 }
 
@@ -730,68 +726,72 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
 // ||z_J||^2 and <z_i, w_J> for i <= J, and for J = 2 also ||w_2||^2 (the last
 // Arnoldi norm then follows without another pass over the vectors). w_1 goes
 // to Wout for pass 4; w_2 only where Wout.p is set (the update pass of the
-// last pre-smoothing step forms its residual from it).
-template <typename Op, typename T, int J, int BY>
+// last pre-smoothing step forms its residual from it). The raw tile values
+// (w_{J-1}, z_0 .. z_{J-1}) of the first batch are loaded together with the
+// previous pass's partial sums and combined once the reduction has given the
+// coefficients.
+template <typename Op, typename T, int J, int BY, bool kOv>
 __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
                                                     const int* active, int rpt) {
     const int b = blockIdx.z;
-    // flag, state and partial sums are loaded together; the block leaves
-    // after the reduction if there is nothing to do (uniform in the block)
     const bool act = rhs_active(active, b);
     const int done = st[b].arnoldi_done;
     const double s0 = st[b].s[0], beta0 = st[b].beta;
     constexpr int KIN = (J == 1) ? 2 : 5;  // previous pass: [||z_{J-1}||^2 (J > 1)], <z_i, w_{J-1}>
-    double t[KIN];
-    reduce_partials<KIN>(pin + b * kPartStride, nblk_in, t);
-    if (!act || done) return;
-    double sv[J];  // s_0 .. s_{J-1}
-    sv[0] = s0;
-    double hn = 0.0;
-    bool broke = false;
-    if (J > 1) {
-        hn = sqrt(t[0]);
-        broke = !(hn > breakdown * beta0);
-        sv[J - 1] = broke ? 0.0 : 1.0 / hn;
-    }
-    constexpr int D0 = (J > 1) ? 1 : 0;  // offset of the inner products in t
-    double hr[J], hi[J];
-#pragma unroll
-    for (int q = 0; q < J; ++q) {
-        hr[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q];
-        hi[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q + 1];
-    }
-    if (lead_thread()) {
-        GmState& S = st[b];
-        if (J > 1) {
-            S.hr[J - 1][J - 2] = hn;
-            S.hi[J - 1][J - 2] = 0.0;
-            if (broke) {
-                S.k = J - 1;
-                S.arnoldi_done = 1;
-            } else {
-                S.s[J - 1] = sv[J - 1];
-            }
-        }
-        if (!broke)
-#pragma unroll
-            for (int q = 0; q < J; ++q) {
-                S.hr[q][J - 1] = hr[q];
-                S.hi[q][J - 1] = hi[q];
-            }
-    }
-    if (broke) return;
-    // z_J = s_{J-1} w_{J-1} - sum_q c_q z_q with c_q = H[q][J-1] s_q
-    const T sJ1 = T(sv[J - 1]);
-    cplx<T> c[J];
-#pragma unroll
-    for (int q = 0; q < J; ++q) c[q] = {T(hr[q] * sv[q]), T(hi[q] * sv[q])};
     const cplx<T>* z[J];
 #pragma unroll
     for (int q = 0; q < J; ++q) z[q] = Z.p + (long long)(b * 4 + q) * Z.plane;
     cplx<T>* zJ = Z.p + (long long)(b * 4 + J) * Z.plane;
     const cplx<T>* wi = Win.rhs(b);
     cplx<T>* wo = Wout.p ? Wout.rhs(b) : nullptr;  // w_2 is stored only for a residual by recurrence
+    // z_J = s_{J-1} w_{J-1} - sum_q c_q z_q with c_q = H[q][J-1] s_q, set by mid()
+    T sJ1 = T(0);
+    cplx<T> c[J];
+    // the block leaves after the reduction if there is nothing to do (uniform in the block)
+    auto mid = [&](const double (&t)[KIN]) -> bool {
+        if (!act || done) return false;
+        double sv[J];  // s_0 .. s_{J-1}
+        sv[0] = s0;
+        double hn = 0.0;
+        bool broke = false;
+        if (J > 1) {
+            hn = sqrt(t[0]);
+            broke = !(hn > breakdown * beta0);
+            sv[J - 1] = broke ? 0.0 : 1.0 / hn;
+        }
+        constexpr int D0 = (J > 1) ? 1 : 0;  // offset of the inner products in t
+        double hr[J], hi[J];
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+            hr[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q];
+            hi[q] = sv[q] * sv[J - 1] * t[D0 + 2 * q + 1];
+        }
+        if (lead_thread()) {
+            GmState& S = st[b];
+            if (J > 1) {
+                S.hr[J - 1][J - 2] = hn;
+                S.hi[J - 1][J - 2] = 0.0;
+                if (broke) {
+                    S.k = J - 1;
+                    S.arnoldi_done = 1;
+                } else {
+                    S.s[J - 1] = sv[J - 1];
+                }
+            }
+            if (!broke)
+#pragma unroll
+                for (int q = 0; q < J; ++q) {
+                    S.hr[q][J - 1] = hr[q];
+                    S.hi[q][J - 1] = hi[q];
+                }
+        }
+        if (broke) return false;
+        sJ1 = T(sv[J - 1]);
+#pragma unroll
+        for (int q = 0; q < J; ++q) c[q] = {T(hr[q] * sv[q]), T(hi[q] * sv[q])};
+        return true;
+    };
     // z_J at a tile node from w_{J-1} (v[0]) and z_0 .. z_{J-1} (v[1..J])
     auto zload = [&](long long q) {
         Vals<T, J + 1> o;
@@ -810,6 +810,13 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
         }
         return v;
     };
+    constexpr int R = op_radius<Op>::value;
+    // level 0, second pass of a single right-hand side: tiles in contiguous
+    // runs per XCD (halo lines of its three tile arrays shared in one L2)
+    constexpr bool kX = kOv && J == 2 && std::is_same<Op, FineOp<T>>::value;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<R> tl = block_tile<R, kX>(rpt);
+    if (!reduce_and_fill<KIN, kOv, T, R>(pin + b * kPartStride, nblk_in, lds, tl, op.g, zload, zmake, mid)) return;
     constexpr int KOUT = 1 + 2 * (J + 1) + (J == 2 ? 1 : 0);
     double acc[KOUT];
 #pragma unroll
@@ -820,8 +827,8 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
         for (int a = 0; a < J; ++a) o.v[a] = z[a][q];
         return o;
     };
-    for_nodes_applied_pre<Op, T>(op, rpt, zload, zmake, zold, [&](int, int, long long p, const Vals<T, J>& zo, cplx<T> zp,
-                                                         cplx<T> w) {
+    apply_from_tile<Op, T, kX>(op, rpt, tl, lds, zold, [&](int, int, long long p, const Vals<T, J>& zo, cplx<T> zp,
+                                                          cplx<T> w) {
         zJ[p] = zp;
         if (J == 1 || wo) wo[p] = w;
         acc[0] += dnorm2(zp);
@@ -830,7 +837,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
         acc_dot(acc[1 + 2 * J], acc[2 + 2 * J], zp, w);
         if constexpr (J == 2) acc[KOUT - 1] += dnorm2(w);
     });
-    block_partials<KOUT>(acc, pout + b * kPartStride);
+    block_partials<KOUT, kX>(acc, pout + b * kPartStride);
 }
 
 // Pass 5 prologue: column 2 of H from pass 4's sums (unless the Arnoldi
@@ -992,10 +999,10 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_rr(Grid g, Vec<T> Z, Vec<T> u
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_prereduce(double* part, int nblk, const int* active) {
     const int b = blockIdx.x;
-    if (!rhs_active(active, b)) return;
+    const bool act = rhs_active(active, b);
     double t[K];
     reduce_partials<K>(part + b * kPartStride, nblk, t);  // ends with barriers after every read
-    if (thread_linear() == 0)
+    if (act && thread_linear() == 0)
 #pragma unroll
         for (int k = 0; k < K; ++k) part[b * kPartStride + k] = t[k];
 }
@@ -1033,10 +1040,10 @@ __global__ __launch_bounds__(kBX * BY) void k_norm(Grid g, Vec<T> f, double* pou
 __global__ __launch_bounds__(kThreads) void k_sum_norms(const double* pin, int nblk_in, RhsNorms* norms, int which,
                                                         const int* active, StopTest st) {
     const int b = blockIdx.x;
-    if (!rhs_active(active, b)) return;
+    const bool act = rhs_active(active, b);
     double t[1];
     reduce_partials<1>(pin + b * kPartStride, nblk_in, t);
-    if (thread_linear() == 0) {
+    if (act && thread_linear() == 0) {
         if (which == 0) {
             norms[b].f2 = t[0];
         } else {
@@ -1213,7 +1220,7 @@ template <typename T>
 void launch_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> y) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
+        const Geom q = geom_op<Op, T>(lop.g, ctx);
         HM_LAUNCH_OP(q, (k_apply<Op, T, BY>), op, x, y, HM_ACTIVE, q.rpt);
     });
 }
@@ -1222,7 +1229,7 @@ template <typename T>
 void launch_residual(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> r) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
+        const Geom q = geom_op<Op, T>(lop.g, ctx);
         HM_LAUNCH_OP(q, (k_residual<Op, T, BY>), op, x, f, r, HM_ACTIVE, q.rpt);
     });
 }
@@ -1231,7 +1238,7 @@ template <typename T>
 void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega) {
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
+        const Geom q = geom_op<Op, T>(lop.g, ctx);
         HM_LAUNCH_OP(q, (k_jacobi<Op, T, BY>), op, x, f, y, T(inv_omega), HM_ACTIVE, q.rpt);
     });
 }
@@ -1241,7 +1248,7 @@ double* region(const LaunchCtx& ctx, int r);
 template <typename T>
 int launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, Vec<T> r, Vec<T> fc, Vec<T> uc,
                     Vec<T> z0) {
-    const Geom q = geom(coarse, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(coarse, false, ctx);
     double* pout = z0.p ? region(ctx, 0) : nullptr;
     if (transfer == 0) HM_LAUNCH(q, (k_restrict<T, true, BY>), fine, coarse, r, fc, uc, z0, pout, HM_ACTIVE, q.rpt);
     else HM_LAUNCH(q, (k_restrict<T, false, BY>), fine, coarse, r, fc, uc, z0, pout, HM_ACTIVE, q.rpt);
@@ -1250,7 +1257,7 @@ int launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, 
 
 template <typename T>
 void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u) {
-    const Geom q = geom(fine, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(fine, false, ctx);
     const size_t shm = size_t(kProlongTW) * prolong_rows(q.by * q.rpt) * sizeof(cplx<T>);
     with_by(q.by, [&](auto byc) {
         constexpr int BY = decltype(byc)::value;
@@ -1265,18 +1272,22 @@ void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transf
 
 double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }
 
+// Level grids of at most this many blocks per right-hand side are resident
+// on the GPU at once when solved alone (256 compute units, several blocks each).
+constexpr int kOverlapMaxBlocks = 2048;
+
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
                        Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
-    const Geom qv = geom(lop.g, false, ctx.nrhs, ctx.block_cap);  // vector-only passes
+    const Geom qv = geom(lop.g, false, ctx);  // vector-only passes
     int nb_op = 0;
     Vec<T> uin{nullptr, 0};  // iterate the update pass starts from, when not u itself
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
+        const Geom q = geom_op<Op, T>(lop.g, ctx);
         nb_op = q.nblk;
         // consumers read the producer's partials directly, or one pre-reduced row
         const bool pre = q.nblk > ctx.block_cap;
@@ -1317,9 +1328,19 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             HM_LAUNCH_OP(q, (k_gm_r<Op, T, BY>), op, u, f, Z, A, HM_ACTIVE, q.rpt);
             prereduce(A, std::integral_constant<int, 1>{});
         }
-        HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
+        // handles of a single right-hand side overlap the reduction with the
+        // tile loads (see reduce_and_fill) and give the second orthogonalise
+        // pass of level 0 the XCD tile map; handles for batches keep the
+        // reduce-first order and the plain map, which measured faster once a
+        // launch queues several rounds of blocks. The choice follows the
+        // handle, not the call, so a batch member runs the same code as a solo
+        // solve on the same handle and matches it bit for bit.
+        const bool ov = ctx.nrhs_cap == 1 && q.nblk <= kOverlapMaxBlocks;
+        if (ov) HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, true>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
+        else HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, false>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
         prereduce(B, std::integral_constant<int, 2>{});
-        HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
+        if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
+        else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
         prereduce(A, std::integral_constant<int, 5>{});
         // w_2 is kept (in the fourth Arnoldi plane, w_0 stays in Wa) only for a
         // residual by recurrence
@@ -1327,12 +1348,20 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         if (timed) {
             with_by<Op::kHeavy>(q.by, [&](auto byc) {
                 constexpr int BY = decltype(byc)::value;
-                hipExtLaunchKernelGGL((k_gm_oa<Op, T, 2, BY>), q.grid, q.block, uint32_t(tile_bytes<Op, T>(q.by, q.rpt)),
-                                      ctx.stream, timed[0], timed[1], 0u, op, Z, Wb, w2, st, breakdown,
-                                      (const double*)A, nb, B, (const int*)HM_ACTIVE, q.rpt);
+                if (ov)
+                    hipExtLaunchKernelGGL((k_gm_oa<Op, T, 2, BY, true>), q.grid, q.block,
+                                          uint32_t(tile_bytes<Op, T>(q.by, q.rpt)), ctx.stream, timed[0], timed[1],
+                                          0u, op, Z, Wb, w2, st, breakdown, (const double*)A, nb, B,
+                                          (const int*)HM_ACTIVE, q.rpt);
+                else
+                    hipExtLaunchKernelGGL((k_gm_oa<Op, T, 2, BY, false>), q.grid, q.block,
+                                          uint32_t(tile_bytes<Op, T>(q.by, q.rpt)), ctx.stream, timed[0], timed[1],
+                                          0u, op, Z, Wb, w2, st, breakdown, (const double*)A, nb, B,
+                                          (const int*)HM_ACTIVE, q.rpt);
             });
         } else {
-            HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY>), op, Z, Wb, w2, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
+            if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY, true>), op, Z, Wb, w2, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
+            else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 2, BY, false>), op, Z, Wb, w2, st, breakdown, A, nb, B, HM_ACTIVE, q.rpt);
         }
         prereduce(B, std::integral_constant<int, 8>{});
         nb_op = nb;
@@ -1359,7 +1388,7 @@ void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T
     int nb = 0;
     with_op(lop, [&](auto op) {
         using Op = decltype(op);
-        const Geom q = geom_op<Op, T>(lop.g, ctx.nrhs, ctx.block_cap);
+        const Geom q = geom_op<Op, T>(lop.g, ctx);
         nb = q.nblk;
         HM_LAUNCH_OP(q, (k_resnorm<Op, T, BY>), op, x, f, region(ctx, 0), HM_ACTIVE, q.rpt);
     });
@@ -1368,7 +1397,7 @@ void launch_resnorm(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T
 
 template <typename T>
 void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
-    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(g, false, ctx);
     HM_LAUNCH(q, (k_norm<T, BY>), g, f, region(ctx, 0), HM_ACTIVE, q.rpt);
     launch_sum_norms(ctx, q.nblk, norms, 0);
 }
@@ -1379,7 +1408,7 @@ int launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec
                            Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(lop.g, false, ctx);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     const int rn = z0.p ? 1 : 0;
     HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, z0, region(ctx, rn), region(ctx, 0), HM_ACTIVE, q.rpt);
@@ -1391,7 +1420,7 @@ int launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Ve
                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(lop.g, false, ctx);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     const int rn = z0.p ? 1 : 0;
     HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, z0, region(ctx, rn), region(ctx, 0),
@@ -1403,7 +1432,7 @@ int launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Ve
 template <typename T>
 void launch_copy_in(const LaunchCtx& ctx, Grid g, const void* src, bool src_is_f32, Vec<T> dst, bool scale_w,
                     bool conj) {
-    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(g, false, ctx);
     if (src_is_f32)
         HM_LAUNCH(q, (k_copy_in<T, float, BY>), g, static_cast<const cplx<float>*>(src), dst, int(scale_w),
                   int(conj), q.rpt);
@@ -1414,7 +1443,7 @@ void launch_copy_in(const LaunchCtx& ctx, Grid g, const void* src, bool src_is_f
 
 template <typename T>
 void launch_copy_out(const LaunchCtx& ctx, Grid g, Vec<T> src, void* dst, bool dst_is_f32, bool scale_w, bool conj) {
-    const Geom q = geom(g, false, ctx.nrhs, ctx.block_cap);
+    const Geom q = geom(g, false, ctx);
     if (dst_is_f32)
         HM_LAUNCH(q, (k_copy_out<T, float, BY>), g, src, static_cast<cplx<float>*>(dst), int(scale_w), int(conj),
                   q.rpt);

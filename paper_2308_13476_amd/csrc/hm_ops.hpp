@@ -114,7 +114,25 @@ struct ProductOp {
 struct BlockXY {
     int x, y;
 };
-__device__ __forceinline__ BlockXY block_xy() { return BlockXY{int(blockIdx.x), int(blockIdx.y)}; }
+// kXcd: the tiles of a grid are dealt out in contiguous runs, one run per
+// XCD. Workgroups are dispatched to the eight XCDs round-robin by linear id,
+// so the ids of one residue class mod 8 share an XCD (and its L2); giving
+// each class a contiguous run of tiles lets horizontally and vertically
+// adjacent tiles share their halo lines in one L2 instead of fetching them
+// twice. A bijection on the tiles of any grid; used by the pass whose tile
+// reads three arrays with a halo (elsewhere the integer division it costs at
+// the start of every block outweighed the saving).
+template <bool kXcd = false>
+__device__ __forceinline__ BlockXY block_xy() {
+    if constexpr (kXcd) {
+        const int gx = gridDim.x, T = gx * gridDim.y;
+        const int t = blockIdx.y * gx + blockIdx.x;
+        const int r = t & 7, k = t >> 3, q = T >> 3, rem = T & 7;
+        const int tile = r * q + min(r, rem) + k;
+        return BlockXY{tile % gx, tile / gx};
+    }
+    return BlockXY{int(blockIdx.x), int(blockIdx.y)};
+}
 
 // Calls f(i, j, p) for the nodes of this thread: column bx * 64 + lane,
 // rows interleaved by 4 over rows_per_thread consecutive row groups of row
@@ -144,9 +162,9 @@ __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70)
 // per batch instead of one per row. Only the row count decides which loads
 // are issued (uniform in the block, so no divergent branch separates them);
 // a row below the grid loads its column's last node instead.
-template <int NB, typename Load, typename Body>
+template <int NB, bool kXcd = false, typename Load, typename Body>
 __device__ __forceinline__ void for_nodes_batched(const Grid& g, int rpt, Load&& load, Body&& body) {
-    const BlockXY bt = block_xy();
+    const BlockXY bt = block_xy<kXcd>();
     const int i = bt.x * kBX + threadIdx.x;
     if (i > g.n) return;
     const int by = blockDim.y;
@@ -199,9 +217,9 @@ struct Tile {
     __device__ __forceinline__ int count() const { return TW * (rows + 2 * R); }
 };
 
-template <int R>
+template <int R, bool kXcd = false>
 __device__ __forceinline__ Tile<R> block_tile(int rpt) {
-    const BlockXY bt = block_xy();
+    const BlockXY bt = block_xy<kXcd>();
     return Tile<R>{bt.x * kBX, bt.y * int(blockDim.y) * rpt, int(blockDim.y) * rpt};
 }
 
@@ -236,6 +254,51 @@ __device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const 
         },
         [&](int u, int q) { lds[q] = ok[u] ? make(v[u]) : cplx<T>{T(0), T(0)}; });
     __syncthreads();
+}
+
+// fill_tile with work in the middle: the loads of the first stride batch are
+// issued (unconditionally, indices clamped to the tile), then mid() runs
+// while they are in flight, then the batch is combined; mid() returning false
+// (uniformly in the block) ends the fill before anything is written, and the
+// function returns false. make may use what mid() computes.
+template <typename T, int R, typename Load, typename Make, typename Mid>
+__device__ __forceinline__ bool fill_tile_mid(cplx<T>* lds, const Tile<R>& t, const Grid& g, Load&& load,
+                                              Make&& make, Mid&& mid) {
+    static_assert(R <= kGhost, "tile halo beyond the stored ghost layers");
+    constexpr int FB = FillBatch<T>::value;
+    decltype(load(0LL)) v[FB];
+    bool ok[FB];
+    const int count = t.count();
+    auto ld = [&](int u, int q) {
+        const int i = t.c0 - R + q % Tile<R>::TW;
+        const int j = t.r0 - R + q / Tile<R>::TW;
+        const int ic = min(max(i, -R), g.n + R), jc = min(max(j, -R), g.n + R);
+        ok[u] = i == ic && j == jc;
+        v[u] = load(g.at(ic, jc));
+    };
+    const int nt = blockDim.x * blockDim.y;
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < FB; ++u) ld(u, min(tid + u * nt, count - 1));
+    if (!mid()) return false;
+    wait_vmem();
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+        const int q = tid + u * nt;
+        if (q < count) lds[q] = ok[u] ? make(v[u]) : cplx<T>{T(0), T(0)};
+    }
+    for (int s0 = FB * nt; s0 < count; s0 += FB * nt) {  // uniform: first index of the round
+        const int q0 = s0 + tid;
+#pragma unroll
+        for (int u = 0; u < FB; ++u)
+            if (s0 + u * nt < count) ld(u, min(q0 + u * nt, count - 1));
+        wait_vmem();
+#pragma unroll
+        for (int u = 0; u < FB; ++u)
+            if (q0 + u * nt < count) lds[q0 + u * nt] = ok[u] ? make(v[u]) : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    return true;
 }
 
 // Stencil of radius R applied at node p whose tile index is li, values from LDS.
@@ -344,8 +407,9 @@ __device__ __forceinline__ bool rhs_active(const int* active, int b) { return ac
 // partials + (r * nrhs_cap + b) * kPartStride.
 
 // Row-major index of this block's tile, the slot of its partial sums.
+template <bool kXcd = false>
 __device__ __forceinline__ int block_linear() {
-    const BlockXY bt = block_xy();
+    const BlockXY bt = block_xy<kXcd>();
     return bt.y * int(gridDim.x) + bt.x;
 }
 __device__ __forceinline__ int thread_linear() { return threadIdx.y * kBX + threadIdx.x; }
@@ -402,13 +466,13 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (&tot)[K]) {
 }
 
 // Writes this block's K sums to out[block * K + k].
-template <int K>
+template <int K, bool kXcd = false>
 __device__ __forceinline__ void block_partials(double (&v)[K], double* out) {
     double tot[K];
     block_sum<K>(v, tot);
     if (thread_linear() == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) out[block_linear() * K + k] = tot[k];
+        for (int k = 0; k < K; ++k) out[block_linear<kXcd>() * K + k] = tot[k];
     }
 }
 
@@ -436,6 +500,89 @@ __device__ __forceinline__ void reduce_partials(const double* in, int nblk, doub
             for (int k = 0; k < K; ++k) acc[k] += v[u][k];
     }
     block_sum<K>(acc, tot);
+}
+
+// reduce_partials in two steps, so that the reduction's loads and the
+// caller's next loads are in flight together (one memory round trip instead
+// of two on the critical path of a reduction-consuming pass):
+// partials_issue loads the first kReduceBatch strides, every index clamped to
+// the last partial so that the loads are issued unconditionally and can be
+// waited for alone (vector loads complete in order); partials_finish adds
+// them, and any further strides, in the order of reduce_partials (the same
+// totals) and block-sums.
+template <int K>
+struct PartialBatch {
+    double v[kReduceBatch][K];
+};
+
+template <int K>
+__device__ __forceinline__ void partials_issue(const double* in, int nblk, PartialBatch<K>& pb) {
+    const int nt = blockDim.x * blockDim.y;
+    const int last = nblk > 0 ? nblk - 1 : 0;
+#pragma unroll
+    for (int u = 0; u < kReduceBatch; ++u) {
+        const int q = min(thread_linear() + u * nt, last);
+#pragma unroll
+        for (int k = 0; k < K; ++k) pb.v[u][k] = in[q * K + k];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void partials_finish(const double* in, int nblk, const PartialBatch<K>& pb,
+                                                double (&tot)[K]) {
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    const int nt = blockDim.x * blockDim.y;
+    const int q0 = thread_linear();
+#pragma unroll
+    for (int u = 0; u < kReduceBatch; ++u) {
+        const bool in_range = q0 + u * nt < nblk;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += in_range ? pb.v[u][k] : 0.0;
+    }
+    for (int q1 = q0 + kReduceBatch * nt; q1 < nblk; q1 += kReduceBatch * nt) {
+        double v[kReduceBatch][K];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) {
+            const int q = q1 + u * nt;
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[u][k] = (q < nblk) ? in[q * K + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u)
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += v[u][k];
+    }
+    block_sum<K>(acc, tot);
+}
+
+// The reduction of the previous pass's K partial sums and the tile fill of a
+// reduction-consuming pass, in one of two orders. kOverlap: both sets of
+// loads in flight together (the reduction runs while the tile arrives; more
+// registers, for launches whose blocks all fit on the GPU at once);
+// otherwise the reduction first (fewer registers, hence more resident blocks
+// for launches that queue several rounds of blocks). after(totals) returns
+// false to end the block (uniformly) before anything is written; make may
+// use what it computes.
+template <int K, bool kOverlap, typename T, int R, typename Load, typename Make, typename After>
+__device__ __forceinline__ bool reduce_and_fill(const double* pin, int nblk, cplx<T>* lds, const Tile<R>& t,
+                                                const Grid& g, Load&& load, Make&& make, After&& after) {
+    if constexpr (kOverlap) {
+        PartialBatch<K> pb;
+        partials_issue<K>(pin, nblk, pb);
+        return fill_tile_mid<T, R>(lds, t, g, load, make, [&]() -> bool {
+            double tot[K];
+            partials_finish<K>(pin, nblk, pb, tot);
+            return after(tot);
+        });
+    } else {
+        double tot[K];
+        reduce_partials<K>(pin, nblk, tot);
+        if (!after(tot)) return false;
+        fill_tile<T, R>(lds, t, g, load, make);
+        return true;
+    }
 }
 
 // Least-squares min || beta e1 - H y || over the k Arnoldi columns by complex

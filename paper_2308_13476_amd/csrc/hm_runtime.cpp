@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -160,6 +161,12 @@ struct mg_ctx {
     // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
     // beyond it reductions are pre-reduced in a one-block pass
     int block_cap = 640;
+    // block heights: light kernels on grids of >= 256 intervals (4, 8, 16;
+    // HELMG_TALL_BLOCKS) and every kernel on grids of <= 128 intervals (2 or 4;
+    // HELMG_SMALL_ROWS)
+    int tall_rows = 4, small_rows = 2;
+    // JSON file of autotuned launch settings (mg_setup_opts.tune_cache), or empty
+    std::string tune_cache;
     // the coarse grid correction folded into the first post-smoothing pass
     // where its LDS stage fits (HELMG_FUSE_CORRECTION=0: always a pass of its own)
     int fuse_correction = 1;
@@ -313,7 +320,10 @@ template <typename T>
 Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
-    return LaunchCtx{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap, c->fuse_correction};
+    LaunchCtx lc{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap, c->fuse_correction};
+    lc.tall_rows = c->tall_rows;
+    lc.small_rows = c->small_rows;
+    return lc;
 }
 
 // Timing hook: events around the launches of one kernel class.
@@ -1063,6 +1073,13 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     c->ws = static_cast<char*>(workspace);
     c->ws_bytes = need;
     if (const char* e = std::getenv("HELMG_GRAPH")) c->use_graph = std::atoi(e) != 0;
+    if (opts && opts->use_graph < 0) c->use_graph = false;
+    if (opts && opts->tune_cache) c->tune_cache = opts->tune_cache;
+    if (const char* e = std::getenv("HELMG_TALL_BLOCKS")) {
+        const int v = std::atoi(e);
+        c->tall_rows = (v == 8 || v == 16) ? v : 4;
+    }
+    if (const char* e = std::getenv("HELMG_SMALL_ROWS")) c->small_rows = std::atoi(e) == 4 ? 4 : 2;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
@@ -1640,6 +1657,112 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
     return res;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Launch settings the autotuner chooses among.
+struct TuneSettings {
+    int block_cap, tail_n, product, tall_rows, small_rows;
+    double ms;
+};
+
+void apply_settings(mg_ctx* c, const TuneSettings& t) {
+    c->block_cap = t.block_cap;
+    c->tail_n = t.tail_n;
+    pick_tail_levels(c, t.tail_n);
+    c->product_l1 = t.product;
+    c->tall_rows = t.tall_rows;
+    c->small_rows = t.small_rows;
+    clear_graphs(c);
+}
+
+// Key of a tuned configuration: the problem shape, the cycle and the device.
+std::string tune_key(const mg_ctx* c, int nrhs, int cyc, int smoother, const mg_solve_opts& o) {
+    std::string arch = "unknown";
+    hipDeviceProp_t prop;
+    if (c->device >= 0 && hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "n=%d levels=%d transfer=%d nrhs=%d cycle=%d smoother=%d nu=%d,%d fp32=%d arch=%s",
+                  c->n, c->L, c->transfer, nrhs, cyc, smoother, o.nu_pre, o.nu_post,
+                  o.precision == MG_FP32_REFINED ? 1 : 0, arch.c_str());
+    return buf;
+}
+
+// The cache file holds {"entries": [ {"key": "...", "block_cap": ..., "tail_n": ...,
+// "level1_product": ..., "tall_rows": ..., "small_rows": ..., "ms_per_cycle": ...}, ... ]};
+// the reader below accepts exactly what tune_cache_write produces (one entry
+// per line).
+struct CacheEntry {
+    std::string key;
+    TuneSettings t;
+};
+
+bool json_number(const std::string& line, const char* field, double* out) {
+    const std::string tag = std::string("\"") + field + "\":";
+    const size_t p = line.find(tag);
+    if (p == std::string::npos) return false;
+    char* end = nullptr;
+    const double v = std::strtod(line.c_str() + p + tag.size(), &end);
+    if (end == line.c_str() + p + tag.size()) return false;
+    *out = v;
+    return true;
+}
+
+std::vector<CacheEntry> tune_cache_read(const std::string& path) {
+    std::vector<CacheEntry> out;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, k);
+    std::fclose(f);
+    size_t pos = 0;
+    while (pos < text.size()) {
+        size_t eol = text.find('\n', pos);
+        if (eol == std::string::npos) eol = text.size();
+        const std::string line = text.substr(pos, eol - pos);
+        pos = eol + 1;
+        const size_t kp = line.find("\"key\": \"");
+        if (kp == std::string::npos) continue;
+        const size_t ks = kp + 8, ke = line.find('"', ks);
+        if (ke == std::string::npos) continue;
+        CacheEntry e;
+        e.key = line.substr(ks, ke - ks);
+        double v[6];
+        if (!json_number(line, "block_cap", &v[0]) || !json_number(line, "tail_n", &v[1]) ||
+            !json_number(line, "level1_product", &v[2]) || !json_number(line, "tall_rows", &v[3]) ||
+            !json_number(line, "small_rows", &v[4]) || !json_number(line, "ms_per_cycle", &v[5]))
+            continue;
+        e.t = TuneSettings{int(v[0]), int(v[1]), int(v[2]), int(v[3]), int(v[4]), v[5]};
+        out.push_back(e);
+    }
+    return out;
+}
+
+bool tune_cache_write(const std::string& path, const std::vector<CacheEntry>& entries) {
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"entries\": [\n");
+    for (size_t i = 0; i < entries.size(); ++i) {
+        const TuneSettings& t = entries[i].t;
+        std::fprintf(f,
+                     "  {\"key\": \"%s\", \"block_cap\": %d, \"tail_n\": %d, \"level1_product\": %d, "
+                     "\"tall_rows\": %d, \"small_rows\": %d, \"ms_per_cycle\": %.6f}%s\n",
+                     entries[i].key.c_str(), t.block_cap, t.tail_n, t.product, t.tall_rows, t.small_rows, t.ms,
+                     i + 1 < entries.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
 mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother, const mg_solve_opts* opts,
                   mg_tune_result* out, void* stream) {
     if (!c) return MG_E_ARG;
@@ -1647,6 +1770,20 @@ mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother,
     if (mg_status st = check_solve_args(c, nrhs, 1.0, cyc, smoother, o)) return st;
     if (!is_dev_ptr_ok(rhs)) { c->err = "rhs NULL or misaligned"; return MG_E_ARG; }
     if (c->timing_class != 0) { c->err = "mg_tune needs the timing hook off"; return MG_E_STATE; }
+    const std::string key = tune_key(c, nrhs, cyc, smoother, o);
+    std::vector<CacheEntry> cache;
+    if (!c->tune_cache.empty()) {
+        cache = tune_cache_read(c->tune_cache);
+        for (const CacheEntry& e : cache)
+            if (e.key == key) {
+                apply_settings(c, e.t);
+                if (out) {
+                    *out = mg_tune_result{e.t.block_cap, e.t.tail_n, e.t.product, e.t.ms, 0, e.t.tall_rows,
+                                          e.t.small_rows, 1};
+                }
+                return MG_OK;
+            }
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     LevelBuf& l0 = c->lv[0];
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1663,61 +1800,64 @@ mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother,
             (void)hipEventDestroy(b);
         }
     } guard{e0, e1};
+    // launch settings: block cap, tail size, level-1 operator, and the tile
+    // shape (block heights on large and on small grids); the heights only
+    // matter where such grids exist
     const int caps[] = {320, 640, 1280};
     const int tails[] = {0, 16, 32};
     const int prods[] = {0, 1};
-    const int keep_cap = c->block_cap, keep_tail = c->tail_n, keep_prod = c->product_l1;
-    double best = 1e300;
-    int best_cap = keep_cap, best_tail = keep_tail, best_prod = keep_prod, tried = 0;
+    const bool has_tall = c->n >= 256, has_small = (c->n >> 1) <= 128 || c->L > 2;
+    std::vector<int> talls = has_tall ? std::vector<int>{4, 8} : std::vector<int>{c->tall_rows};
+    std::vector<int> smalls = has_small ? std::vector<int>{2, 4} : std::vector<int>{c->small_rows};
+    TuneSettings best{c->block_cap, c->tail_n, c->product_l1, c->tall_rows, c->small_rows, 1e300};
+    int tried = 0;
     constexpr int kTimed = 3;
     for (int cap : caps)
         for (int tail : tails)
-            for (int prod : prods) {
-                c->block_cap = cap;
-                c->tail_n = tail;
-                pick_tail_levels(c, tail);
-                c->product_l1 = prod;
-                clear_graphs(c);
-                LaunchCtx lc = launch_ctx(c, s, nrhs);
-                lc.active = nullptr;
-                launch_copy_in<double>(lc, l0.g, rhs, false, vec<double>(l0.f64, l0), true, false);
-                launch_zero<double>(s, l0.u64, l0.g.plane * nrhs);
-                if (mg_status st = check_launch(c)) return st;
-                SolveRun run(c, nrhs, 1e-300, cyc, smoother, o);
-                if (mg_status st = run.start(s)) return st;
-                HM_HIP(hipStreamSynchronize(s));
-                if (mg_status st = run.begin(s)) return st;
-                auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
-                if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;  // warm-up and capture
-                HM_HIP(hipEventRecord(e0, s));
-                for (int k = 0; k < kTimed; ++k)
-                    if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
-                HM_HIP(hipEventRecord(e1, s));
-                HM_HIP(hipEventSynchronize(e1));
-                float ms = 0.0f;
-                HM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                ++tried;
-                const double per = double(ms) / kTimed;
-                if (per < best) {
-                    best = per;
-                    best_cap = cap;
-                    best_tail = tail;
-                    best_prod = prod;
-                }
-            }
-    c->block_cap = best_cap;
-    c->tail_n = best_tail;
-    pick_tail_levels(c, best_tail);
-    c->product_l1 = best_prod;
-    clear_graphs(c);
+            for (int prod : prods)
+                for (int tr : talls)
+                    for (int sr : smalls) {
+                        const TuneSettings cand{cap, tail, prod, tr, sr, 0.0};
+                        apply_settings(c, cand);
+                        LaunchCtx lc = launch_ctx(c, s, nrhs);
+                        lc.active = nullptr;
+                        launch_copy_in<double>(lc, l0.g, rhs, false, vec<double>(l0.f64, l0), true, false);
+                        launch_zero<double>(s, l0.u64, l0.g.plane * nrhs);
+                        if (mg_status st = check_launch(c)) return st;
+                        SolveRun run(c, nrhs, 1e-300, cyc, smoother, o);
+                        if (mg_status st = run.start(s)) return st;
+                        HM_HIP(hipStreamSynchronize(s));
+                        if (mg_status st = run.begin(s)) return st;
+                        auto body = [&](hipStream_t st) { run.enqueue_cycle(st); };
+                        if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;  // warm-up and capture
+                        HM_HIP(hipEventRecord(e0, s));
+                        for (int k = 0; k < kTimed; ++k)
+                            if (mg_status st = run_cycle_graph(c, s, run.key, body)) return st;
+                        HM_HIP(hipEventRecord(e1, s));
+                        HM_HIP(hipEventSynchronize(e1));
+                        float ms = 0.0f;
+                        HM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        ++tried;
+                        const double per = double(ms) / kTimed;
+                        if (per < best.ms) {
+                            best = cand;
+                            best.ms = per;
+                        }
+                    }
+    apply_settings(c, best);
     HM_HIP(hipStreamSynchronize(s));
-    if (out) {
-        out->block_cap = best_cap;
-        out->tail_n = best_tail;
-        out->level1_product = best_prod;
-        out->ms_per_cycle = best;
-        out->candidates = tried;
+    if (!c->tune_cache.empty()) {
+        std::vector<CacheEntry> kept;
+        for (const CacheEntry& e : cache)
+            if (e.key != key) kept.push_back(e);
+        kept.push_back(CacheEntry{key, best});
+        if (!tune_cache_write(c->tune_cache, kept)) {
+            c->err = "mg_tune: could not write the tuning cache " + c->tune_cache;
+            return MG_E_ARG;
+        }
     }
+    if (out) *out = mg_tune_result{best.block_cap, best.tail_n, best.product, best.ms, tried, best.tall_rows,
+                                   best.small_rows, 0};
     return MG_OK;
 }
 

@@ -57,7 +57,8 @@ class Solver:
     """
 
     def __init__(self, k2: torch.Tensor, h: float, shift: float, levels: int = 0, transfer: str = "bezier",
-                 precision: str = "fp64", max_batch: int = 1, coarsest_n: int = 4):
+                 precision: str = "fp64", max_batch: int = 1, coarsest_n: int = 4, use_graph: bool = True,
+                 tune_cache: str | None = None):
         lib = B.lib()
         if k2.dim() != 2 or k2.shape[0] != k2.shape[1]:
             raise ValueError("k2 must be a square (n+1, n+1) tensor")
@@ -68,7 +69,9 @@ class Solver:
         self.max_batch = int(max_batch)
         self.setup_precision = precision
         self.handle = ctypes.c_void_p()
-        self._opts = B.SetupOpts(_PREC[precision], self.max_batch, int(coarsest_n))
+        self._tune_cache = tune_cache.encode() if tune_cache else None  # kept alive for the C side
+        self._opts = B.SetupOpts(_PREC[precision], self.max_batch, int(coarsest_n), 1 if use_graph else -1,
+                                 self._tune_cache)
         nbytes = lib.mg_workspace_bytes(self.n, int(levels), _TRANSFER[transfer], ctypes.byref(self._opts))
         if nbytes == 0:
             raise ValueError("invalid grid / level configuration")
@@ -174,7 +177,8 @@ class Solver:
         _check(B.lib().mg_tune(self.handle, _ptr(f), f.shape[0], _CYCLE[cycle], _SMOOTHER[smoother],
                                ctypes.byref(opts), ctypes.byref(res), _stream()), self.handle)
         return {"block_cap": res.block_cap, "tail_n": res.tail_n, "level1_product": res.level1_product,
-                "ms_per_cycle": res.ms_per_cycle, "candidates": res.candidates}
+                "ms_per_cycle": res.ms_per_cycle, "candidates": res.candidates, "tall_rows": res.tall_rows,
+                "small_rows": res.small_rows, "from_cache": bool(res.from_cache)}
 
     @staticmethod
     def solve_multi(solvers, rhs_list, x0_list=None, tol: float = 1e-6, cycle="V", smoother="gmres", nu_pre=1,

@@ -39,12 +39,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_workspace_size_and_argument_checks_without_gpu():
     L, B = _lib()
-    opts = B.SetupOpts(B.MG_FP64, 1, 4)
+    opts = B.SetupOpts(B.MG_FP64, 1, 4, 0, None)
     assert L.mg_workspace_bytes(64, 0, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) > 0
     assert L.mg_workspace_bytes(63, 0, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # not halvable to 4
     assert L.mg_workspace_bytes(64, 9, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # too many levels
     assert L.mg_workspace_bytes(4096, 3, B.MG_TRANSFER_BEZIER, ctypes.byref(opts)) == 0  # coarsest too large
-    big = B.SetupOpts(B.MG_FP32_REFINED, 4, 4)
+    big = B.SetupOpts(B.MG_FP32_REFINED, 4, 4, 0, None)
     assert L.mg_workspace_bytes(64, 0, 0, ctypes.byref(big)) > L.mg_workspace_bytes(64, 0, 0, ctypes.byref(opts))
     h = ctypes.c_void_p()
     fake = ctypes.c_void_p(1 << 20)  # never dereferenced: the checks fail first

@@ -97,20 +97,33 @@ def test_config4_64_sources_one_launch_per_kernel():
         assert _relres(k2, f[b], to_np(x)[b]) <= 1e-6
 
 
-def test_autotuner_choice_keeps_oracle_results():
-    """mg_tune times all 18 launch settings on the caller's problem and keeps the
-    fastest; a solve afterwards still matches the oracle (cycle count within
-    one, iterate within 1e-10 after the same number of cycles)."""
+def test_autotuner_choice_keeps_oracle_results(tmp_path):
+    """mg_tune times all 36 launch settings of a 128-interval grid (block cap,
+    tail size, level-1 operator, block height of the small grids) on the
+    caller's problem and keeps the fastest; a solve afterwards still matches
+    the oracle (cycle count within one, iterate within 1e-10 after the same
+    number of cycles). The choice goes to the tuning cache, from which a new
+    handle of the same problem takes it without timing."""
     require_gpu()
     from paper_2308_13476_amd.solver import Solver
     n, k = 128, 30.0
     k2 = W.random_k2(n, 6, 20.0, 30.0)
     f = W.point_source_rhs(n, [W.center_node(n)])
-    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k)
+    cache = str(tmp_path / "tune.json")
+    S = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, tune_cache=cache)
     choice = S.tune(to_gpu(f))
-    assert choice["candidates"] == 18
+    assert choice["candidates"] == 36 and not choice["from_cache"]
     assert choice["block_cap"] in (320, 640, 1280) and choice["tail_n"] in (0, 16, 32)
     assert choice["level1_product"] in (0, 1) and choice["ms_per_cycle"] > 0
+    assert choice["small_rows"] in (2, 4)
+    again = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, tune_cache=cache).tune(to_gpu(f))
+    assert again["from_cache"] and again["candidates"] == 0
+    for key in ("block_cap", "tail_n", "level1_product", "tall_rows", "small_rows"):
+        assert again[key] == choice[key], key
+    other = Solver(to_gpu(k2), 1.0 / n, 1.0 / k, tune_cache=cache).tune(to_gpu(f), cycle="W")
+    assert not other["from_cache"]  # another cycle is another entry
+    import json
+    assert len(json.load(open(cache))["entries"]) == 2
     x, info = S.solve(to_gpu(f), tol=1e-6)
     assert info["status"] == 0
     H = O.build_hierarchy(k2, 1.0 / n, 1.0 / k)
