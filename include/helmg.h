@@ -176,7 +176,8 @@ typedef struct {
 /* Autotuner (a launch-setting search; the method is unchanged): times three
  * captured cycles of the given problem (rhs [dev] complex128 [nrhs][n+1][n+1]
  * as in mg_solve, zero initial guess) for each combination of block cap
- * {320, 640, 1280}, tail size {0, 16, 32}, level-1 operator {stored,
+ * ({320, 640, 1280} blocks per right-hand side on handles with max_batch 1,
+ * {64, 160, 320, 640} on batch handles), tail size {0, 16, 32}, level-1 operator {stored,
  * product} and tile shape (block heights {4, 8} on grids of >= 256 intervals
  * and {2, 4} on grids of <= 128), keeps the fastest on the handle for later
  * solves and reports it in *out (may be NULL). With a tune_cache file (see

@@ -1257,8 +1257,16 @@ int launch_restrict(const LaunchCtx& ctx, Grid fine, Grid coarse, int transfer, 
 
 template <typename T>
 void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u) {
-    const Geom q = geom(fine, false, ctx);
-    const size_t shm = size_t(kProlongTW) * prolong_rows(q.by * q.rpt) * sizeof(cplx<T>);
+    Geom q = geom(fine, false, ctx);
+    // the coarse tile is dynamic shared memory: rows per thread lowered until
+    // it fits the same bound as the operator tiles
+    auto bytes = [&](int rpt) { return size_t(kProlongTW) * prolong_rows(q.by * rpt) * sizeof(cplx<T>); };
+    if (bytes(q.rpt) > kMaxTileBytes) {
+        while (q.rpt > 1 && bytes(q.rpt) > kMaxTileBytes) --q.rpt;
+        q.grid = level_grid(fine, q.rpt, ctx.nrhs, q.by);
+        q.nblk = int(q.grid.x * q.grid.y);
+    }
+    const size_t shm = bytes(q.rpt);
     with_by(q.by, [&](auto byc) {
         constexpr int BY = decltype(byc)::value;
         if (transfer == 0)
@@ -1271,6 +1279,10 @@ void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transf
 }
 
 double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }
+
+// On batch handles, partial sums of producers with more blocks than this per
+// right-hand side are pre-reduced before their consumers.
+constexpr int kBatchPrereduceBlocks = 32;
 
 // Level grids of at most this many blocks per right-hand side are resident
 // on the GPU at once when solved alone (256 compute units, several blocks each).
@@ -1290,7 +1302,12 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         const Geom q = geom_op<Op, T>(lop.g, ctx);
         nb_op = q.nblk;
         // consumers read the producer's partials directly, or one pre-reduced row
-        const bool pre = q.nblk > ctx.block_cap;
+        // (and on handles for batches: every block of a consumer reads all of
+        // its right-hand side's partial sums, which for B right-hand sides of
+        // nblk blocks each is B nblk^2 values per pass; one block per
+        // right-hand side pre-reduces them instead. Solo solves on such a
+        // handle take the same path and keep matching batch members bit for bit.)
+        const bool pre = q.nblk > ctx.block_cap || (ctx.nrhs_cap > 1 && q.nblk > kBatchPrereduceBlocks);
         const int nb = pre ? 1 : q.nblk;
         auto prereduce = [&](double* part, auto kc) {
             if (pre)
@@ -1319,7 +1336,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         } else if (r_ready_nblk > 0) {
             // u = 0: z_0 = f and its partial norms were written by the restriction
             nb_r = r_ready_nblk;
-            if (r_ready_nblk > ctx.block_cap) {
+            if (r_ready_nblk > ctx.block_cap || (ctx.nrhs_cap > 1 && r_ready_nblk > kBatchPrereduceBlocks)) {
                 hipLaunchKernelGGL((k_prereduce<1>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, A, r_ready_nblk,
                                    HM_ACTIVE);
                 nb_r = 1;
@@ -1408,7 +1425,7 @@ int launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec
                            Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx);
+    const Geom q = geom_op<Op, T>(lop.g, ctx);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     const int rn = z0.p ? 1 : 0;
     HM_LAUNCH_OP(q, (k_refine_residual<BY>), op, x, f, r32, z0, region(ctx, rn), region(ctx, 0), HM_ACTIVE, q.rpt);
@@ -1420,7 +1437,7 @@ int launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Ve
                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
     using Op = FineOp<double>;
     using T = double;
-    const Geom q = geom(lop.g, false, ctx);
+    const Geom q = geom_op<Op, T>(lop.g, ctx);
     FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     const int rn = z0.p ? 1 : 0;
     HM_LAUNCH_OP(q, (k_correct_residual<BY>), op, x_in, e, x_out, f, r32, z0, region(ctx, rn), region(ctx, 0),

@@ -1082,6 +1082,10 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (const char* e = std::getenv("HELMG_SMALL_ROWS")) c->small_rows = std::atoi(e) == 4 ? 4 : 2;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
+    // batch handles: fewer, larger tiles per right-hand side (the launch has
+    // max_batch times as many blocks; larger tiles amortise each block's
+    // fixed costs: reduction, tile halo, block sums)
+    if (max_batch > 1) c->block_cap = std::max(64, 640 / max_batch);
     if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
         const int v = std::atoi(e);
         c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
@@ -1803,7 +1807,8 @@ mg_status mg_tune(mg_handle c, const void* rhs, int nrhs, int cyc, int smoother,
     // launch settings: block cap, tail size, level-1 operator, and the tile
     // shape (block heights on large and on small grids); the heights only
     // matter where such grids exist
-    const int caps[] = {320, 640, 1280};
+    std::vector<int> caps = {320, 640, 1280};
+    if (c->max_batch > 1) caps = {64, 160, 320, 640};
     const int tails[] = {0, 16, 32};
     const int prods[] = {0, 1};
     const bool has_tall = c->n >= 256, has_small = (c->n >> 1) <= 128 || c->L > 2;

@@ -241,3 +241,28 @@ def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
         ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
         assert rel(got[b], ref) <= 1e-10, (b, rel(got[b], ref))
         assert rel(got32[b], ref) <= 1e-4, (b, rel(got32[b], ref))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_tall_tiles_fit_lds(monkeypatch, precision):
+    """A block cap of 64 on the 1024-interval grid asks for tiles of 69 rows
+    per thread (276 rows per block): every kernel that stages its tile in LDS,
+    the FP64 residual passes of the refinement included, lowers its rows per
+    thread until the tile fits, and the solve converges as with the default
+    cap, to the same cycle count and iterate."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    n, k = 1024, 200.0
+    k2 = to_gpu(W.constant_k2(n, k))
+    f = to_gpu(W.point_source_rhs(n, [W.center_node(n)]))
+    kw = dict(tol=1e-6, max_cycles=200, precision=precision)
+    x_ref, ref = Solver(k2, 1.0 / n, 1.0 / k, precision="fp32_refined").solve(f, **kw)
+    monkeypatch.setenv("HELMG_MAX_BLOCKS", "64")
+    x, info = Solver(k2, 1.0 / n, 1.0 / k, precision="fp32_refined").solve(f, **kw)
+    assert info["status"] == 0 and abs(info["cycles"][0] - ref["cycles"][0]) <= 1
+    d = rel(to_np(x)[0], to_np(x_ref)[0])
+    print(f"{precision}: cycles {info['cycles'][0]} (default cap {ref['cycles'][0]}), iterate difference {d:.2e}")
+    if precision == "fp64" and info["cycles"][0] == ref["cycles"][0]:
+        assert d <= 1e-10  # the two differ in the order of their reductions only
+    else:
+        assert d <= 1e-4  # both iterates are within the tolerance of the solution
