@@ -56,6 +56,7 @@ struct LaunchCtx {
     int nrhs_cap;       // right-hand sides the partials were sized for
     int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
     int fuse_correction = 1;  // 0: the coarse grid correction always runs as its own pass
+    int fuse_restrict = 1;    // 0: the restriction always runs as its own pass
     StopTest stop{};          // taken by the residual-norm pass when stop.ring is set
     int tall_rows = 4;        // block height of light kernels on grids of >= 256 intervals (4, 8, 16)
     int small_rows = 2;       // block height on grids of <= 128 intervals (2 or 4)
@@ -112,6 +113,20 @@ struct ProlongIn {
     Vec<T> xt{nullptr, 0};
 };
 
+// The restriction to fold into the last pass of a pre-smoothing step (§3
+// coarse grid correction, §4 transfer): fc = R r' on the coarse grid gc for
+// the residual r' of the updated iterate, uc = 0 (uc.p may be null) and, with
+// zc.p set, fc into the first coarse Arnoldi plane with partial sums of
+// ||fc||^2 in reduction region 0, as launch_restrict does. nblk receives the
+// number of blocks per right-hand side of that launch.
+template <typename T>
+struct RestrictOut {
+    Grid gc{};
+    int transfer = 0;
+    Vec<T> fc{nullptr, 0}, uc{nullptr, 0}, zc{nullptr, 0};
+    int nblk = 0;
+};
+
 // One GMRES(3) smoothing step (§5.3) on A u = f: five passes (residual; apply;
 // two fused orthogonalise + apply passes; last column + least squares + update).
 // Z holds 4 planes per right-hand side (Arnoldi vectors), Wa / Wb the
@@ -130,12 +145,15 @@ struct ProlongIn {
 // (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
 // starts with the second pass. u_zero: the step starts from u = 0 although u
 // does not hold zeros (its update pass then writes sum y_i s_i z_i without
-// reading u).
+// reading u). rout (with res.p; may be null): the last pass restricts the
+// residual itself (unless ctx.fuse_restrict is 0) and res is not written;
+// rout->nblk is set to the partial-sum count of the coarse launch, or to 0
+// when the caller must restrict res itself.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, const hipEvent_t* timed, Vec<T> res = Vec<T>{nullptr, 0},
                        int r_ready_nblk = 0,
-                       ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false);
+                       ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false, RestrictOut<T>* rout = nullptr);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

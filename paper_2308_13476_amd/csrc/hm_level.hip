@@ -993,6 +993,143 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_rr(Grid g, Vec<T> Z, Vec<T> u
         });
 }
 
+// Pass 5 of the last pre-smoothing step fused with the restriction of §4
+// (one pass instead of k_gm_u_rr + k_restrict): this block owns the coarse
+// tile of the coarse-grid geometry and the fine nodes 2I, 2I + 1 (both
+// directions) of its coarse nodes I. Over the fine region the tile's
+// restriction reads (the owned nodes and a halo of kH fine nodes), the
+// residual r' = z_0 - sum_i c_i w_i of the updated iterate is formed by the
+// recurrence of k_gm_u_rr and staged in LDS (zero off the grid, as the fine
+// ghosts the separate restriction reads); the owned fine nodes also get
+// u' = u + sum_i c_i z_i. Then fc = R r' from LDS, in k_restrict's order of
+// operations (so both paths give the same bits), with uc = 0, and with zc
+// set fc into the first coarse Arnoldi plane and partial sums of ||fc||^2.
+template <bool kBez>
+struct RestrictStage {
+    static constexpr int kH = kBez ? 2 : 1;          // fine halo of the restriction
+    static constexpr int TW = 2 * kBX - 1 + 2 * kH;  // staged fine columns
+    __host__ __device__ static int rows(int coarse_rows) { return 2 * coarse_rows - 1 + 2 * kH; }
+};
+
+template <typename T, int BY, bool kFromZero, bool kBez>
+__global__ __launch_bounds__(kBX * BY) void k_gm_u_restrict(Grid gf, Grid gc, Vec<T> Z, Vec<T> u, Vec<T> Wa,
+                                                            Vec<T> Wb, const GmState* st, double breakdown,
+                                                            const double* pin, int nblk_in, Vec<T> fc, Vec<T> uc,
+                                                            Vec<T> Zc, double* pout, const int* active, int rpt) {
+    using RS = RestrictStage<kBez>;
+    constexpr int H = RS::kH;
+    const int b = blockIdx.z;
+    const bool act = rhs_active(active, b);
+    cplx<T> c[3];
+    const int k = gm_update_weights<T>(st, b, breakdown, pin, nblk_in, c);
+    if (!act) return;
+    const cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    const cplx<T>* z1 = z0 + Z.plane;
+    const cplx<T>* z2 = z1 + Z.plane;
+    const cplx<T>* w2 = z2 + Z.plane;
+    const cplx<T>* w0 = Wa.rhs(b);
+    const cplx<T>* w1 = Wb.rhs(b);
+    cplx<T>* ub = u.rhs(b);
+    cplx<T> mc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) mc[q] = {-c[q].re, -c[q].im};
+    const BlockXY bt = block_xy();
+    const int c0 = bt.x * kBX, r0 = bt.y * BY * rpt;
+    const int fi0 = 2 * c0 - H, fj0 = 2 * r0 - H;  // fine node of LDS entry 0
+    const int frows = RS::rows(BY * rpt);
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    constexpr int NB = sizeof(T) == 4 ? 4 : 2;
+    cplx<T> xu[NB], x0[NB], x1[NB], x2[NB], y0[NB], y1[NB], y2[NB];
+    bool in[NB], own[NB];
+    long long pp[NB];
+    for_strided_batched<NB>(
+        RS::TW * frows,
+        [&](int v, int q) {
+            const int di = q % RS::TW, dj = q / RS::TW;
+            const int i = fi0 + di, j = fj0 + dj;
+            in[v] = i >= 0 && i <= gf.n && j >= 0 && j <= gf.n;
+            own[v] = in[v] && di >= H && di < H + 2 * kBX && dj >= H && dj < H + 2 * BY * rpt;
+            pp[v] = gf.at(min(max(i, 0), gf.n), min(max(j, 0), gf.n));
+            if (in[v]) {
+                x0[v] = z0[pp[v]];
+                y0[v] = w0[pp[v]];
+                y1[v] = w1[pp[v]];
+                y2[v] = w2[pp[v]];
+            }
+            if (own[v]) {
+                if constexpr (kFromZero) xu[v] = {T(0), T(0)};
+                else xu[v] = ub[pp[v]];
+                x1[v] = z1[pp[v]];
+                x2[v] = z2[pp[v]];
+            }
+        },
+        [&](int v, int q) {
+            cplx<T> rr{T(0), T(0)};
+            if (in[v]) {
+                rr = x0[v];
+                if (k > 0) rr = cfma(rr, mc[0], y0[v]);
+                if (k > 1) rr = cfma(rr, mc[1], y1[v]);
+                if (k > 2) rr = cfma(rr, mc[2], y2[v]);
+            }
+            lds[q] = rr;
+            if (own[v]) {
+                cplx<T> x = xu[v];
+                if (k > 0) x = cfma(x, c[0], x0[v]);
+                if (k > 1) x = cfma(x, c[1], x1[v]);
+                if (k > 2) x = cfma(x, c[2], x2[v]);
+                ub[pp[v]] = x;
+            }
+        });
+    __syncthreads();
+    cplx<T>* fb = fc.rhs(b);
+    cplx<T>* ucb = uc.p ? uc.rhs(b) : nullptr;
+    cplx<T>* zb = Zc.p ? Zc.p + (long long)(b * 4) * Zc.plane : nullptr;
+    double nrm[1] = {0.0};
+    for_nodes(gc, rpt, [&](int I, int J, long long pc) {
+        if (ucb) ucb[pc] = cplx<T>{T(0), T(0)};
+        const int l = (2 * J - fj0) * RS::TW + (2 * I - fi0);
+        cplx<T> acc{T(0), T(0)};
+        cplx<T> v;
+        if constexpr (kBez) {
+            constexpr T w[5] = {T(1), T(4), T(6), T(4), T(1)};
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+                cplx<T> row{T(0), T(0)};
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const cplx<T> x = lds[l + dy * RS::TW + dx];
+                    row.re += w[dx + 2] * x.re;
+                    row.im += w[dx + 2] * x.im;
+                }
+                acc.re += w[dy + 2] * row.re;
+                acc.im += w[dy + 2] * row.im;
+            }
+            v = T(1.0 / 256.0) * acc;
+        } else {
+            constexpr T w[3] = {T(1), T(2), T(1)};
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                cplx<T> row{T(0), T(0)};
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const cplx<T> x = lds[l + dy * RS::TW + dx];
+                    row.re += w[dx + 1] * x.re;
+                    row.im += w[dx + 1] * x.im;
+                }
+                acc.re += w[dy + 1] * row.re;
+                acc.im += w[dy + 1] * row.im;
+            }
+            v = T(1.0 / 16.0) * acc;
+        }
+        fb[pc] = v;
+        if (zb) {
+            zb[pc] = v;
+            nrm[0] += dnorm2(v);
+        }
+    });
+    if (zb) block_partials<1>(nrm, pout + b * kPartStride);
+}
+
 // Sums the nblk partial rows of a region into row 0 (same thread count and
 // order as a consumer-side reduction, hence the same totals), so that the
 // consumers of a large producer grid read one row.
@@ -1291,7 +1428,7 @@ constexpr int kOverlapMaxBlocks = 2048;
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
-                       Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero) {
+                       Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero, RestrictOut<T>* rout) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     const Geom qv = geom(lop.g, false, ctx);  // vector-only passes
@@ -1383,7 +1520,38 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         prereduce(B, std::integral_constant<int, 8>{});
         nb_op = nb;
     });
-    if (res.p && u_zero)
+    if (rout) rout->nblk = 0;
+    if (res.p && rout && ctx.fuse_restrict) {
+        // update + restriction in one pass on the coarse grid; rows per thread
+        // lowered until the staged fine region fits the tile bound
+        Geom qr = geom(rout->gc, false, ctx);
+        const bool bez = rout->transfer == 0;
+        auto bytes = [&](int rpt) {
+            return size_t(bez ? RestrictStage<true>::TW : RestrictStage<false>::TW) *
+                   (bez ? RestrictStage<true>::rows(qr.by * rpt) : RestrictStage<false>::rows(qr.by * rpt)) *
+                   sizeof(cplx<T>);
+        };
+        if (bytes(qr.rpt) > kMaxTileBytes) {
+            while (qr.rpt > 1 && bytes(qr.rpt) > kMaxTileBytes) --qr.rpt;
+            qr.grid = level_grid(rout->gc, qr.rpt, ctx.nrhs, qr.by);
+            qr.nblk = int(qr.grid.x * qr.grid.y);
+        }
+        const size_t shm = bytes(qr.rpt);
+        const Grid gf = lop.g, gc = rout->gc;
+        const RestrictOut<T>& ro = *rout;
+        with_by(qr.by, [&](auto byc) {
+            constexpr int BY = decltype(byc)::value;
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, qr.grid, qr.block, shm, ctx.stream, gf, gc, Z, u, Wa, Wb, st, breakdown,
+                                   (const double*)B, nb_op, ro.fc, ro.uc, ro.zc, A, HM_ACTIVE, qr.rpt);
+            };
+            if (u_zero && bez) go(k_gm_u_restrict<T, BY, true, true>);
+            else if (u_zero) go(k_gm_u_restrict<T, BY, true, false>);
+            else if (bez) go(k_gm_u_restrict<T, BY, false, true>);
+            else go(k_gm_u_restrict<T, BY, false, false>);
+        });
+        rout->nblk = qr.nblk;
+    } else if (res.p && u_zero)
         HM_LAUNCH(qv, (k_gm_u_rr<T, BY, true>), lop.g, Z, u, Wa, Wb, res, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
     else if (res.p)
         HM_LAUNCH(qv, (k_gm_u_rr<T, BY, false>), lop.g, Z, u, Wa, Wb, res, st, breakdown, B, nb_op, HM_ACTIVE,
@@ -1501,7 +1669,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
                                        Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>,                     \
-                                       int, ProlongIn<T>, bool);                                                \
+                                       int, ProlongIn<T>, bool, RestrictOut<T>*);                               \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

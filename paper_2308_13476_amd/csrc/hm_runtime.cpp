@@ -170,6 +170,9 @@ struct mg_ctx {
     // the coarse grid correction folded into the first post-smoothing pass
     // where its LDS stage fits (HELMG_FUSE_CORRECTION=0: always a pass of its own)
     int fuse_correction = 1;
+    // the restriction folded into the last pre-smoothing pass of GMRES cycles
+    // (HELMG_FUSE_RESTRICT=0: always a pass of its own)
+    int fuse_restrict = 1;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -321,6 +324,7 @@ Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
     LaunchCtx lc{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap, c->fuse_correction};
+    lc.fuse_restrict = c->fuse_restrict;
     lc.tall_rows = c->tall_rows;
     lc.small_rows = c->small_rows;
     return lc;
@@ -489,7 +493,8 @@ struct CycleParams {
 // not hold.
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
-            int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false) {
+            int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false,
+            RestrictOut<T>* rout = nullptr) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -515,7 +520,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, tev[1] ? tev : nullptr,
-                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero);
+                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero, rout);
     if (tev[1]) {
         c->ev_pending.push_back({tev[0], tev[1]});
         c->t_nodes += nodes;
@@ -576,22 +581,29 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
         return;
     }
     LevelBuf& cb = c->lv[l + 1];
-    // the last GMRES pre-smoothing step also forms the residual to restrict
-    const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0;
-    for (int s = 0; s < cp.nu1; ++s)
-        smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
-                  s == 0 && u_zero);
-    if (!fused)
-        launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
-                           vec<T>(Prec<T>::w(lb), lb));
     // the next level's first GMRES step starts from its zeroed iterate: its
     // residual pass is the restriction itself (launched levels only)
     const int lc1 = l + 1;
     const bool r_in_restrict = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && lc1 != c->tail_level[sizeof(T) == 4] &&
                                lc1 != c->L - 1;
-    const int nb_r = launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb),
-                                        vec<T>(Prec<T>::f(cb), cb), vec<T>(Prec<T>::u(cb), cb),
-                                        r_in_restrict ? vec<T>(Prec<T>::V(cb), cb) : Vec<T>{nullptr, 0});
+    RestrictOut<T> ro;
+    ro.gc = cb.g;
+    ro.transfer = c->transfer;
+    ro.fc = vec<T>(Prec<T>::f(cb), cb);
+    ro.uc = vec<T>(Prec<T>::u(cb), cb);
+    ro.zc = r_in_restrict ? vec<T>(Prec<T>::V(cb), cb) : Vec<T>{nullptr, 0};
+    // the last GMRES pre-smoothing step also forms the residual to restrict,
+    // and restricts it itself where the handle fuses the two
+    const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0;
+    for (int s = 0; s < cp.nu1; ++s)
+        smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
+                  s == 0 && u_zero, fused && s == cp.nu1 - 1 ? &ro : nullptr);
+    if (!fused)
+        launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
+                           vec<T>(Prec<T>::w(lb), lb));
+    const int nb_r = ro.nblk > 0 ? ro.nblk
+                                 : launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb),
+                                                      ro.fc, ro.uc, ro.zc);
     for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0, false, g == 0);
     // the coarse grid correction u += P e is formed by the first pass of the
     // first post-smoothing GMRES step, into the fourth Arnoldi plane (unused
@@ -1082,6 +1094,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (const char* e = std::getenv("HELMG_SMALL_ROWS")) c->small_rows = std::atoi(e) == 4 ? 4 : 2;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
     // batch handles: fewer, larger tiles per right-hand side (the launch has
     // max_batch times as many blocks; larger tiles amortise each block's
     // fixed costs: reduction, tile halo, block sums)

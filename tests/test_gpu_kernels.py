@@ -208,15 +208,17 @@ def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
 
 @pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"},
                                  {"HELMG_L1_PRODUCT": "2", "HELMG_MAX_BLOCKS": "200"},
-                                 {"HELMG_FUSE_CORRECTION": "0"}],
-                         ids=["block_cap_64", "stored_level1", "product_level1_fp64", "unfused_correction"])
+                                 {"HELMG_FUSE_CORRECTION": "0"}, {"HELMG_FUSE_RESTRICT": "0"}],
+                         ids=["block_cap_64", "stored_level1", "product_level1_fp64", "unfused_correction",
+                              "unfused_restriction"])
 def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
     """With a block cap of 64 every GMRES reduction goes through the one-block
     pre-reduction pass; HELMG_L1_PRODUCT=0 makes level 1 apply its stored
     Galerkin stencil in both precisions, =2 the product R C_s P in both (FP32
     cycles use the product by default, FP64 cycles the stored stencil);
     HELMG_FUSE_CORRECTION=0 runs the coarse grid correction as a pass of its
-    own instead of inside the first post-smoothing pass. Each
+    own instead of inside the first post-smoothing pass, HELMG_FUSE_RESTRICT=0
+    the restriction instead of inside the last pre-smoothing pass. Each
     gives the oracle's level-1 apply and cycle (FP64) and stays close to it in
     FP32."""
     require_gpu()
@@ -266,3 +268,35 @@ def test_tall_tiles_fit_lds(monkeypatch, precision):
         assert d <= 1e-10  # the two differ in the order of their reductions only
     else:
         assert d <= 1e-4  # both iterates are within the tolerance of the solution
+
+
+@pytest.mark.parametrize("transfer", ["bezier", "linear"])
+@pytest.mark.parametrize("n,cap", [(128, None), (256, "64"), (96, None)])
+def test_fused_restriction_is_bit_identical(monkeypatch, transfer, n, cap):
+    """The last pre-smoothing pass that also restricts its residual (staged in
+    LDS over the coarse tile's fine region and halo) gives the bits of the
+    separate update and restriction passes: V and W cycles, FP64 and FP32,
+    both transfers, two right-hand sides, ragged tiles (96 intervals), and
+    tall tiles (block cap 64 on 256 intervals)."""
+    require_gpu()
+    import torch
+    from paper_2308_13476_amd.solver import Solver
+    if cap:
+        monkeypatch.setenv("HELMG_MAX_BLOCKS", cap)
+    k2 = to_gpu(W.random_k2(n, 13, 10.0, 30.0))
+    u = _rand(n, 2, 140)
+    f = _rand(n, 2, 141)
+    out = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("HELMG_FUSE_RESTRICT", fuse)
+        S = Solver(k2, 1.0 / n, 0.2, transfer=transfer, max_batch=2, precision="fp32_refined",
+                   coarsest_n=6 if n == 96 else 4)
+        for cyc in ("V", "W"):
+            out[fuse, cyc, 64] = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, nu_pre=2, nu_post=1))
+            out[fuse, cyc, 32] = to_np(S.cycle(to_gpu(u.astype(np.complex64)), to_gpu(f.astype(np.complex64)),
+                                            cycle=cyc, nu_pre=1, nu_post=1, precision="fp32_refined"))
+        del S
+        torch.cuda.synchronize()
+    for cyc in ("V", "W"):
+        for bits in (64, 32):
+            assert np.array_equal(out["1", cyc, bits], out["0", cyc, bits]), (cyc, bits)
