@@ -195,7 +195,10 @@ mg_status mg_tune(mg_handle h, const void* rhs, int nrhs, int cycle, int smoothe
  * in FP64 on A_s x = W f with right preconditioning: every direction is
  * z_j = one cycle (cycle, smoother, opts->nu_pre / nu_post / omega) on
  * A_s z = v_j from z = 0, an FP64 cycle, or the FP32 cycle when
- * opts->precision is MG_FP32_REFINED; modified Gram-Schmidt Arnoldi; the
+ * opts->precision is MG_FP32_REFINED; classical Gram-Schmidt Arnoldi (all
+ * inner products of a column from one sweep over A_s z_j, then one update
+ * sweep; the oracle's modified Gram-Schmidt gives the same column up to
+ * rounding); the
  * least-squares problem by Givens rotations on the host, which reads each
  * Hessenberg column while the next iteration already runs (so a solve that
  * stops inside a restart cycle computes one iteration it does not use). The

@@ -234,17 +234,19 @@ void tail_init();
 void launch_lu_inverse(hipStream_t, int N, const cplx<double>* lu, const int* piv, cplx<double>* inv);
 
 // ---- outer flexible GMRES (level-0 FP64 vectors, [j][b][plane]) ----
-// w is orthogonalised against V_0..V_j by modified Gram-Schmidt; H[b * hstride + i]
-// receives column j (i = 0..j) and the subdiagonal ||w|| (i = j + 1); V_{j+1} = w / ||w||.
+constexpr int kMaxRestart = 64;  // longest restart cycle m
+// w is orthogonalised against V_0..V_j by classical Gram-Schmidt (all h_i =
+// <V_i, w> from the incoming w, then w -= sum h_i V_i); H[b * hstride + i]
+// receives column j (i = 0..j) and the subdiagonal ||w|| (i = j + 1);
+// V_{j+1} = w / ||w||, and its complex64 copy into v32 when v32 is not null.
 void launch_kry_orthogonalise(const LaunchCtx&, Grid g, cplx<double>* V, long long vstride, int j,
-                              cplx<double>* w, cplx<double>* H, int hstride, long long plane);
-// v = r / ||r|| with ||r||^2 from norms[b].r2.
+                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32);
+// v = r / ||r|| with ||r||^2 from norms[b].r2 (and its complex64 copy into v32 when not null).
 void launch_kry_first(const LaunchCtx&, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
-                      const RhsNorms* norms);
+                      const RhsNorms* norms, cplx<float>* v32);
 // x += sum_{i < nz} y[b * ystride + i] Z_i.
 void launch_kry_update(const LaunchCtx&, Grid g, const cplx<double>* Z, long long zstride, int nz,
                        const cplx<double>* y, int ystride, cplx<double>* x, long long plane);
-void launch_kry_cast_down(const LaunchCtx&, Grid g, const cplx<double>* src, cplx<float>* dst, long long plane);
 void launch_kry_cast_up(const LaunchCtx&, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane);
 
 // ---- setup ----

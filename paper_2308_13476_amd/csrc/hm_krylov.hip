@@ -1,8 +1,9 @@
 // Level-0 vector kernels of the outer flexible GMRES(m) (§1: multigrid on the
-// CSL as a preconditioner for GMRES): modified Gram-Schmidt passes with
-// consumer-side reductions, normalisation, the update x += Z y, precision
-// casts of whole planes and the first basis vector r / ||r||. FP64 data,
-// [b][plane] per vector, the Krylov vectors [j][b][plane].
+// CSL as a preconditioner for GMRES): classical Gram-Schmidt in two sweeps
+// (all inner products <v_i, w> in one pass over w, then w -= sum h_i v_i),
+// normalisation, the update x += Z y, precision casts of whole planes and
+// the first basis vector r / ||r||. FP64 data, [b][plane] per vector, the
+// Krylov vectors [j][b][plane].
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -10,51 +11,89 @@ namespace {
 
 __device__ __forceinline__ int kry_lead() { return blockIdx.x == 0 && blockIdx.y == 0 && thread_linear() == 0; }
 
-// partials of <v, w>
-__global__ __launch_bounds__(kBX * kBY) void k_kry_dot(Grid g, const cplx<double>* v, const cplx<double>* w,
-                                                      long long plane, double* pout, const int* active, int rpt) {
+// Inner products <v_i, w> for i = i0 .. i0 + cnt - 1 (cnt <= kCgsChunk) in
+// one sweep over w: block partial sums, 2 kCgsChunk per block (re, im per
+// vector; unused slots zero) at pout + b * kPartStride.
+constexpr int kCgsChunk = 16;
+__global__ __launch_bounds__(kBX * kBY) void k_kry_cdots(Grid g, const cplx<double>* V, long long vstride, int i0,
+                                                        int cnt, const cplx<double>* w, long long plane,
+                                                        double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
-    const cplx<double>* vb = v + b * plane;
     const cplx<double>* wb = w + b * plane;
-    double acc[2] = {0.0, 0.0};
+    const cplx<double>* vb = V + i0 * vstride + b * plane;
+    double acc[2 * kCgsChunk];
+#pragma unroll
+    for (int k = 0; k < 2 * kCgsChunk; ++k) acc[k] = 0.0;
     for_nodes(g, rpt, [&](int, int, long long p) {
-        const cplx<double> a = vb[p], c = wb[p];
-        acc[0] += a.re * c.re + a.im * c.im;
-        acc[1] += a.re * c.im - a.im * c.re;
+        const cplx<double> c = wb[p];
+        cplx<double> a[kCgsChunk];
+#pragma unroll
+        for (int q = 0; q < kCgsChunk; ++q)
+            if (q < cnt) a[q] = vb[q * vstride + p];
+#pragma unroll
+        for (int q = 0; q < kCgsChunk; ++q)
+            if (q < cnt) {
+                acc[2 * q] += a[q].re * c.re + a[q].im * c.im;
+                acc[2 * q + 1] += a[q].re * c.im - a[q].im * c.re;
+            }
     });
-    block_partials<2>(acc, pout + b * kPartStride);
+    block_partials<2 * kCgsChunk>(acc, pout + b * kPartStride);
 }
 
-// h = <v_i, w> from the previous pass's partials; H[b][i] = h; w -= h v_i;
-// then partials of <v_next, w> (v_next != null) or of ||w||^2.
-__global__ __launch_bounds__(kBX * kBY) void k_kry_mgs(Grid g, const cplx<double>* vi, const cplx<double>* vnext,
-                                                      cplx<double>* w, long long plane, cplx<double>* Hcol,
-                                                      int hstride, const double* pin, int nblk_in, double* pout,
-                                                      const int* active, int rpt) {
+// h_i = <v_i, w> for i = 0 .. j from the partials of the k_kry_cdots chunks
+// (chunk c of nblk blocks at pin + b * kPartStride + c * nblk * 2 kCgsChunk):
+// one block per right-hand side, one wavefront per inner product at a time,
+// lanes over the blocks in a fixed order (deterministic); H[b][i] = h_i.
+__global__ __launch_bounds__(kBX * kBY) void k_kry_hreduce(const double* pin, int nblk, int j, cplx<double>* H,
+                                                          int hstride, const int* active) {
+    const int b = blockIdx.x;
+    if (!rhs_active(active, b)) return;
+    const int lane = threadIdx.x;
+    for (int i = threadIdx.y; i <= j; i += blockDim.y) {
+        const int c = i / kCgsChunk, k = i % kCgsChunk;
+        const double* src = pin + b * kPartStride + (long long)c * nblk * 2 * kCgsChunk + 2 * k;
+        double re = 0.0, im = 0.0;
+        for (int q = lane; q < nblk; q += kBX) {
+            re += src[q * 2 * kCgsChunk];
+            im += src[q * 2 * kCgsChunk + 1];
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == kBX - 1) H[b * hstride + i] = cplx<double>{re, im};
+    }
+}
+
+// w -= sum_{i <= j} h_i v_i (h_i from H[b][i], in order of i); partials of
+// ||w||^2 (two per block, the second zero: the layout k_kry_normalize reads).
+__global__ __launch_bounds__(kBX * kBY) void k_kry_cgs_update(Grid g, const cplx<double>* V, long long vstride, int j,
+                                                             cplx<double>* w, long long plane, const cplx<double>* H,
+                                                             int hstride, double* pout, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
-    double t[2];
-    reduce_partials<2>(pin + b * kPartStride, nblk_in, t);
-    const cplx<double> h{t[0], t[1]};
-    if (kry_lead()) Hcol[b * hstride] = h;
-    const cplx<double>* vb = vi + b * plane;
-    const cplx<double>* nb = vnext ? vnext + b * plane : nullptr;
+    __shared__ cplx<double> hs[kMaxRestart];
+    for (int i = thread_linear(); i <= j; i += kBX * kBY) hs[i] = H[b * hstride + i];
+    __syncthreads();
     cplx<double>* wb = w + b * plane;
+    const cplx<double>* vb = V + b * plane;
     double acc[2] = {0.0, 0.0};
     for_nodes(g, rpt, [&](int, int, long long p) {
         cplx<double> x = wb[p];
-        const cplx<double> a = vb[p];
-        x.re -= h.re * a.re - h.im * a.im;
-        x.im -= h.re * a.im + h.im * a.re;
-        wb[p] = x;
-        if (nb) {
-            const cplx<double> c = nb[p];
-            acc[0] += c.re * x.re + c.im * x.im;
-            acc[1] += c.re * x.im - c.im * x.re;
-        } else {
-            acc[0] += x.re * x.re + x.im * x.im;
+        for (int i0 = 0; i0 <= j; i0 += 8) {
+            cplx<double> a[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (i0 + q <= j) a[q] = vb[(i0 + q) * vstride + p];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (i0 + q <= j) {
+                    const cplx<double> h = hs[i0 + q];
+                    x.re -= h.re * a[q].re - h.im * a[q].im;
+                    x.im -= h.re * a[q].im + h.im * a[q].re;
+                }
         }
+        wb[p] = x;
+        acc[0] += x.re * x.re + x.im * x.im;
     });
     block_partials<2>(acc, pout + b * kPartStride);
 }
@@ -63,8 +102,8 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_mgs(Grid g, const cplx<double
 // v_out = w / ||w|| (zero when ||w|| = 0).
 __global__ __launch_bounds__(kBX * kBY) void k_kry_normalize(Grid g, const cplx<double>* w, cplx<double>* vout,
                                                             long long plane, cplx<double>* Hsub, int hstride,
-                                                            const double* pin, int nblk_in, const int* active,
-                                                            int rpt) {
+                                                            const double* pin, int nblk_in, cplx<float>* v32,
+                                                            const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     double t[2];
@@ -74,20 +113,30 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_normalize(Grid g, const cplx<
     const double s = hn > 0.0 ? 1.0 / hn : 0.0;
     const cplx<double>* wb = w + b * plane;
     cplx<double>* ob = vout + b * plane;
-    for_nodes(g, rpt, [&](int, int, long long p) { ob[p] = s * wb[p]; });
+    cplx<float>* fb = v32 ? v32 + b * plane : nullptr;
+    for_nodes(g, rpt, [&](int, int, long long p) {
+        const cplx<double> v = s * wb[p];
+        ob[p] = v;
+        if (fb) fb[p] = cast<float>(v);
+    });
 }
 
 // v = r / ||r|| with ||r||^2 from norms[b].r2
 __global__ __launch_bounds__(kBX * kBY) void k_kry_first(Grid g, const cplx<double>* r, cplx<double>* v,
-                                                        long long plane, const RhsNorms* norms, const int* active,
-                                                        int rpt) {
+                                                        long long plane, const RhsNorms* norms, cplx<float>* v32,
+                                                        const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const double nr = sqrt(norms[b].r2);
     const double s = nr > 0.0 ? 1.0 / nr : 0.0;
     const cplx<double>* rb = r + b * plane;
     cplx<double>* vb = v + b * plane;
-    for_nodes(g, rpt, [&](int, int, long long p) { vb[p] = s * rb[p]; });
+    cplx<float>* fb = v32 ? v32 + b * plane : nullptr;
+    for_nodes(g, rpt, [&](int, int, long long p) {
+        const cplx<double> x = s * rb[p];
+        vb[p] = x;
+        if (fb) fb[p] = cast<float>(x);
+    });
 }
 
 // x += sum_i y[b][i] z_i for i < nz (y complex, [b][ystride])
@@ -120,10 +169,10 @@ struct KGeom {
     int rpt, nblk;
 };
 
-KGeom kgeom(const LaunchCtx& ctx, const Grid& g) {
+KGeom kgeom(const LaunchCtx& ctx, const Grid& g, long long cap_limit = 1LL << 30) {
     const long long m = g.n + 1;
     const long long bx = (m + kBX - 1) / kBX;
-    const long long cap = ctx.block_cap;
+    const long long cap = std::max(1LL, std::min<long long>(ctx.block_cap, cap_limit - bx));
     long long rpt = (m * bx + (long long)kBY * cap - 1) / ((long long)kBY * cap);
     if (rpt < 1) rpt = 1;
     KGeom q;
@@ -139,29 +188,28 @@ double* kregion(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)
 }  // namespace
 
 void launch_kry_orthogonalise(const LaunchCtx& ctx, Grid g, cplx<double>* V, long long vstride, int j,
-                              cplx<double>* w, cplx<double>* H, int hstride, long long plane) {
-    const KGeom q = kgeom(ctx, g);
+                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32) {
+    // the partials of every chunk fit one reduction region
+    constexpr int kChunks = (kMaxRestart + kCgsChunk - 1) / kCgsChunk;
+    const KGeom q = kgeom(ctx, g, kPartStride / (2 * kCgsChunk * kChunks));
     double* A = kregion(ctx, 0);
     double* B = kregion(ctx, 1);
-    hipLaunchKernelGGL(k_kry_dot, q.grid, q.block, 0, ctx.stream, g, V, w, plane, A, ctx.active, q.rpt);
-    double* in = A;
-    double* out = B;
-    for (int i = 0; i <= j; ++i) {
-        const cplx<double>* vnext = (i < j) ? V + (i + 1) * vstride : nullptr;
-        hipLaunchKernelGGL(k_kry_mgs, q.grid, q.block, 0, ctx.stream, g, V + i * vstride, vnext, w, plane, H + i,
-                           hstride, in, q.nblk, out, ctx.active, q.rpt);
-        double* t = in;
-        in = out;
-        out = t;
-    }
+    for (int i0 = 0; i0 <= j; i0 += kCgsChunk)
+        hipLaunchKernelGGL(k_kry_cdots, q.grid, q.block, 0, ctx.stream, g, V, vstride, i0,
+                           std::min(kCgsChunk, j + 1 - i0), w, plane,
+                           A + (long long)(i0 / kCgsChunk) * q.nblk * 2 * kCgsChunk, ctx.active, q.rpt);
+    hipLaunchKernelGGL(k_kry_hreduce, dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, A, q.nblk, j, H, hstride,
+                       ctx.active);
+    hipLaunchKernelGGL(k_kry_cgs_update, q.grid, q.block, 0, ctx.stream, g, V, vstride, j, w, plane, H, hstride, B,
+                       ctx.active, q.rpt);
     hipLaunchKernelGGL(k_kry_normalize, q.grid, q.block, 0, ctx.stream, g, w, V + (j + 1) * vstride, plane,
-                       H + j + 1, hstride, in, q.nblk, ctx.active, q.rpt);
+                       H + j + 1, hstride, B, q.nblk, v32, ctx.active, q.rpt);
 }
 
 void launch_kry_first(const LaunchCtx& ctx, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
-                      const RhsNorms* norms) {
+                      const RhsNorms* norms, cplx<float>* v32) {
     const KGeom q = kgeom(ctx, g);
-    hipLaunchKernelGGL(k_kry_first, q.grid, q.block, 0, ctx.stream, g, r, v, plane, norms, ctx.active, q.rpt);
+    hipLaunchKernelGGL(k_kry_first, q.grid, q.block, 0, ctx.stream, g, r, v, plane, norms, v32, ctx.active, q.rpt);
 }
 
 void launch_kry_update(const LaunchCtx& ctx, Grid g, const cplx<double>* Z, long long zstride, int nz,
@@ -169,12 +217,6 @@ void launch_kry_update(const LaunchCtx& ctx, Grid g, const cplx<double>* Z, long
     const KGeom q = kgeom(ctx, g);
     hipLaunchKernelGGL(k_kry_update, q.grid, q.block, 0, ctx.stream, g, Z, zstride, nz, y, ystride, x, plane,
                        ctx.active, q.rpt);
-}
-
-void launch_kry_cast_down(const LaunchCtx& ctx, Grid g, const cplx<double>* src, cplx<float>* dst, long long plane) {
-    const KGeom q = kgeom(ctx, g);
-    hipLaunchKernelGGL((k_kry_cast<double, float>), q.grid, q.block, 0, ctx.stream, g, src, dst, plane, ctx.active,
-                       q.rpt);
 }
 
 void launch_kry_cast_up(const LaunchCtx& ctx, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane) {

@@ -427,6 +427,18 @@ __device__ __forceinline__ double dpp_move(double x) {
     return __longlong_as_double((unsigned long long)unsigned(lo) | ((unsigned long long)unsigned(hi) << 32));
 }
 
+// One value summed over the 64 lanes of a wavefront by the moves of
+// block_sum; lane 63 ends with the total.
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_move<0xb1, 0xF>(x);
+    x += dpp_move<0x4e, 0xF>(x);
+    x += dpp_move<0x124, 0xF>(x);
+    x += dpp_move<0x128, 0xF>(x);
+    x += dpp_move<0x142, 0xA>(x);
+    x += dpp_move<0x143, 0xC>(x);
+    return x;
+}
+
 // Block sum for 64 x BY thread blocks, BY <= kMaxBY (wavefront = threadIdx.y):
 // each wavefront reduces its K values with DPP moves, lane 63 stores them,
 // and every thread adds the wavefront totals in wavefront order.

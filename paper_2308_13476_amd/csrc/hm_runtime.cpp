@@ -1385,8 +1385,6 @@ mg_status mg_solve_multi(mg_handle* handles, int nprob, const void* const* rhs, 
 
 namespace {
 
-constexpr int kMaxRestart = 64;
-
 // Carve of the caller's FGMRES buffer (base == nullptr only measures).
 struct KrylovBuf {
     cplx<double>* V = nullptr;  // (m + 1) vectors
@@ -1536,7 +1534,10 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
         }
         if (running == 0) break;
         if (mg_status st = set_active(act)) return st;
-        launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms);
+        // v_0, and each v_{j+1} below, is also written in complex64 to the
+        // FP32 cycle's right-hand side plane when the preconditioner is the
+        // FP32 cycle
+        launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms, fp32 ? l0.f32 : nullptr);
         std::vector<int> in_cycle = act;  // right-hand sides updated at the end of this cycle
         std::vector<int> stopped(nrhs, 0);
         // iteration j on the stream: z_j = M(v_j), one cycle from zero on
@@ -1545,13 +1546,12 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
         auto enqueue = [&](int j) -> mg_status {
             cplx<double>* vj = K.V + j * K.vstride;
             cplx<double>* zj = K.Z + j * K.vstride;
-            if (fp32) launch_kry_cast_down(lc, g0, vj, l0.f32, pl);
-            else HM_HIP(hipMemcpyAsync(l0.f64, vj, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
+            if (!fp32) HM_HIP(hipMemcpyAsync(l0.f64, vj, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
             if (mg_status st = run_cycle_graph(c, s, key, precond_body)) return st;
             if (fp32) launch_kry_cast_up(lc, g0, l0.u32, zj, pl);
             else HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
             launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
-            launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl);
+            launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl, fp32 ? l0.f32 : nullptr);
             if (mg_status st = check_launch(c)) return st;
             HM_HIP(hipMemcpyAsync(c->h_hcol + size_t(j & 1) * nrhs * (m + 1), K.H,
                                   sizeof(cplx<double>) * nrhs * (m + 1), hipMemcpyDeviceToHost, s));
