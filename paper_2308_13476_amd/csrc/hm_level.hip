@@ -36,8 +36,19 @@ int level_rpt(const Grid& g, int by, int cap) {
     return int(r < 1 ? 1 : r);
 }
 
-dim3 level_grid(const Grid& g, int rpt, int nrhs, int by) {
-    return dim3((g.n + 1 + kBX - 1) / kBX, (g.n + 1 + by * rpt - 1) / (by * rpt), nrhs);
+// Grid of a level launch. pad8 (handles for batches): the row-block count is
+// raised until the tiles of one right-hand side are a multiple of 8, so that
+// tile t of every right-hand side is dispatched to the same XCD (workgroups
+// go to the eight XCDs round-robin by linear id) and the operator data all
+// right-hand sides share (stencil coefficient planes, k^2) is fetched once
+// into that XCD's L2 instead of once per right-hand side. The extra tiles lie
+// below the grid: their blocks touch no node and write zero partial sums.
+dim3 level_grid(const Grid& g, int rpt, int nrhs, int by, bool pad8 = false) {
+    const unsigned gx = (g.n + 1 + kBX - 1) / kBX;
+    unsigned gy = (g.n + 1 + by * rpt - 1) / (by * rpt);
+    if (pad8)
+        while ((gx * gy) % 8 != 0) ++gy;
+    return dim3(gx, gy, nrhs);
 }
 
 struct Geom {
@@ -49,7 +60,7 @@ Geom geom(const Grid& g, bool heavy, const LaunchCtx& ctx) {
     Geom q;
     q.by = block_rows(g, heavy, ctx);
     q.rpt = level_rpt(g, q.by, ctx.block_cap);
-    q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by);
+    q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by, ctx.nrhs_cap > 1);
     q.block = dim3(kBX, q.by);
     q.nblk = int(q.grid.x * q.grid.y);
     return q;
@@ -65,7 +76,7 @@ Geom geom_op(const Grid& g, const LaunchCtx& ctx) {
     Geom q = geom(g, Op::kHeavy, ctx);
     if (tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) {
         while (q.rpt > 1 && tile_bytes<Op, T>(q.by, q.rpt) > kMaxTileBytes) --q.rpt;
-        q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by);
+        q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by, ctx.nrhs_cap > 1);
         q.nblk = int(q.grid.x * q.grid.y);
     }
     return q;
@@ -122,6 +133,7 @@ template <typename T, bool kBez, typename PGet, typename F>
 __device__ __forceinline__ void product_stages(const ProductOp<T, kBez>& op, const Tile<3>& tl, cplx<T>* lds,
                                                PGet&& pget, F&& f) {
     using PS = ProductStages<T>;
+    if (tl.r0 > op.g.n) return;  // padding tile of a batch grid: no coarse node
     const int rows = tl.rows;
     cplx<T>* y = lds + Tile<3>::TW * (rows + 6);
     cplx<T>* v = y + PS::YW * PS::yrows(rows);
@@ -1400,7 +1412,7 @@ void launch_prolong_add(const LaunchCtx& ctx, Grid coarse, Grid fine, int transf
     auto bytes = [&](int rpt) { return size_t(kProlongTW) * prolong_rows(q.by * rpt) * sizeof(cplx<T>); };
     if (bytes(q.rpt) > kMaxTileBytes) {
         while (q.rpt > 1 && bytes(q.rpt) > kMaxTileBytes) --q.rpt;
-        q.grid = level_grid(fine, q.rpt, ctx.nrhs, q.by);
+        q.grid = level_grid(fine, q.rpt, ctx.nrhs, q.by, ctx.nrhs_cap > 1);
         q.nblk = int(q.grid.x * q.grid.y);
     }
     const size_t shm = bytes(q.rpt);
@@ -1533,7 +1545,7 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         };
         if (bytes(qr.rpt) > kMaxTileBytes) {
             while (qr.rpt > 1 && bytes(qr.rpt) > kMaxTileBytes) --qr.rpt;
-            qr.grid = level_grid(rout->gc, qr.rpt, ctx.nrhs, qr.by);
+            qr.grid = level_grid(rout->gc, qr.rpt, ctx.nrhs, qr.by, ctx.nrhs_cap > 1);
             qr.nblk = int(qr.grid.x * qr.grid.y);
         }
         const size_t shm = bytes(qr.rpt);

@@ -237,9 +237,14 @@ struct Ident {
     template <typename X>
     __device__ __forceinline__ X operator()(const X& x) const { return x; }
 };
+template <typename T, int R>
+__device__ __forceinline__ bool tile_below_grid(const Tile<R>& t, const Grid& g) {
+    return t.r0 - R > g.n;  // padding tiles of batch grids (uniform in the block)
+}
 template <typename T, int R, typename Load, typename Make>
 __device__ __forceinline__ void fill_tile(cplx<T>* lds, const Tile<R>& t, const Grid& g, Load&& load, Make&& make) {
     static_assert(R <= kGhost, "tile halo beyond the stored ghost layers");
+    if (tile_below_grid<T, R>(t, g)) return;  // no node of the tile or its halo exists
     constexpr int FB = FillBatch<T>::value;
     decltype(load(0LL)) v[FB];
     bool ok[FB];
@@ -265,6 +270,7 @@ template <typename T, int R, typename Load, typename Make, typename Mid>
 __device__ __forceinline__ bool fill_tile_mid(cplx<T>* lds, const Tile<R>& t, const Grid& g, Load&& load,
                                               Make&& make, Mid&& mid) {
     static_assert(R <= kGhost, "tile halo beyond the stored ghost layers");
+    if (tile_below_grid<T, R>(t, g)) return mid();  // nothing to stage
     constexpr int FB = FillBatch<T>::value;
     decltype(load(0LL)) v[FB];
     bool ok[FB];

@@ -154,8 +154,9 @@ struct mg_ctx {
     int tail_level[2] = {-1, -1};
     int tail_n = 16;
     // level 1 applied as R C_s P from level-0 data instead of its stored
-    // stencil: 1 in FP32 cycles (default; measured faster there, while FP64
-    // cycles are faster with the stored stencil), 2 in both, 0 never
+    // stencil: 1 in FP32 cycles (default on handles for one right-hand side;
+    // measured faster there, while FP64 cycles are faster with the stored
+    // stencil), 2 in both, 0 never (default on batch handles)
     // (HELMG_L1_PRODUCT)
     int product_l1 = 1;
     // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
@@ -1092,6 +1093,10 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
         c->tall_rows = (v == 8 || v == 16) ? v : 4;
     }
     if (const char* e = std::getenv("HELMG_SMALL_ROWS")) c->small_rows = std::atoi(e) == 4 ? 4 : 2;
+    // batch handles: level 1 applies its stored stencil in both precisions (its
+    // coefficient planes are read once per XCD for all right-hand sides, which
+    // the product's fine-grid stages, recomputed per right-hand side, cannot match)
+    if (max_batch > 1) c->product_l1 = 0;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
@@ -1101,7 +1106,10 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (max_batch > 1) c->block_cap = std::max(64, 640 / max_batch);
     if (const char* e = std::getenv("HELMG_MAX_BLOCKS")) {
         const int v = std::atoi(e);
-        c->block_cap = v < 64 ? 64 : (v > kMaxPartialBlocks ? kMaxPartialBlocks : v);
+        // room below kMaxPartialBlocks for the rounding of the grid to whole
+        // tiles and for the padding of batch grids to multiples of 8 tiles
+        constexpr int kCapMax = kMaxPartialBlocks - 1024;
+        c->block_cap = v < 64 ? 64 : (v > kCapMax ? kCapMax : v);
     }
     {
         // default tail: levels of at most 16 intervals (the autotuner's choice on
