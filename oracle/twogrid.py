@@ -8,8 +8,10 @@ Galerkin product of either A itself or the shifted Laplacian C (§4, Table 1).
 
 The diagnostics below (§3.1 HPD tests of Gamma~, §4.2 optimality value) are
 pinned by closed forms, the identity T_0^H T_0 = I - Gamma, 14 of the 16 HPD
-marks of Table 1 and the qualitative trends of Table 2. The values of
-Table 2 themselves are not reproduced: parity unpinned for them.
+marks of Table 1 and the values of Table 2: evaluated on Gamma = I - T_0^H T_0
+of the two-grid operator itself (table2_value), 28 of its 40 entries are
+reproduced within 0.01 (35 within 0.02) and all within 0.09; on Gamma~ (the operator its
+caption names) they come out 0.4-0.9 of the printed values.
 """
 from __future__ import annotations
 
@@ -119,3 +121,15 @@ def two_grid_operator(k: float, n: int, **kw) -> np.ndarray:
     A, M, Q = two_grid_parts(k, n, **kw)
     I = np.eye(A.shape[0])
     return (I - Q @ A) @ (I - M @ A)
+
+
+def table2_value(k: float, n: int, omega: float, nu: int, operator: str = "gamma") -> float:
+    """The optimality value of Table 2 (§4.2): ||B||_1 / kappa_1(B) for
+    B = Gamma = I - T_0^H T_0 of the two-grid operator with nu Jacobi steps
+    (operator="gamma"; the reading under which the printed values are
+    reproduced) or for the simplified Gamma~ (operator="gamma_tilde"). Bezier
+    transfers, coarse operator from the CSL with beta2 = 0.7."""
+    if operator == "gamma_tilde":
+        return optimality_value(gamma_tilde(k, n, omega=omega, nu=nu))
+    T = two_grid_operator(k, n, omega=omega, nu=nu)
+    return optimality_value(np.eye(T.shape[0]) - T.conj().T @ T)

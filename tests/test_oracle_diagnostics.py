@@ -5,8 +5,10 @@ Pins: closed forms (D = A^{-1} gives Gamma = I; D = 0 gives 0),
 T_0^H T_0 = I - Gamma against the separately built T_0, the HPD marks of
 Table 1 (tests/golden/table1_two_grid_norms.json) where they are reproduced,
 and the paper's corollary chain Gamma~ HPD => ||T_0||_2 < 1 on every case.
-Table 2's values are not reproduced (reported beside the paper's in the
-design notes): parity unpinned for them."""
+Table 2: evaluated on Gamma = I - T_0^H T_0 of the two-grid operator, 28 of
+its 40 printed values are reproduced within 0.01 and all within 0.09 (on
+Gamma~, the operator its caption names, they come out 0.4-0.9 of the printed
+values)."""
 import json
 import os
 
@@ -126,3 +128,30 @@ def test_two_smoothing_steps_give_the_expanded_approximate_inverse():
     # the coarse part is a projection-like map: Q A Q = Q when A_c = R A P
     A2, M2, Q2 = TG.two_grid_parts(5, 8, coarse_on="A")
     np.testing.assert_allclose(Q2 @ A2 @ Q2, Q2, atol=1e-9 * np.abs(Q2).max())
+
+
+def test_table2_values_on_the_two_grid_gamma():
+    """§4.2 Table 2 (omega in {1.5, 2, 2.5, 4.5, 7}, nu in {1, 2}, k in
+    {5, 10, 20, 30} at kh = 0.625) against the printed values: the omega = 4.5
+    column that the experiments use within 0.006 (nu = 1) and 0.02 (nu = 2),
+    28 of the 40 entries within 0.01 (35 within 0.02), every entry within 0.09; and the paper's
+    reading of the table: at omega = 4.5 a second smoothing step raises the
+    value at every k, at omega = 1.5 it lowers it for k >= 20."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table2_optimality.json")))
+    within = 0
+    got = {}
+    for q, om in enumerate(g["omega"]):
+        for nu, key in ((1, "values_nu1"), (2, "values_nu2")):
+            vals = [TG.table2_value(k, n, om, nu) for k, n in zip(g["k"], g["n"])]
+            got[om, nu] = vals
+            err = [abs(a - b) for a, b in zip(vals, g[key][q])]
+            assert max(err) <= 0.09, (om, nu, vals, g[key][q])
+            within += sum(e <= 0.01 for e in err)
+            if om == 4.5:
+                assert max(err) <= (0.006 if nu == 1 else 0.02), (nu, vals, g[key][q])
+    assert within >= 28, within
+    assert all(b > a for a, b in zip(got[4.5, 1], got[4.5, 2]))
+    assert all(b < a for a, b in zip(got[1.5, 1][2:], got[1.5, 2][2:]))
+    # the simplified operator of the caption gives markedly smaller values
+    k, n = g["k"][0], g["n"][0]
+    assert TG.table2_value(k, n, 4.5, 1, operator="gamma_tilde") < 0.5 * got[4.5, 1][0]
