@@ -92,6 +92,10 @@ template <typename T> void launch_apply(const LaunchCtx&, const LevelOp<T>&, Vec
 template <typename T> void launch_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> r);
 template <typename T>
 void launch_jacobi(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
+// Two sweeps from x into y in one pass on level 0; returns false, launching
+// nothing, on any other level (or where the two LDS stages do not fit).
+template <typename T>
+bool launch_jacobi2(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
 // fc = R r; when uc.p is not null the coarse iterate uc is zeroed in the same
 // pass. When z0.p is not null, fc is also written to the first Arnoldi plane of
 // z0 (4 planes per right-hand side) with the partial sums of ||fc||^2 in

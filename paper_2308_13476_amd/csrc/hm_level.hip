@@ -429,6 +429,93 @@ __global__ __launch_bounds__(kBX * BY) void k_jacobi(Op op, Vec<T> x, Vec<T> f, 
                              });
 }
 
+// Two weighted-Jacobi sweeps in one pass on level 0 (temporal blocking of the
+// smoother of §3): x is staged for the tile plus a halo of 2, the first sweep
+// runs on the tile plus a halo of 1 (nodes off the grid hold zero, the ghosts
+// the second sweep reads) into a second LDS stage, the second sweep on the
+// tile. Per node the arithmetic of k_jacobi (the general form of the
+// five-point operator everywhere); f and k^2 of the tile are read by both
+// sweeps, the second time from cache, and the loads of each sweep are
+// gathered in batches. (On stored-stencil levels the first sweep's halo of R
+// nodes, each with its (2R+1)^2 coefficients, cost more than the second pass
+// it saves: measured 1.3-2.6x slower, so those levels keep one sweep per pass.)
+struct Jacobi2Stage {
+    static constexpr int TA = kBX + 4;  // stage A (x): tile plus 2
+    static constexpr int TB = kBX + 2;  // stage B (first sweep): tile plus 1
+    __host__ __device__ static size_t values(int rows) { return size_t(TA) * (rows + 4) + size_t(TB) * (rows + 2); }
+};
+
+template <typename T, int BY>
+__global__ __launch_bounds__(kBX * BY) void k_jacobi2(FineOp<T> op, Vec<T> x, Vec<T> f, Vec<T> y, T inv_omega,
+                                                      const int* active, int rpt) {
+    using JS = Jacobi2Stage;
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    const cplx<T>* xb = x.rhs(b);
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* yb = y.rhs(b);
+    const Grid& g = op.g;
+    const BlockXY bt = block_xy();
+    const int rows = BY * rpt;
+    const int c0 = bt.x * kBX, r0 = bt.y * rows;
+    cplx<T>* sa = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    cplx<T>* sb = sa + JS::TA * (rows + 4);
+    constexpr int NB = FillBatch<T>::value;
+    if (r0 - 2 <= g.n) {  // padding tiles of batch grids stage nothing
+        // stage A: x on the tile plus 2 (zero off the grid)
+        cplx<T> v[NB];
+        bool ok[NB];
+        for_strided_batched<NB>(
+            JS::TA * (rows + 4),
+            [&](int u, int q) {
+                const int i = c0 - 2 + q % JS::TA, j = r0 - 2 + q / JS::TA;
+                ok[u] = i >= 0 && i <= g.n && j >= 0 && j <= g.n;
+                v[u] = xb[g.at(min(max(i, 0), g.n), min(max(j, 0), g.n))];
+            },
+            [&](int u, int q) { sa[q] = ok[u] ? v[u] : cplx<T>{T(0), T(0)}; });
+        __syncthreads();
+        // first sweep on the tile plus 1
+        cplx<T> fv[NB];
+        T kv[NB];
+        for_strided_batched<NB>(
+            JS::TB * (rows + 2),
+            [&](int u, int q) {
+                const int i = c0 - 1 + q % JS::TB, j = r0 - 1 + q / JS::TB;
+                ok[u] = i >= 0 && i <= g.n && j >= 0 && j <= g.n;
+                const long long p = g.at(min(max(i, 0), g.n), min(max(j, 0), g.n));
+                fv[u] = fb[p];
+                kv[u] = op.k2[p];
+            },
+            [&](int u, int q) {
+                const int i = c0 - 1 + q % JS::TB, j = r0 - 1 + q / JS::TB;
+                cplx<T> out{T(0), T(0)};
+                if (ok[u]) {
+                    const int la = (j - r0 + 2) * JS::TA + (i - c0 + 2);
+                    const cplx<T> r = fv[u] - op.apply5k(i, j, kv[u], sa[la], sa[la - 1], sa[la + 1],
+                                                          sa[la - JS::TA], sa[la + JS::TA]);
+                    out = sa[la] + inv_omega * cdiv(r, op.diag_k(i, j, kv[u]));
+                }
+                sb[q] = out;
+            });
+    }
+    __syncthreads();
+    // second sweep on the tile
+    cplx<T> fv[NB];
+    T kv[NB];
+    for_nodes_batched<NB>(
+        g, rpt,
+        [&](int u, long long p) {
+            fv[u] = fb[p];
+            kv[u] = op.k2[p];
+        },
+        [&](int u, int i, int j, long long p) {
+            const int lb = (j - r0 + 1) * JS::TB + (i - c0 + 1);
+            const cplx<T> r = fv[u] - op.apply5k(i, j, kv[u], sb[lb], sb[lb - 1], sb[lb + 1], sb[lb - JS::TB],
+                                                  sb[lb + JS::TB]);
+            yb[p] = sb[lb] + inv_omega * cdiv(r, op.diag_k(i, j, kv[u]));
+        });
+}
+
 // ---------------------------------------------------------------- transfers
 // Restriction R = P^T / 4 of the §4 prolongation: the 2D row is the outer
 // product of [1 4 6 4 1]/16 (Bézier) or [1 2 1]/4 (linear) centred on the
@@ -1392,6 +1479,30 @@ void launch_jacobi(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T>
     });
 }
 
+template <typename T>
+bool launch_jacobi2(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega) {
+    bool done = false;
+    with_op(lop, [&](auto op) {
+        using Op = decltype(op);
+        if constexpr (std::is_same<Op, FineOp<T>>::value) {
+            Geom q = geom(lop.g, Op::kHeavy, ctx);
+            // rows per thread lowered until both LDS stages fit the tile bound
+            auto bytes = [&](int rpt) { return Jacobi2Stage::values(q.by * rpt) * sizeof(cplx<T>); };
+            while (q.rpt > 1 && bytes(q.rpt) > kMaxTileBytes) --q.rpt;
+            q.grid = level_grid(lop.g, q.rpt, ctx.nrhs, q.by, ctx.nrhs_cap > 1);
+            if (bytes(q.rpt) <= kMaxTileBytes) {
+                with_by(q.by, [&](auto byc) {
+                    constexpr int BY = decltype(byc)::value;
+                    hipLaunchKernelGGL((k_jacobi2<T, BY>), q.grid, q.block, bytes(q.rpt), ctx.stream, op, x, f, y,
+                                       T(inv_omega), HM_ACTIVE, q.rpt);
+                });
+                done = true;
+            }
+        }
+    });
+    return done;
+}
+
 double* region(const LaunchCtx& ctx, int r);
 
 template <typename T>
@@ -1677,6 +1788,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_apply<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>);                         \
     template void launch_residual<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>);              \
     template void launch_jacobi<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, double);        \
+    template bool launch_jacobi2<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, double);       \
     template int launch_restrict<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>, Vec<T>, Vec<T>);         \
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \

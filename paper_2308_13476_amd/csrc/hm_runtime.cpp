@@ -174,6 +174,9 @@ struct mg_ctx {
     // the restriction folded into the last pre-smoothing pass of GMRES cycles
     // (HELMG_FUSE_RESTRICT=0: always a pass of its own)
     int fuse_restrict = 1;
+    // weighted-Jacobi sweeps two per pass where the level allows it
+    // (HELMG_JACOBI_PAIRS=0: one per pass)
+    int jacobi_pairs = 1;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -495,19 +498,29 @@ struct CycleParams {
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
             int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false,
-            RestrictOut<T>* rout = nullptr) {
+            RestrictOut<T>* rout = nullptr, int jsteps = 1) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
     if (cp.smoother == MG_JACOBI) {
+        // jsteps = 2: two sweeps, in one pass where the level allows it
         if (pro.e.p) launch_prolong_add<T>(lc, pro.gc, lb.g, pro.transfer, pro.e, vec<T>(Prec<T>::u(lb), lb));
-        {
-            TimedScope ts(c, lc.stream, l == 0 ? 2 : -1, nodes);
+        auto swap_buffers = [&] {
+            std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
+            if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
+        };
+        TimedScope ts(c, lc.stream, l == 0 ? 2 : -1, nodes * jsteps);
+        if (jsteps == 2 && c->jacobi_pairs &&
+            launch_jacobi2<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
+                              vec<T>(Prec<T>::t_ref(lb), lb), 1.0 / cp.omega)) {
+            swap_buffers();
+            return;
+        }
+        for (int k = 0; k < jsteps; ++k) {
             launch_jacobi<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                              vec<T>(Prec<T>::t_ref(lb), lb), 1.0 / cp.omega);
+            swap_buffers();
         }
-        std::swap(Prec<T>::u_ref(lb), Prec<T>::t_ref(lb));
-        if (l == 0 && sizeof(T) == 8) c->cur_buf ^= 1;
         return;
     }
     // timing hook: the second fused orthogonalise + apply pass (launch 3 of
@@ -596,9 +609,11 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     // the last GMRES pre-smoothing step also forms the residual to restrict,
     // and restricts it itself where the handle fuses the two
     const bool fused = cp.smoother == MG_GMRES3 && cp.nu1 > 0;
-    for (int s = 0; s < cp.nu1; ++s)
+    // Jacobi sweeps go in pairs (one pass each where the level allows it)
+    auto jsteps = [&](int s, int nu) { return cp.smoother == MG_JACOBI && s + 1 < nu ? 2 : 1; };
+    for (int s = 0; s < cp.nu1; s += jsteps(s, cp.nu1))
         smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
-                  s == 0 && u_zero, fused && s == cp.nu1 - 1 ? &ro : nullptr);
+                  s == 0 && u_zero, fused && s == cp.nu1 - 1 ? &ro : nullptr, jsteps(s, cp.nu1));
     if (!fused)
         launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                            vec<T>(Prec<T>::w(lb), lb));
@@ -612,13 +627,13 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     const bool pro_fused = cp.smoother == MG_GMRES3 && cp.nu2 > 0;
     const Vec<T> e = vec<T>(Prec<T>::u(cb), cb);
     if (!pro_fused) launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, e, vec<T>(Prec<T>::u(lb), lb));
-    for (int s = 0; s < cp.nu2; ++s) {
+    for (int s = 0; s < cp.nu2; s += jsteps(s, cp.nu2)) {
         ProlongIn<T> pro{};
         if (pro_fused && s == 0) {
             const Vec<T> Z = vec<T>(Prec<T>::V(lb), lb);
             pro = ProlongIn<T>{cb.g, e, c->transfer, Vec<T>{Z.p + 3 * Z.plane, 4 * Z.plane}};
         }
-        smooth<T>(c, lc, l, cp, false, 0, pro);
+        smooth<T>(c, lc, l, cp, false, 0, pro, false, nullptr, jsteps(s, cp.nu2));
     }
 }
 
@@ -1100,6 +1115,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_JACOBI_PAIRS")) c->jacobi_pairs = std::atoi(e) != 0;
     // batch handles: fewer, larger tiles per right-hand side (the launch has
     // max_batch times as many blocks; larger tiles amortise each block's
     // fixed costs: reduction, tile halo, block sums)
@@ -2010,7 +2026,11 @@ mg_status level_op_run(mg_ctx* c, int kind, int level, const void* a, const void
             lc.active = c->active;
             const CycleParams cp{1, smoother, 0, 0, omega};
             const int saved = c->cur_buf;
-            for (int k = 0; k < nsteps; ++k) smooth<T>(c, lc, level, cp);
+            for (int k = 0; k < nsteps;) {
+                const int js = smoother == MG_JACOBI && k + 1 < nsteps ? 2 : 1;
+                smooth<T>(c, lc, level, cp, false, 0, ProlongIn<T>{}, false, nullptr, js);
+                k += js;
+            }
             c->cur_buf = saved;
             launch_copy_out<T>(lc, lb.g, V(Prec<T>::u(lb)), out, f32, false, false);
             break;

@@ -300,3 +300,43 @@ def test_fused_restriction_is_bit_identical(monkeypatch, transfer, n, cap):
     for cyc in ("V", "W"):
         for bits in (64, 32):
             assert np.array_equal(out["1", cyc, bits], out["0", cyc, bits]), (cyc, bits)
+
+
+@pytest.mark.parametrize("n,cap", [(128, None), (96, None), (256, "64")])
+def test_paired_jacobi_sweeps(monkeypatch, n, cap):
+    """Weighted-Jacobi sweeps on level 0 run two per pass (x staged for the
+    tile plus a halo of 2, the first sweep on the tile plus 1 in LDS): V(4,4) and
+    W(3,3) cycles, the odd count taking one pass of two and one single sweep,
+    match the oracle's cycle (FP64 within 1e-10, FP32 within 1e-4) and the
+    one-sweep-per-pass path to rounding; ragged tiles (96 intervals) and tall
+    tiles (block cap 64 on 256 intervals, rows lowered until both LDS stages
+    fit)."""
+    require_gpu()
+    import torch
+    from paper_2308_13476_amd.solver import Solver
+    if cap:
+        monkeypatch.setenv("HELMG_MAX_BLOCKS", cap)
+    k2 = W.random_k2(n, 14, 8.0, 20.0)
+    cn = 6 if n == 96 else 4
+    H = O.build_hierarchy(k2, 1.0 / n, 0.7, coarsest_n=cn)
+    u = _rand(n, 2, 150)
+    f = _rand(n, 2, 151)
+    out = {}
+    for pairs in ("1", "0"):
+        monkeypatch.setenv("HELMG_JACOBI_PAIRS", pairs)
+        S = Solver(to_gpu(k2), 1.0 / n, 0.7, max_batch=2, precision="fp32_refined", coarsest_n=cn)
+        for cyc, nu in (("V", 4), ("W", 3)):
+            out[pairs, cyc, 64] = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, smoother="jacobi", nu_pre=nu,
+                                                nu_post=nu))
+            out[pairs, cyc, 32] = to_np(S.cycle(to_gpu(u.astype(np.complex64)), to_gpu(f.astype(np.complex64)),
+                                                cycle=cyc, smoother="jacobi", nu_pre=nu, nu_post=nu,
+                                                precision="fp32_refined"))
+        del S
+        torch.cuda.synchronize()
+    for cyc, nu in (("V", 4), ("W", 3)):
+        opts = O.CycleOptions(gamma=1 if cyc == "V" else 2, smoother="jacobi", nu1=nu, nu2=nu)
+        for b in range(2):
+            ref = O.cycle(H, 0, u[b].ravel(), f[b].ravel(), opts)
+            assert rel(out["1", cyc, 64][b], ref) <= 1e-10, (cyc, b, rel(out["1", cyc, 64][b], ref))
+            assert rel(out["1", cyc, 32][b], ref) <= 1e-4, (cyc, b)
+            assert node_rel(out["1", cyc, 64][b], out["0", cyc, 64][b]) <= 1e-12, (cyc, b)
