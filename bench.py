@@ -47,19 +47,38 @@ CLASS1_FP64_BYTES_PER_NODE = 80.0
 CLASS1_FP32_VECTOR_BYTES = 36.0
 CLASS1_FP32_K2_BYTES = 4.0
 
-# HBM traffic of the class-1 kernel per launch from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE; profiles/ holds the summary and the commands), each
-# scaled by what the counter reads for a plain copy of known size. Valid only
-# for the kernel sources it was measured on: the hash below is of the files in
-# TRAFFIC_SOURCES, and a different hash reports traffic as null.
+# Traffic of the roofline kernel per launch from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE; profiles/ holds the summaries and the commands),
+# each scaled by what the counter reads for a plain copy of known size. These
+# counters see the bytes the L2 caches request from and write to the fabric
+# (Infinity Cache, then HBM): "L2->fabric" bytes, reported next to the
+# algorithmic bytes. Valid only for the kernel sources they were measured on:
+# the hash below is of the files in TRAFFIC_SOURCES, and a different hash
+# reports traffic as null.
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
-MEASURED_TRAFFIC = {  # per launch of k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024
-    "sources_sha256": "87701874b2647dd260eaeef8ef8ba2522a6d49bead98693274ae8c09dc91ac94",
-    "fetch_bytes": 50696268,  # FETCH_SIZE x 1.9998 (copy-calibrated)
-    "write_bytes": 12684816,  # WRITE_SIZE x 1.0000
-    "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md",
+MEASURED_TRAFFIC = {
+    "sources_sha256": "1b14a3341d29675af6de0292bd74c2f4f3802a33e01676cc61edd0f2dc8c4423",
+    # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
+    "mp2a": {"fetch_bytes": 32485242, "write_bytes": 12684816,
+             "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
+    # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
+    "beyond_cache": {"fetch_bytes": 370184667, "write_bytes": 100890288,
+                     "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
+    # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
+    "batch64": {"fetch_bytes": 908539520, "write_bytes": 198098198,
+                "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
+
+
+def measured_traffic(which):
+    """Fetch + write bytes per launch of the roofline kernel of workload
+    `which`, or None when the kernel sources changed since the counters were
+    taken."""
+    if MEASURED_TRAFFIC is None or MEASURED_TRAFFIC["sources_sha256"] != sources_sha256():
+        return None
+    m = MEASURED_TRAFFIC[which]
+    return m["fetch_bytes"] + m["write_bytes"]
 
 
 def sources_sha256():
@@ -115,6 +134,8 @@ def beyond_cache_roofline(steps):
     if r is not None:
         r["workload"] = (f"MP 2-A n={n} ({(n + 1) ** 2} unknowns), k={k:g}, FP64 GMRES(3) V(1,1), {steps} cycles; "
                          f"working set beyond the Infinity Cache")
+        r["traffic"] = measured_traffic("beyond_cache")
+        r["traffic_kind"] = "L2->fabric (HBM here: the working set exceeds the Infinity Cache)"
     return r
 
 
@@ -168,10 +189,15 @@ def batch_workloads(args):
         config = {"workload": "64 point sources at seeded interior nodes, n=512, k=100, shift 1/k, GMRES(3) V(1,1), "
                               "FP32-refined, tol 1e-6, one batched solve", "n": n, "k": k, "batch": 64}
         nb = 64
-        roof = lambda: class1_roofline(  # noqa: E731
-            S, lambda: S.solve(f, tol=1e-30, max_cycles=3, cycle="V", smoother="gmres", precision="fp32_refined"),
-            lambda nodes: CLASS1_FP32_VECTOR_BYTES * nodes + CLASS1_FP32_K2_BYTES * nodes / nb,
-            "level-0 GMRES(3) orthogonalise + apply pass (complex64), 64 right-hand sides per launch")
+        def roof():
+            r = class1_roofline(
+                S, lambda: S.solve(f, tol=1e-30, max_cycles=3, cycle="V", smoother="gmres", precision="fp32_refined"),
+                lambda nodes: CLASS1_FP32_VECTOR_BYTES * nodes + CLASS1_FP32_K2_BYTES * nodes / nb,
+                "level-0 GMRES(3) orthogonalise + apply pass (complex64), 64 right-hand sides per launch")
+            if r is not None:
+                r["traffic"] = measured_traffic("batch64")
+                r["traffic_kind"] = "L2->fabric"
+            return r
     else:
         order = np.random.default_rng(4).permutation(np.repeat([128, 256, 512, 1024], 8))
         solvers, rhs = [], []
@@ -533,11 +559,11 @@ def main():
         kc = KERNEL_CLASSES[args.kernel_class]
         avg_ms = kms / launches
         achieved = kc["bytes_per_node"] * knodes / (avg_ms * 1e-3) / 1e9
-        traffic = None
-        if MEASURED_TRAFFIC is not None and MEASURED_TRAFFIC["sources_sha256"] == sources_sha256():
-            traffic = MEASURED_TRAFFIC["fetch_bytes"] + MEASURED_TRAFFIC["write_bytes"]  # bytes per launch
+        traffic = measured_traffic("mp2a") if args.kernel_class == 1 else None  # bytes per launch
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kc["name"],
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_kind": "L2->fabric",
+                           "algorithmic_bytes_per_launch": kc["bytes_per_node"] * knodes / launches,
+                           "kernel": kc["name"],
                            "avg_launch_us": avg_ms * 1e3, "launches": launches,
                            "timed_in": "repeat of the timed steps; HIP start/stop events recorded by each "
                                        "launch's own dispatch (hipExtLaunchKernelGGL), no graphs"}
