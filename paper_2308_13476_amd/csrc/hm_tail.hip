@@ -153,105 +153,102 @@ __device__ bool tail_gmres(const TLv<T>& L, double breakdown, bool u_zero, cplx<
     double beta;
     with_radius(L, [&](auto Rc) {
         constexpr int R = decltype(Rc)::value;
-        double a1[1] = {0.0}, t1[1];
-        if (u_zero) {
-            tnodes(L, [&](int, int, int li, long long) { a1[0] += tn2(f[li]); });
-        } else {
-            tnodes(L, [&](int, int, int li, long long gp) {
-                const cplx<T> z = f[li] - tapply<T, R>(L, u, li, gp);
-                z0w[li] = z;
-                a1[0] += tn2(z);
-            });
+        // Each Arnoldi vector's norm is summed in the pass that applies A to
+        // it, together with that pass's inner products: one block sum per
+        // column (the values, and the order of every sum, are those of
+        // separate sums; a breakdown found there discards the apply).
+        if (!u_zero) {
+            tnodes(L, [&](int, int, int li, long long gp) { z0w[li] = f[li] - tapply<T, R>(L, u, li, gp); });
+            __syncthreads();
         }
-        block_sum<1>(a1, t1);
-        beta = sqrt(t1[0]);
+        // column 0: w = A z0; beta = ||z0||, H00 = s0^2 <z0, w>
+        double a3[3] = {0.0, 0.0, 0.0}, t3[3];
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z0, li, gp);
+            wa[li] = w;
+            a3[0] += tn2(z0[li]);
+            tdot(a3[1], a3[2], z0[li], w);
+        });
+        block_sum<3>(a3, t3);
+        beta = sqrt(t3[0]);
         if (!(beta > 0.0)) {
             k = 0;
             return;
         }
         s[0] = 1.0 / beta;
-        // column 0: w = A z0, H00 = s0^2 <z0, w>
-        double a2[2] = {0.0, 0.0}, t2[2];
-        tnodes(L, [&](int, int, int li, long long gp) {
-            const cplx<T> w = tapply<T, R>(L, z0, li, gp);
-            wa[li] = w;
-            tdot(a2[0], a2[1], z0[li], w);
-        });
-        block_sum<2>(a2, t2);
-        hr[0][0] = s[0] * s[0] * t2[0];
-        hi[0][0] = s[0] * s[0] * t2[1];
+        hr[0][0] = s[0] * s[0] * t3[1];
+        hi[0][0] = s[0] * s[0] * t3[2];
         // z1 = s0 w - H00 s0 z0
         {
             const cplx<T> c0 = {T(hr[0][0] * s[0]), T(hi[0][0] * s[0])};
             const T sc = T(s[0]);
-            a1[0] = 0.0;
             tnodes(L, [&](int, int, int li, long long) {
                 const cplx<T> zq = z0[li];
                 cplx<T> v = sc * wa[li];
                 v.re -= c0.re * zq.re - c0.im * zq.im;
                 v.im -= c0.re * zq.im + c0.im * zq.re;
                 z1[li] = v;
-                a1[0] += tn2(v);
             });
-            block_sum<1>(a1, t1);
+            __syncthreads();
         }
-        hr[1][0] = sqrt(t1[0]);
+        // column 1: w1 = A z1; ||z1||, <z0, w1>, <z1, w1>
+        double a5[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, t5[5];
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z1, li, gp);
+            wb[li] = w;
+            a5[0] += tn2(z1[li]);
+            tdot(a5[1], a5[2], z0[li], w);
+            tdot(a5[3], a5[4], z1[li], w);
+        });
+        block_sum<5>(a5, t5);
+        hr[1][0] = sqrt(t5[0]);
         hi[1][0] = 0.0;
         if (!(hr[1][0] > breakdown * beta)) {
             k = 1;
             return;
         }
         s[1] = 1.0 / hr[1][0];
-        // column 1
-        double a4[4] = {0.0, 0.0, 0.0, 0.0}, t4[4];
-        tnodes(L, [&](int, int, int li, long long gp) {
-            const cplx<T> w = tapply<T, R>(L, z1, li, gp);
-            wb[li] = w;
-            tdot(a4[0], a4[1], z0[li], w);
-            tdot(a4[2], a4[3], z1[li], w);
-        });
-        block_sum<4>(a4, t4);
         for (int q = 0; q < 2; ++q) {
-            hr[q][1] = s[q] * s[1] * t4[2 * q];
-            hi[q][1] = s[q] * s[1] * t4[2 * q + 1];
+            hr[q][1] = s[q] * s[1] * t5[1 + 2 * q];
+            hi[q][1] = s[q] * s[1] * t5[2 + 2 * q];
         }
         {
             const cplx<T> c0 = {T(hr[0][1] * s[0]), T(hi[0][1] * s[0])};
             const cplx<T> c1 = {T(hr[1][1] * s[1]), T(hi[1][1] * s[1])};
             const T sc = T(s[1]);
-            a1[0] = 0.0;
             tnodes(L, [&](int, int, int li, long long) {
                 const cplx<T> q0 = z0[li], q1 = z1[li];
                 cplx<T> v = sc * wb[li];
                 v.re -= c0.re * q0.re - c0.im * q0.im + c1.re * q1.re - c1.im * q1.im;
                 v.im -= c0.re * q0.im + c0.im * q0.re + c1.re * q1.im + c1.im * q1.re;
                 z2[li] = v;
-                a1[0] += tn2(v);
             });
-            block_sum<1>(a1, t1);
+            __syncthreads();
         }
-        hr[2][1] = sqrt(t1[0]);
+        // column 2: w2 = A z2; ||z2||, <z_i, w2>, ||w2||^2, and
+        // ||z_3||^2 = s_2^2 ||w2||^2 - sum |H[i][2]|^2 (orthonormal s_i z_i)
+        double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t8[8];
+        tnodes(L, [&](int, int, int li, long long gp) {
+            const cplx<T> w = tapply<T, R>(L, z2, li, gp);
+            if (res) z0w[li] = w;
+            a8[0] += tn2(z2[li]);
+            tdot(a8[1], a8[2], z0[li], w);
+            tdot(a8[3], a8[4], z1[li], w);
+            tdot(a8[5], a8[6], z2[li], w);
+            a8[7] += tn2(w);
+        });
+        block_sum<8>(a8, t8);
+        hr[2][1] = sqrt(t8[0]);
         hi[2][1] = 0.0;
         if (!(hr[2][1] > breakdown * beta)) {
             k = 2;
             return;
         }
         s[2] = 1.0 / hr[2][1];
-        // column 2; ||z_3||^2 = s_2^2 ||w||^2 - sum |H[i][2]|^2 (orthonormal s_i z_i)
-        double a7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, t7[7];
-        tnodes(L, [&](int, int, int li, long long gp) {
-            const cplx<T> w = tapply<T, R>(L, z2, li, gp);
-            if (res) z0w[li] = w;
-            tdot(a7[0], a7[1], z0[li], w);
-            tdot(a7[2], a7[3], z1[li], w);
-            tdot(a7[4], a7[5], z2[li], w);
-            a7[6] += tn2(w);
-        });
-        block_sum<7>(a7, t7);
-        double sq = s[2] * s[2] * t7[6];
+        double sq = s[2] * s[2] * t8[7];
         for (int q = 0; q < 3; ++q) {
-            hr[q][2] = s[q] * s[2] * t7[2 * q];
-            hi[q][2] = s[q] * s[2] * t7[2 * q + 1];
+            hr[q][2] = s[q] * s[2] * t8[1 + 2 * q];
+            hi[q][2] = s[q] * s[2] * t8[2 + 2 * q];
             sq -= hr[q][2] * hr[q][2] + hi[q][2] * hi[q][2];
         }
         hr[3][2] = sqrt(fmax(sq, 0.0));
