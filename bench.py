@@ -562,7 +562,7 @@ def main():
         traffic = measured_traffic("mp2a") if args.kernel_class == 1 else None  # bytes per launch
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_kind": "L2->fabric",
-                           "algorithmic_bytes_per_launch": kc["bytes_per_node"] * knodes / launches,
+                           "algorithmic_bytes_per_launch": kc["bytes_per_node"] * knodes,
                            "kernel": kc["name"],
                            "avg_launch_us": avg_ms * 1e3, "launches": launches,
                            "timed_in": "repeat of the timed steps; HIP start/stop events recorded by each "
