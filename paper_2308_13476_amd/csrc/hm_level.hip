@@ -1137,7 +1137,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_u_restrict(Grid gf, Grid gc, Ve
     const int fi0 = 2 * c0 - H, fj0 = 2 * r0 - H;  // fine node of LDS entry 0
     const int frows = RS::rows(BY * rpt);
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
-    constexpr int NB = sizeof(T) == 4 ? 8 : 2;  // 8: one batch less per block (4 and 12 measured slower)
+    constexpr int NB = sizeof(T) == 4 ? 8 : 4;  // measured: FP32 4, 12 and FP64 2 slower
     cplx<T> xu[NB], x0[NB], x1[NB], x2[NB], y0[NB], y1[NB], y2[NB];
     bool in[NB], own[NB];
     long long pp[NB];
