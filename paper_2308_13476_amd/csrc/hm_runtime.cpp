@@ -159,8 +159,9 @@ struct mg_ctx {
     // stencil), 2 in both, 0 never (default on batch handles)
     // (HELMG_L1_PRODUCT)
     int product_l1 = 1;
-    // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS);
-    // beyond it reductions are pre-reduced in a one-block pass
+    // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS;
+    // max(64, 640 / max_batch) on batch handles); beyond it reductions are
+    // pre-reduced in a one-block pass
     int block_cap = 640;
     // block heights: light kernels on grids of >= 256 intervals (4, 8, 16;
     // HELMG_TALL_BLOCKS) and every kernel on grids of <= 128 intervals (2 or 4;
