@@ -123,7 +123,9 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
 
 /* Rebuilds the hierarchy for a new k^2 field on the same grid (same workspace).
  * The field is checked as in mg_setup first; on MG_E_ARG the handle keeps its
- * previous hierarchy. */
+ * previous hierarchy. Returns once k2 has been copied (it may then be freed);
+ * the rebuild itself is enqueued on stream, ahead of the caller's later work
+ * there (work on other streams must wait for this stream). */
 mg_status mg_update_k2(mg_handle h, const double* k2, void* stream);
 
 /* Solves A_s x = W rhs for nrhs right-hand sides sharing the operator (§5).

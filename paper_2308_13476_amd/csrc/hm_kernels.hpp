@@ -107,14 +107,33 @@ int launch_restrict(const LaunchCtx&, Grid fine, Grid coarse, int transfer, Vec<
 template <typename T>
 void launch_prolong_add(const LaunchCtx&, Grid coarse, Grid fine, int transfer, Vec<T> e, Vec<T> u);
 
+// The update pass of a coarse level's last post-smoothing GMRES step, left to
+// the pass that reads its result (the coarse grid correction of the next finer
+// level): u = base + sum_i c_i z_i with base = uin (or u where uin.p is null)
+// and c_i from the step's state and the partial sums of its last Arnoldi pass,
+// as the update pass computes them. Z.p null: nothing is pending.
+template <typename T>
+struct DeferredUpdate {
+    Vec<T> Z{nullptr, 0};    // the step's Arnoldi planes (4 per right-hand side)
+    Vec<T> u{nullptr, 0};    // the coarse iterate
+    Vec<T> uin{nullptr, 0};  // the iterate the step started from, when not u
+    const GmState* st = nullptr;
+    const double* part = nullptr;  // partial sums of the last Arnoldi pass
+    int nblk = 0;
+    double breakdown = 0.0;
+};
+
 // A coarse grid correction to fold into the next smoothing step: u += P e with
-// e on the coarse grid gc; xt receives u + P e.
+// e on the coarse grid gc; xt receives u + P e. With du.Z.p set, e is the
+// pending update du of the coarse level's last smoothing step, formed on the
+// fly (e.p is then the coarse iterate that update would have written).
 template <typename T>
 struct ProlongIn {
     Grid gc{};
     Vec<T> e{nullptr, 0};
     int transfer = 0;
     Vec<T> xt{nullptr, 0};
+    DeferredUpdate<T> du{};
 };
 
 // The restriction to fold into the last pass of a pre-smoothing step (§3
@@ -152,12 +171,17 @@ struct RestrictOut {
 // reading u). rout (with res.p; may be null): the last pass restricts the
 // residual itself (unless ctx.fuse_restrict is 0) and res is not written;
 // rout->nblk is set to the partial-sum count of the coarse launch, or to 0
-// when the caller must restrict res itself.
+// when the caller must restrict res itself. defer (may be null; ignored with
+// res.p or u_zero): the update pass is not launched and *defer describes it,
+// for the caller to hand to the next finer level's correction (ProlongIn::du);
+// the step's Z, state and partial sums must then stay untouched until that
+// pass has run. Where the step has no plain update pass, defer->Z.p is null.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, const hipEvent_t* timed, Vec<T> res = Vec<T>{nullptr, 0},
                        int r_ready_nblk = 0,
-                       ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false, RestrictOut<T>* rout = nullptr);
+                       ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false, RestrictOut<T>* rout = nullptr,
+                       DeferredUpdate<T>* defer = nullptr);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>

@@ -687,6 +687,61 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r(Op op, Vec<T> u, Vec<T> f, Ve
     block_partials<1>(acc, pout + b * kPartStride);
 }
 
+// Pass 5 prologue: column 2 of H from pass 4's sums (unless the Arnoldi
+// process stopped early), the least-squares problem, and the update weights
+// c_i = y_i s_i (k = 0: nothing to add). H[3][2] = ||z_3|| for
+// z_3 = s_2 w_2 - sum_i H[i][2] s_i z_i comes from
+// ||z_3||^2 = s_2^2 ||w_2||^2 - sum_i |H[i][2]|^2 (the s_i z_i are orthonormal),
+// clamped at zero. Every thread reduces the sums and solves the small problem
+// in registers.
+template <typename T>
+__device__ __forceinline__ int gm_update_weights(const GmState* st, int b, double breakdown, const double* pin,
+                                                 int nblk_in, cplx<T> (&c)[3]) {
+    const GmState S = st[b];
+    double t[8];
+    reduce_partials<8>(pin + b * kPartStride, nblk_in, t);  // read in any case; used after a full Arnoldi pass
+    int k = S.k;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[q] = {T(0), T(0)};
+    if (k == 0) return 0;
+    double hr[4][3], hi[4][3], s[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            hr[a][cc] = S.hr[a][cc];
+            hi[a][cc] = S.hi[a][cc];
+        }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[q] = S.s[q];
+    if (!S.arnoldi_done) {
+        const double hn = sqrt(t[0]);
+        if (!(hn > breakdown * S.beta)) {
+            k = 2;
+        } else {
+            const double s2 = 1.0 / hn;
+            s[2] = s2;
+            hr[2][1] = hn;
+            hi[2][1] = 0.0;
+            double sq = s2 * s2 * t[7];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                hr[q][2] = s[q] * s2 * t[1 + 2 * q];
+                hi[q][2] = s[q] * s2 * t[2 + 2 * q];
+                sq -= hr[q][2] * hr[q][2] + hi[q][2] * hi[q][2];
+            }
+            hr[3][2] = sqrt(fmax(sq, 0.0));
+            hi[3][2] = 0.0;
+            k = 3;
+        }
+    }
+    double yr[3], yi[3];
+    gm_least_squares_regs(hr, hi, s, S.beta, k, yr, yi);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
+    return k;
+}
+
 // The coarse values that a fine tile with halo R reads through the §4
 // prolongation: coarse columns c0/2 - ceil(R/2) - 1 ... and rows likewise,
 // kept in LDS after the operator's own stages.
@@ -700,10 +755,14 @@ struct ProlongTile {
 // correction before it: x = u + P e on the block tile and its halo (zero
 // off the grid), x to xt (u stays as it was: neighbouring blocks read it),
 // z0 = f - A x, partials ||z0||^2. The pass that ends the step reads x from
-// xt and writes the updated iterate to u.
-template <typename Op, typename T, bool kBez, int BY>
+// xt and writes the updated iterate to u. kDefer: the coarse level's last
+// smoothing step left its update pass to this one, and e is formed at the
+// coarse nodes the block reads as that pass forms it (same weights, same
+// order of operations, so the same bits), e = base + sum_i c_i z_i.
+template <typename Op, typename T, bool kBez, int BY, bool kDefer>
 __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e, Vec<T> u, Vec<T> f, Vec<T> xt,
-                                                       Vec<T> Z, double* pout, const int* active, int rpt) {
+                                                       Vec<T> Z, double* pout, const int* active, int rpt,
+                                                       DeferredUpdate<T> du) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     constexpr int R = op_radius<Op>::value;
@@ -718,12 +777,73 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
     cplx<T>* E = lds + tile_bytes<Op, T>(BY, rpt) / sizeof(cplx<T>);
     const int C0 = (tl.c0 >> 1) - (R + 1) / 2 - 1, Q0 = (tl.r0 >> 1) - (R + 1) / 2 - 1;
     const int nc = gc.n, n = op.g.n;
-    {  // coarse e: ghosts (index -1, nc + 1) hold zero; beyond them a clamped read gives zero
+    // fine tile: x = u + P e on the grid, zero on the ghost frame
+    constexpr int FB = FillBatch<T>::value;
+    cplx<T> uv[FB];
+    auto fload = [&](int v, int q) {
+        const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
+        uv[v] = ub[op.g.at(min(max(i, 0), n), min(max(j, 0), n))];
+    };
+    auto fbody = [&](int v, int q) {
+        const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
+        cplx<T> x{T(0), T(0)};
+        if (i >= 0 && j >= 0 && i <= n && j <= n) {
+            T wx[3], wy[3];
+            taps<T>(i, kBez, wx);
+            taps<T>(j, kBez, wy);
+            const int base = ((j >> 1) - 1 - Q0) * PT::EW + (i >> 1) - 1 - C0;
+            x = uv[v];
+#pragma unroll
+            for (int ty = 0; ty < 3; ++ty) {
+                cplx<T> row{T(0), T(0)};
+#pragma unroll
+                for (int tx = 0; tx < 3; ++tx) {
+                    const cplx<T> c = E[base + ty * PT::EW + tx];
+                    row.re += wx[tx] * c.re;
+                    row.im += wx[tx] * c.im;
+                }
+                x.re += wy[ty] * row.re;
+                x.im += wy[ty] * row.im;
+            }
+        }
+        lds[q] = x;
+    };
+    const int ecount = PT::EW * PT::rows(tl.rows);
+    if constexpr (kDefer) {  // coarse e from the pending update; zero off the grid
+        cplx<T> c[3];
+        const int k = gm_update_weights<T>(du.st, b, du.breakdown, du.part, du.nblk, c);
+        const cplx<T>* bb = du.uin.p ? du.uin.rhs(b) : du.u.rhs(b);
+        const cplx<T>* zc0 = du.Z.p + (long long)(b * 4) * du.Z.plane;
+        const cplx<T>* zc1 = zc0 + du.Z.plane;
+        const cplx<T>* zc2 = zc1 + du.Z.plane;
+        constexpr int EB = 4;
+        cplx<T> xu[EB], x0[EB], x1[EB], x2[EB];
+        bool ok[EB];
+        for_strided_batched<EB>(
+            ecount,
+            [&](int v, int q) {
+                const int I = C0 + q % PT::EW, J = Q0 + q / PT::EW;
+                const int Ic = min(max(I, 0), nc), Jc = min(max(J, 0), nc);
+                ok[v] = I == Ic && J == Jc;
+                const long long p = gc.at(Ic, Jc);
+                xu[v] = bb[p];
+                x0[v] = zc0[p];
+                x1[v] = zc1[p];
+                x2[v] = zc2[p];
+            },
+            [&](int v, int q) {
+                cplx<T> x = xu[v];
+                if (k > 0) x = cfma(x, c[0], x0[v]);
+                if (k > 1) x = cfma(x, c[1], x1[v]);
+                if (k > 2) x = cfma(x, c[2], x2[v]);
+                E[q] = ok[v] ? x : cplx<T>{T(0), T(0)};
+            });
+    } else {  // coarse e: ghosts (index -1, nc + 1) hold zero; beyond them a clamped read gives zero
         constexpr int EB = 8;
         cplx<T> ev[EB];
         bool ok[EB];
         for_strided_batched<EB>(
-            PT::EW * PT::rows(tl.rows),
+            ecount,
             [&](int v, int q) {
                 const int I = C0 + q % PT::EW, J = Q0 + q / PT::EW;
                 const int Ic = min(max(I, -1), nc + 1), Jc = min(max(J, -1), nc + 1);
@@ -733,40 +853,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
             [&](int v, int q) { E[q] = ok[v] ? ev[v] : cplx<T>{T(0), T(0)}; });
     }
     __syncthreads();
-    {  // fine tile: x = u + P e on the grid, zero on the ghost frame
-        constexpr int FB = FillBatch<T>::value;
-        cplx<T> uv[FB];
-        for_strided_batched<FB>(
-            tl.count(),
-            [&](int v, int q) {
-                const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
-                uv[v] = ub[op.g.at(min(max(i, 0), n), min(max(j, 0), n))];
-            },
-            [&](int v, int q) {
-                const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
-                cplx<T> x{T(0), T(0)};
-                if (i >= 0 && j >= 0 && i <= n && j <= n) {
-                    T wx[3], wy[3];
-                    taps<T>(i, kBez, wx);
-                    taps<T>(j, kBez, wy);
-                    const int base = ((j >> 1) - 1 - Q0) * PT::EW + (i >> 1) - 1 - C0;
-                    x = uv[v];
-#pragma unroll
-                    for (int ty = 0; ty < 3; ++ty) {
-                        cplx<T> row{T(0), T(0)};
-#pragma unroll
-                        for (int tx = 0; tx < 3; ++tx) {
-                            const cplx<T> c = E[base + ty * PT::EW + tx];
-                            row.re += wx[tx] * c.re;
-                            row.im += wx[tx] * c.im;
-                        }
-                        x.re += wy[ty] * row.re;
-                        x.im += wy[ty] * row.im;
-                    }
-                }
-                lds[q] = x;
-            });
-    }
+    for_strided_batched<FB>(tl.count(), fload, fbody);
     __syncthreads();
     double acc[1] = {0.0};
     apply_from_tile<Op, T>(op, rpt, tl, lds, [fb](long long q) { return fb[q]; },
@@ -937,61 +1024,6 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
         if constexpr (J == 2) acc[KOUT - 1] += dnorm2(w);
     });
     block_partials<KOUT, kX>(acc, pout + b * kPartStride);
-}
-
-// Pass 5 prologue: column 2 of H from pass 4's sums (unless the Arnoldi
-// process stopped early), the least-squares problem, and the update weights
-// c_i = y_i s_i (k = 0: nothing to add). H[3][2] = ||z_3|| for
-// z_3 = s_2 w_2 - sum_i H[i][2] s_i z_i comes from
-// ||z_3||^2 = s_2^2 ||w_2||^2 - sum_i |H[i][2]|^2 (the s_i z_i are orthonormal),
-// clamped at zero. Every thread reduces the sums and solves the small problem
-// in registers.
-template <typename T>
-__device__ __forceinline__ int gm_update_weights(const GmState* st, int b, double breakdown, const double* pin,
-                                                 int nblk_in, cplx<T> (&c)[3]) {
-    const GmState S = st[b];
-    double t[8];
-    reduce_partials<8>(pin + b * kPartStride, nblk_in, t);  // read in any case; used after a full Arnoldi pass
-    int k = S.k;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = {T(0), T(0)};
-    if (k == 0) return 0;
-    double hr[4][3], hi[4][3], s[3];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-            hr[a][cc] = S.hr[a][cc];
-            hi[a][cc] = S.hi[a][cc];
-        }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) s[q] = S.s[q];
-    if (!S.arnoldi_done) {
-        const double hn = sqrt(t[0]);
-        if (!(hn > breakdown * S.beta)) {
-            k = 2;
-        } else {
-            const double s2 = 1.0 / hn;
-            s[2] = s2;
-            hr[2][1] = hn;
-            hi[2][1] = 0.0;
-            double sq = s2 * s2 * t[7];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                hr[q][2] = s[q] * s2 * t[1 + 2 * q];
-                hi[q][2] = s[q] * s2 * t[2 + 2 * q];
-                sq -= hr[q][2] * hr[q][2] + hi[q][2] * hi[q][2];
-            }
-            hr[3][2] = sqrt(fmax(sq, 0.0));
-            hi[3][2] = 0.0;
-            k = 3;
-        }
-    }
-    double yr[3], yi[3];
-    gm_least_squares_regs(hr, hi, s, S.beta, k, yr, yi);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) c[q] = {T(yr[q]), T(yi[q])};
-    return k;
 }
 
 // Pass 5: u += sum y_i s_i z_i.
@@ -1544,6 +1576,14 @@ double* region(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r
 // right-hand side are pre-reduced before their consumers.
 constexpr int kBatchPrereduceBlocks = 32;
 
+// The pending update pass of a coarse level's last smoothing step, launched
+// on its own (where the correction that would form it on the fly does not fit).
+template <typename T>
+void launch_deferred_update(const LaunchCtx& ctx, Grid gc, const DeferredUpdate<T>& du) {
+    const Geom qv = geom(gc, false, ctx);
+    HM_LAUNCH(qv, (k_gm_u<T, BY>), gc, du.Z, du.u, du.uin, du.st, du.breakdown, du.part, du.nblk, HM_ACTIVE, qv.rpt);
+}
+
 // Level grids of at most this many blocks per right-hand side are resident
 // on the GPU at once when solved alone (256 compute units, several blocks each).
 constexpr int kOverlapMaxBlocks = 2048;
@@ -1551,9 +1591,11 @@ constexpr int kOverlapMaxBlocks = 2048;
 template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
-                       Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero, RestrictOut<T>* rout) {
+                       Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero, RestrictOut<T>* rout,
+                       DeferredUpdate<T>* defer) {
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
+    if (defer) *defer = DeferredUpdate<T>{};
     const Geom qv = geom(lop.g, false, ctx);  // vector-only passes
     int nb_op = 0;
     Vec<T> uin{nullptr, 0};  // iterate the update pass starts from, when not u itself
@@ -1580,16 +1622,23 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         const size_t pro_bytes = tile_bytes<Op, T>(q.by, q.rpt) +
                                  size_t(ProlongTile<R>::EW) * ProlongTile<R>::rows(q.by * q.rpt) * sizeof(cplx<T>);
         const bool fuse_pro = pro.e.p && ctx.fuse_correction && pro_bytes <= kMaxTileBytes;
-        if (pro.e.p && !fuse_pro) launch_prolong_add<T>(ctx, pro.gc, lop.g, pro.transfer, pro.e, u);
+        const DeferredUpdate<T>& du = pro.du;
+        if (pro.e.p && !fuse_pro) {
+            if (du.Z.p) launch_deferred_update<T>(ctx, pro.gc, du);
+            launch_prolong_add<T>(ctx, pro.gc, lop.g, pro.transfer, pro.e, u);
+        }
         if (fuse_pro) {
             with_by<Op::kHeavy>(q.by, [&](auto byc) {
                 constexpr int BY = decltype(byc)::value;
-                if (pro.transfer == 0)
-                    hipLaunchKernelGGL((k_gm_r_pro<Op, T, true, BY>), q.grid, q.block, pro_bytes, ctx.stream, op,
-                                       pro.gc, pro.e, u, f, pro.xt, Z, A, HM_ACTIVE, q.rpt);
-                else
-                    hipLaunchKernelGGL((k_gm_r_pro<Op, T, false, BY>), q.grid, q.block, pro_bytes, ctx.stream, op,
-                                       pro.gc, pro.e, u, f, pro.xt, Z, A, HM_ACTIVE, q.rpt);
+                auto go = [&](auto kern) {
+                    hipLaunchKernelGGL(kern, q.grid, q.block, pro_bytes, ctx.stream, op, pro.gc, pro.e, u, f, pro.xt,
+                                       Z, A, HM_ACTIVE, q.rpt, du);
+                };
+                const bool d = du.Z.p != nullptr;
+                if (pro.transfer == 0 && d) go(k_gm_r_pro<Op, T, true, BY, true>);
+                else if (pro.transfer == 0) go(k_gm_r_pro<Op, T, true, BY, false>);
+                else if (d) go(k_gm_r_pro<Op, T, false, BY, true>);
+                else go(k_gm_r_pro<Op, T, false, BY, false>);
             });
             prereduce(A, std::integral_constant<int, 1>{});
             uin = pro.xt;
@@ -1681,7 +1730,9 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
                   qv.rpt);
     else if (u_zero)
         HM_LAUNCH(qv, (k_gm_u<T, BY, true>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
-    else if (!res.p)
+    else if (defer)
+        *defer = DeferredUpdate<T>{Z, u, uin, st, B, nb_op, breakdown};
+    else
         HM_LAUNCH(qv, (k_gm_u<T, BY>), lop.g, Z, u, uin, st, breakdown, B, nb_op, HM_ACTIVE, qv.rpt);
 }
 
@@ -1793,7 +1844,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
                                        Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>,                     \
-                                       int, ProlongIn<T>, bool, RestrictOut<T>*);                               \
+                                       int, ProlongIn<T>, bool, RestrictOut<T>*, DeferredUpdate<T>*);           \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

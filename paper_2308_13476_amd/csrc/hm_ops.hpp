@@ -68,7 +68,16 @@ struct FineOp {
 };
 
 // Levels >= 1: stored Galerkin stencil (§3) of radius R, one complex plane per
-// offset; ghost coefficients are zero.
+// offset; ghost coefficients are zero. A Galerkin operator R C P with
+// R = P^T / 4 (§4) and a complex symmetric C (the scaled operator W A and its
+// shifted form differ from their transposes in no entry) is complex
+// symmetric: the coefficient of offset d at node p equals that of offset -d
+// at node p + d, up to the rounding of the product that formed them. Passes
+// read the offsets of the upper half (dy > 0, or dy = 0 and dx >= 0) at p and
+// those of the lower half from the upper-half plane at p + d, so that only
+// the upper half of the planes is streamed from memory (the mirrored reads
+// are the neighbouring nodes' own coefficients, found in cache); the operator
+// applied is then exactly symmetric.
 template <typename T, int R>
 struct StencilOp {
     static constexpr bool kHeavy = R >= 2;  // 25/49-point stencils: many registers, short blocks
@@ -76,14 +85,19 @@ struct StencilOp {
     const cplx<T>* __restrict__ coef;
     static constexpr int D = 2 * R + 1;
     __device__ __forceinline__ cplx<T> diag(int, int, long long p) const { return coef[(R * D + R) * g.plane + p]; }
+    // coefficient of offset (dx, dy) at node p (dx, dy compile-time after unrolling)
+    __device__ __forceinline__ cplx<T> at(int dy, int dx, long long p) const {
+        const bool lower = dy < 0 || (dy == 0 && dx < 0);
+        return lower ? coef[((R - dy) * D + R - dx) * g.plane + p + (long long)dy * g.pitch + dx]
+                     : coef[((dy + R) * D + dx + R) * g.plane + p];
+    }
     template <typename X>
     __device__ __forceinline__ cplx<T> apply_at(const X& x, int, int, long long p) const {
         cplx<T> y{T(0), T(0)};
 #pragma unroll
         for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
-            for (int dx = -R; dx <= R; ++dx)
-                y = cfma(y, coef[((dy + R) * D + dx + R) * g.plane + p], x(p + (long long)dy * g.pitch + dx));
+            for (int dx = -R; dx <= R; ++dx) y = cfma(y, at(dy, dx, p), x(p + (long long)dy * g.pitch + dx));
         return y;
     }
     __device__ __forceinline__ cplx<T> apply(const cplx<T>* __restrict__ x, int i, int j, long long p) const {
@@ -312,14 +326,13 @@ __device__ __forceinline__ bool fill_tile_mid(cplx<T>* lds, const Tile<R>& t, co
 // Stencil of radius R applied at node p whose tile index is li, values from LDS.
 template <typename T, int R>
 __device__ __forceinline__ cplx<T> apply_tile(const StencilOp<T, R>& op, const cplx<T>* lds, int li, long long p) {
-    constexpr int D = 2 * R + 1;
     constexpr int TW = Tile<R>::TW;
     cplx<T> y{T(0), T(0)};
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx)
-            y = cfma(y, op.coef[((dy + R) * D + dx + R) * op.g.plane + p], lds[li + dy * TW + dx]);
+            y = cfma(y, op.at(dy, dx, p), lds[li + dy * TW + dx]);
     return y;
 }
 

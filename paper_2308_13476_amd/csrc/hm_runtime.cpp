@@ -154,11 +154,10 @@ struct mg_ctx {
     int tail_level[2] = {-1, -1};
     int tail_n = 16;
     // level 1 applied as R C_s P from level-0 data instead of its stored
-    // stencil: 1 in FP32 cycles (default on handles for one right-hand side;
-    // measured faster there, while FP64 cycles are faster with the stored
-    // stencil), 2 in both, 0 never (default on batch handles)
+    // stencil: 1 in FP32 cycles, 2 in both, 0 never (default: the stored
+    // stencil, read as its upper half, is faster in both precisions)
     // (HELMG_L1_PRODUCT)
-    int product_l1 = 1;
+    int product_l1 = 0;
     // blocks per right-hand side that a level grid aims at (HELMG_MAX_BLOCKS;
     // max(64, 640 / max_batch) on batch handles); beyond it reductions are
     // pre-reduced in a one-block pass
@@ -178,6 +177,10 @@ struct mg_ctx {
     // weighted-Jacobi sweeps two per pass where the level allows it
     // (HELMG_JACOBI_PAIRS=0: one per pass)
     int jacobi_pairs = 1;
+    // the update pass of a coarse level's last post-smoothing GMRES step is
+    // formed by the next finer level's correction pass instead of launched
+    // (HELMG_DEFER_UPDATE=0: always launched)
+    int defer_update = 1;
     // which of u64 / t64 holds the level-0 FP64 iterate of each right-hand side
     int cur_buf = 0;
     std::vector<int> final_buf;
@@ -495,11 +498,12 @@ struct CycleParams {
 // One smoothing step on level l. With then_residual (GMRES only), the step's
 // last pass also forms the residual f - A u of the updated iterate into the
 // level's w buffer. u_zero (GMRES): the step starts from u = 0, which u does
-// not hold.
+// not hold. defer (GMRES; may be null): the step's update pass is left to the
+// caller, as launch_gmres_step describes.
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
             int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false,
-            RestrictOut<T>* rout = nullptr, int jsteps = 1) {
+            RestrictOut<T>* rout = nullptr, int jsteps = 1, DeferredUpdate<T>* defer = nullptr) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -535,7 +539,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, tev[1] ? tev : nullptr,
-                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero, rout);
+                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero, rout, defer);
     if (tev[1]) {
         c->ev_pending.push_back({tev[0], tev[1]});
         c->t_nodes += nodes;
@@ -583,9 +587,12 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
 // on level 0 of an FP32 cycle, the FP64 residual pass before it) also formed
 // the first GMRES residual. u_zero: u itself does not hold those zeros.
 // first_visit: level l was entered by the restriction that zeroed its u.
+// defer (may be null): the update pass of the last post-smoothing step is left
+// to the caller's coarse grid correction (*defer describes it; defer->Z.p is
+// null where no update is pending and u holds the result).
 template <typename T>
 void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false,
-           bool first_visit = false) {
+           bool first_visit = false, DeferredUpdate<T>* defer = nullptr) {
     if (l == c->tail_level[sizeof(T) == 4]) {
         launch_tail_from<T>(c, lc, l, cp, first_visit);
         return;
@@ -621,20 +628,33 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     const int nb_r = ro.nblk > 0 ? ro.nblk
                                  : launch_restrict<T>(lc, lb.g, cb.g, c->transfer, vec<T>(Prec<T>::w(lb), lb),
                                                       ro.fc, ro.uc, ro.zc);
-    for (int g = 0; g < cp.gamma; ++g) cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0, false, g == 0);
     // the coarse grid correction u += P e is formed by the first pass of the
     // first post-smoothing GMRES step, into the fourth Arnoldi plane (unused
-    // by the step's own passes)
+    // by the step's own passes); on handles for one right-hand side that pass
+    // also forms e itself from the pending update of the coarse level's last
+    // visit (earlier visits of a W-cycle write their iterate, from which the
+    // next visit starts), except on a level-1 product operator. Measured per
+    // level at n = 1024: the update pass it replaces costs 5-9 us, the
+    // correction pass grows by 3-6 us (the weights' reduction and
+    // least-squares solve move onto its critical path), by 13 us on the
+    // product operator; batch launches were slower with it.
     const bool pro_fused = cp.smoother == MG_GMRES3 && cp.nu2 > 0;
+    const bool defer_coarse =
+        pro_fused && c->defer_update && lc.nrhs_cap == 1 && !(l == 1 && level_op<T>(c, 1).product);
+    DeferredUpdate<T> du{};
+    for (int g = 0; g < cp.gamma; ++g)
+        cycle<T>(c, lc, l + 1, cp, g == 0 && r_in_restrict ? nb_r : 0, false, g == 0,
+                 defer_coarse && g + 1 == cp.gamma ? &du : nullptr);
     const Vec<T> e = vec<T>(Prec<T>::u(cb), cb);
     if (!pro_fused) launch_prolong_add<T>(lc, cb.g, lb.g, c->transfer, e, vec<T>(Prec<T>::u(lb), lb));
     for (int s = 0; s < cp.nu2; s += jsteps(s, cp.nu2)) {
         ProlongIn<T> pro{};
         if (pro_fused && s == 0) {
             const Vec<T> Z = vec<T>(Prec<T>::V(lb), lb);
-            pro = ProlongIn<T>{cb.g, e, c->transfer, Vec<T>{Z.p + 3 * Z.plane, 4 * Z.plane}};
+            pro = ProlongIn<T>{cb.g, e, c->transfer, Vec<T>{Z.p + 3 * Z.plane, 4 * Z.plane}, du};
         }
-        smooth<T>(c, lc, l, cp, false, 0, pro, false, nullptr, jsteps(s, cp.nu2));
+        const bool last = s + jsteps(s, cp.nu2) >= cp.nu2;
+        smooth<T>(c, lc, l, cp, false, 0, pro, false, nullptr, jsteps(s, cp.nu2), last ? defer : nullptr);
     }
 }
 
@@ -674,9 +694,11 @@ mg_status check_k2(mg_ctx* c, const double* k2, hipStream_t s, std::string* why)
     return MG_E_ARG;
 }
 
-mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s) {
+// input_read (may be null) is recorded once the caller's k2 has been copied.
+mg_status build_hierarchy(mg_ctx* c, const double* k2, hipStream_t s, hipEvent_t input_read = nullptr) {
     const Grid g0 = c->lv[0].g;
     launch_k2_in(s, g0, k2, c->k2_64, c->k2_32);
+    if (input_read) HM_HIP(hipEventRecord(input_read, s));
     for (int l = 0; l + 1 < c->L; ++l) {
         const LevelBuf& f = c->lv[l];
         LevelBuf& cc = c->lv[l + 1];
@@ -1109,14 +1131,11 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
         c->tall_rows = (v == 8 || v == 16) ? v : 4;
     }
     if (const char* e = std::getenv("HELMG_SMALL_ROWS")) c->small_rows = std::atoi(e) == 4 ? 4 : 2;
-    // batch handles: level 1 applies its stored stencil in both precisions (its
-    // coefficient planes are read once per XCD for all right-hand sides, which
-    // the product's fine-grid stages, recomputed per right-hand side, cannot match)
-    if (max_batch > 1) c->product_l1 = 0;
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_JACOBI_PAIRS")) c->jacobi_pairs = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_DEFER_UPDATE")) c->defer_update = std::atoi(e) != 0;
     // batch handles: fewer, larger tiles per right-hand side (the launch has
     // max_batch times as many blocks; larger tiles amortise each block's
     // fixed costs: reduction, tile halo, block sums)
@@ -1200,8 +1219,11 @@ mg_status mg_update_k2(mg_handle c, const double* k2, void* stream) {
             return st;
         }
     }
-    if (mg_status st = build_hierarchy(c, k2, s)) return st;
-    HM_HIP(hipStreamSynchronize(s));
+    // returns once the caller's k2 has been copied; the Galerkin products and
+    // the coarsest factorisation stay queued on the stream ahead of the
+    // caller's next work (an event slot of the solve loop, idle between calls)
+    if (mg_status st = build_hierarchy(c, k2, s, c->cycle_done[0])) return st;
+    HM_HIP(hipEventSynchronize(c->cycle_done[0]));
     return MG_OK;
 }
 

@@ -206,16 +206,16 @@ def test_one_cycle_tail_setting(monkeypatch, tail_n, cyc, smoother):
     assert rel(got32[0], ref) <= 1e-4, rel(got32[0], ref)
 
 
-@pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "0"},
+@pytest.mark.parametrize("env", [{"HELMG_MAX_BLOCKS": "64"}, {"HELMG_L1_PRODUCT": "1"},
                                  {"HELMG_L1_PRODUCT": "2", "HELMG_MAX_BLOCKS": "200"},
                                  {"HELMG_FUSE_CORRECTION": "0"}, {"HELMG_FUSE_RESTRICT": "0"}],
-                         ids=["block_cap_64", "stored_level1", "product_level1_fp64", "unfused_correction",
+                         ids=["block_cap_64", "product_level1_fp32", "product_level1_fp64", "unfused_correction",
                               "unfused_restriction"])
-def test_cycle_with_prereduction_and_stored_level1(monkeypatch, env):
+def test_cycle_with_prereduction_and_level1_operators(monkeypatch, env):
     """With a block cap of 64 every GMRES reduction goes through the one-block
-    pre-reduction pass; HELMG_L1_PRODUCT=0 makes level 1 apply its stored
-    Galerkin stencil in both precisions, =2 the product R C_s P in both (FP32
-    cycles use the product by default, FP64 cycles the stored stencil);
+    pre-reduction pass; HELMG_L1_PRODUCT=1 makes FP32 cycles apply level 1 as
+    the product R C_s P from level-0 data, =2 both precisions (by default both
+    apply the stored Galerkin stencil, read as its upper half);
     HELMG_FUSE_CORRECTION=0 runs the coarse grid correction as a pass of its
     own instead of inside the first post-smoothing pass, HELMG_FUSE_RESTRICT=0
     the restriction instead of inside the last pre-smoothing pass. Each
@@ -300,6 +300,48 @@ def test_fused_restriction_is_bit_identical(monkeypatch, transfer, n, cap):
     for cyc in ("V", "W"):
         for bits in (64, 32):
             assert np.array_equal(out["1", cyc, bits], out["0", cyc, bits]), (cyc, bits)
+
+
+@pytest.mark.parametrize("transfer", ["bezier", "linear"])
+@pytest.mark.parametrize("n,env", [(128, {}), (256, {"HELMG_MAX_BLOCKS": "64"}), (96, {}),
+                                   (128, {"HELMG_FUSE_CORRECTION": "0"}), (128, {"HELMG_TAIL_N": "0"}),
+                                   (128, {"HELMG_L1_PRODUCT": "1"})],
+                         ids=["n128", "n256_cap64", "n96", "n128_unfused_correction", "n128_no_tail",
+                              "n128_product_level1"])
+def test_deferred_coarse_update_is_bit_identical(monkeypatch, transfer, n, env):
+    """The update pass of a coarse level's last post-smoothing step, formed by
+    the next finer level's correction pass at the coarse nodes it reads (or
+    launched just before a correction pass that does not fuse), gives the bits
+    of the launched update pass: V and W cycles with one and two
+    post-smoothing steps, FP64 and FP32 (a level-1 product operator takes no
+    pending update, while level 0 takes level 1's), both transfers, ragged
+    tiles (96 intervals), pre-reduced partial sums (block cap 64), and a
+    hierarchy launched down to its coarsest level (no tail). Handles for one
+    right-hand side (those for batches launch every update pass)."""
+    require_gpu()
+    import torch
+    from paper_2308_13476_amd.solver import Solver
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    k2 = to_gpu(W.random_k2(n, 16, 10.0, 30.0))
+    u = _rand(n, 1, 170)
+    f = _rand(n, 1, 171)
+    runs = [("V", 1, 1), ("W", 1, 2), ("V", 2, 2)]
+    out = {}
+    for defer in ("1", "0"):
+        monkeypatch.setenv("HELMG_DEFER_UPDATE", defer)
+        S = Solver(k2, 1.0 / n, 0.2, transfer=transfer, max_batch=1, precision="fp32_refined",
+                   coarsest_n=6 if n == 96 else 4)
+        for cyc, nu1, nu2 in runs:
+            out[defer, cyc, nu2, 64] = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, nu_pre=nu1, nu_post=nu2))
+            out[defer, cyc, nu2, 32] = to_np(S.cycle(to_gpu(u.astype(np.complex64)),
+                                                     to_gpu(f.astype(np.complex64)), cycle=cyc, nu_pre=nu1,
+                                                     nu_post=nu2, precision="fp32_refined"))
+        del S
+        torch.cuda.synchronize()
+    for cyc, _, nu2 in runs:
+        for bits in (64, 32):
+            assert np.array_equal(out["1", cyc, nu2, bits], out["0", cyc, nu2, bits]), (cyc, nu2, bits)
 
 
 @pytest.mark.parametrize("n,cap", [(128, None), (96, None), (256, "64")])
