@@ -1,5 +1,6 @@
 """Pins of the Galerkin coarse operators on the shifted Laplacian (paper §3, §4)."""
 import numpy as np
+import pytest
 from scipy.signal import convolve2d
 
 import oracle as O
@@ -45,14 +46,20 @@ def _radius(A, nl):
     return max(np.abs(I1 - I2).max(), np.abs(J1 - J2).max())
 
 
-def test_stencil_radius_and_symmetry():
+@pytest.mark.parametrize("transfer,radii", [("bezier", [1, 2, 3, 3, 3]), ("linear", [1, 1, 1, 1, 1])])
+def test_stencil_radius_and_symmetry(transfer, radii):
+    """Every level operator is complex symmetric (A = A^T, not Hermitian): A_s = W A
+    and its shifted form are, and R = P^T / 4 keeps it through R C P. The stencil
+    passes read the lower half of each stored stencil from the mirrored
+    neighbour's upper half on the strength of this."""
     n = 64
     k2 = W.random_k2(n, 4, 10.0, 30.0)
-    H = O.build_hierarchy(k2, 1.0 / n, 0.05)
-    assert [_radius(A, nl) for A, nl in zip(H.A, H.n)] == [1, 2, 3, 3, 3]
+    H = O.build_hierarchy(k2, 1.0 / n, 0.05, transfer=transfer)
+    assert [_radius(A, nl) for A, nl in zip(H.A, H.n)] == radii
     for A in H.A:
         scale = abs(A).max()
         assert abs(A - A.T).max() <= 1e-14 * scale
+        assert abs(A - A.conj().T).max() > 1e-3 * scale  # symmetric, not Hermitian
 
 
 def test_shift_enters_only_through_the_first_coarsening():
