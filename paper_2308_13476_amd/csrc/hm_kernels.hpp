@@ -57,6 +57,7 @@ struct LaunchCtx {
     int block_cap;      // blocks per right-hand side a level grid aims at (reductions)
     int fuse_correction = 1;  // 0: the coarse grid correction always runs as its own pass
     int fuse_restrict = 1;    // 0: the restriction always runs as its own pass
+    int fuse_r_a0 = 1;        // 0: on level 0 (FP32) the first apply pass of a post-smoothing step runs on its own
     StopTest stop{};          // taken by the residual-norm pass when stop.ring is set
     int tall_rows = 4;        // block height of light kernels on grids of >= 256 intervals (4, 8, 16)
     int small_rows = 2;       // block height on grids of <= 128 intervals (2 or 4)

@@ -2,6 +2,7 @@
 // Jacobi, transfers, GMRES(3) passes, norms, FP32 refinement, adjoint gradient.
 #include <cstdlib>
 #include <type_traits>
+#include <utility>
 
 #include <hip/hip_ext.h>
 
@@ -751,38 +752,25 @@ struct ProlongTile {
     __host__ __device__ static int rows(int fine_rows) { return (fine_rows - 1 + R) / 2 + (R + 1) / 2 + 3; }
 };
 
-// Pass 1 of the first post-smoothing step fused with the coarse grid
-// correction before it: x = u + P e on the block tile and its halo (zero
-// off the grid), x to xt (u stays as it was: neighbouring blocks read it),
-// z0 = f - A x, partials ||z0||^2. The pass that ends the step reads x from
-// xt and writes the updated iterate to u. kDefer: the coarse level's last
+// x = u + P e for the fine tile tl and its halo of R nodes (zero off the grid)
+// into X, the coarse values the tile reads staged in E first (coarse grid
+// correction of §3 with the §4 prolongation). kDefer: the coarse level's last
 // smoothing step left its update pass to this one, and e is formed at the
 // coarse nodes the block reads as that pass forms it (same weights, same
-// order of operations, so the same bits), e = base + sum_i c_i z_i.
-template <typename Op, typename T, bool kBez, int BY, bool kDefer>
-__global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e, Vec<T> u, Vec<T> f, Vec<T> xt,
-                                                       Vec<T> Z, double* pout, const int* active, int rpt,
-                                                       DeferredUpdate<T> du) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
-    constexpr int R = op_radius<Op>::value;
+// order of operations, so the same bits), e = base + sum_i c_i z_i. Ends with
+// a barrier.
+template <typename T, bool kBez, int R, bool kDefer>
+__device__ __forceinline__ void stage_corrected_tile(const Tile<R>& tl, const Grid& g, const Grid& gc,
+                                                     const cplx<T>* eb, const cplx<T>* ub,
+                                                     const DeferredUpdate<T>& du, int b, cplx<T>* X, cplx<T>* E) {
     using PT = ProlongTile<R>;
-    const cplx<T>* eb = e.rhs(b);
-    const cplx<T>* ub = u.rhs(b);
-    const cplx<T>* fb = f.rhs(b);
-    cplx<T>* xb = xt.rhs(b);
-    cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
-    const Tile<R> tl = block_tile<R>(rpt);
-    cplx<T>* E = lds + tile_bytes<Op, T>(BY, rpt) / sizeof(cplx<T>);
     const int C0 = (tl.c0 >> 1) - (R + 1) / 2 - 1, Q0 = (tl.r0 >> 1) - (R + 1) / 2 - 1;
-    const int nc = gc.n, n = op.g.n;
-    // fine tile: x = u + P e on the grid, zero on the ghost frame
+    const int nc = gc.n, n = g.n;
     constexpr int FB = FillBatch<T>::value;
     cplx<T> uv[FB];
     auto fload = [&](int v, int q) {
         const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
-        uv[v] = ub[op.g.at(min(max(i, 0), n), min(max(j, 0), n))];
+        uv[v] = ub[g.at(min(max(i, 0), n), min(max(j, 0), n))];
     };
     auto fbody = [&](int v, int q) {
         const int i = tl.c0 - R + q % Tile<R>::TW, j = tl.r0 - R + q / Tile<R>::TW;
@@ -806,7 +794,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
                 x.im += wy[ty] * row.im;
             }
         }
-        lds[q] = x;
+        X[q] = x;
     };
     const int ecount = PT::EW * PT::rows(tl.rows);
     if constexpr (kDefer) {  // coarse e from the pending update; zero off the grid
@@ -855,6 +843,27 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
     __syncthreads();
     for_strided_batched<FB>(tl.count(), fload, fbody);
     __syncthreads();
+}
+
+// Pass 1 of the first post-smoothing step fused with the coarse grid
+// correction before it: x = u + P e on the block tile and its halo (zero
+// off the grid), x to xt (u stays as it was: neighbouring blocks read it),
+// z0 = f - A x, partials ||z0||^2. The pass that ends the step reads x from
+// xt and writes the updated iterate to u. kDefer: see stage_corrected_tile.
+template <typename Op, typename T, bool kBez, int BY, bool kDefer>
+__global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e, Vec<T> u, Vec<T> f, Vec<T> xt,
+                                                       Vec<T> Z, double* pout, const int* active, int rpt,
+                                                       DeferredUpdate<T> du) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    constexpr int R = op_radius<Op>::value;
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* xb = xt.rhs(b);
+    cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<R> tl = block_tile<R>(rpt);
+    cplx<T>* E = lds + tile_bytes<Op, T>(BY, rpt) / sizeof(cplx<T>);
+    stage_corrected_tile<T, kBez, R, kDefer>(tl, op.g, gc, e.rhs(b), u.rhs(b), du, b, lds, E);
     double acc[1] = {0.0};
     apply_from_tile<Op, T>(op, rpt, tl, lds, [fb](long long q) { return fb[q]; },
                            [&](int, int, long long p, cplx<T> fp, cplx<T> x, cplx<T> ax) {
@@ -864,6 +873,137 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_r_pro(Op op, Grid gc, Vec<T> e,
                                acc[0] += dnorm2(z);
                            });
     block_partials<1>(acc, pout + b * kPartStride);
+}
+
+// Level 0: the first post-smoothing pass (k_gm_r_pro) and the apply pass
+// after it (k_gm_a0) in one. x = u + P e is staged for the tile and a halo of
+// 2, z0 = f - A x for the tile and a halo of 1 (the halo ring evaluated as the
+// block owning each ring node evaluates it, with or without the interior form
+// of the operator, so that the values equal the ones that block stores), then
+// w0 = A z0 on the tile from LDS. The owned nodes are visited in the thread
+// order of the two separate passes, so the partial sums ||z0||^2 and
+// <z0, w0> (three per block) are those passes' bit for bit; the next pass
+// (k_gm_oa<1, kInit>) takes over the state set-up of k_gm_a0.
+template <typename T>
+struct ResApplyStage {
+    static constexpr int kXW = Tile<2>::TW;  // x: tile and a halo of 2
+    static constexpr int kZW = Tile<1>::TW;  // z0: tile and a halo of 1
+    __host__ __device__ static size_t bytes(int rows) {
+        return (size_t(kXW) * (rows + 4) + size_t(kZW) * (rows + 2) +
+                size_t(ProlongTile<2>::EW) * ProlongTile<2>::rows(rows)) *
+               sizeof(cplx<T>);
+    }
+};
+
+template <typename T, bool kBez, int BY, bool kDefer>
+__global__ __launch_bounds__(kBX * BY) void k_gm_r_pro_a0(FineOp<T> op, Grid gc, Vec<T> e, Vec<T> u, Vec<T> f,
+                                                          Vec<T> xt, Vec<T> Z, Vec<T> Wout, double* pout,
+                                                          const int* active, int rpt, DeferredUpdate<T> du) {
+    using RA = ResApplyStage<T>;
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    const cplx<T>* fb = f.rhs(b);
+    cplx<T>* xb = xt.rhs(b);
+    cplx<T>* z0 = Z.p + (long long)(b * 4) * Z.plane;
+    cplx<T>* wb = Wout.rhs(b);
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(hm_dyn_lds);
+    const Tile<2> tx = block_tile<2>(rpt);
+    const Tile<1> tz{tx.c0, tx.r0, tx.rows};
+    cplx<T>* X = lds;
+    cplx<T>* ZL = X + RA::kXW * (tx.rows + 4);
+    cplx<T>* E = ZL + RA::kZW * (tx.rows + 2);
+    stage_corrected_tile<T, kBez, 2, kDefer>(tx, op.g, gc, e.rhs(b), u.rhs(b), du, b, X, E);
+    const int n = op.g.n;
+    constexpr int XW = RA::kXW, ZW = RA::kZW;
+    // operator at fine node (i, j) from X, in the form the tile owning (i, j) uses
+    const int trows = int(blockDim.y) * rpt;
+    auto owner_interior = [&](int i, int j) {
+        const int oc = (i / kBX) * kBX, orow = (j / trows) * trows;
+        return oc >= 1 && oc + kBX <= n && orow >= 1 && orow + trows <= n;
+    };
+    auto ax_at = [&](int i, int j, T kk, bool inner) {
+        const int l = tx.at(i, j);
+        return inner ? op.apply5k_interior(kk, X[l], X[l - 1], X[l + 1], X[l - XW], X[l + XW])
+                     : op.apply5k(i, j, kk, X[l], X[l - 1], X[l + 1], X[l - XW], X[l + XW]);
+    };
+    // z0 on the halo ring of the tile (top and bottom rows, then the left and
+    // right columns): each thread's first ring node has its operands loaded
+    // together with those of its tile nodes (one memory round trip), further
+    // ones (blocks of two wavefronts) after them
+    const int ring = 2 * ZW + 2 * tx.rows;
+    auto ring_node = [&](int q, int& i, int& j) {
+        if (q < 2 * ZW) {
+            i = tx.c0 - 1 + q % ZW;
+            j = q < ZW ? tx.r0 - 1 : tx.r0 + tx.rows;
+        } else {
+            const int m = q - 2 * ZW;
+            i = (m & 1) ? tx.c0 + kBX : tx.c0 - 1;
+            j = tx.r0 + (m >> 1);
+        }
+    };
+    auto ring_z = [&](int i, int j, T kk, cplx<T> fp) {
+        cplx<T> z{T(0), T(0)};
+        if (i >= 0 && j >= 0 && i <= n && j <= n) z = fp - ax_at(i, j, kk, owner_interior(i, j));
+        ZL[tz.at(i, j)] = z;
+    };
+    const int tid = thread_linear(), nt = int(blockDim.x * blockDim.y);
+    int ri = 0, rj = 0;
+    T rk = T(0);
+    cplx<T> rf{T(0), T(0)};
+    if (tid < ring) {
+        ring_node(tid, ri, rj);
+        const long long p = op.g.at(min(max(ri, 0), n), min(max(rj, 0), n));
+        rk = op.k2[p];
+        rf = fb[p];
+    }
+    // z0 on the tile, in the thread order of the residual pass; each thread
+    // first zeroes its own tile positions, so that those off the grid (which
+    // the loop skips) read as zero
+    for (int rr = 0; rr < rpt; ++rr)
+        ZL[tz.at(tx.c0 + int(threadIdx.x), tx.r0 + rr * int(blockDim.y) + int(threadIdx.y))] = cplx<T>{T(0), T(0)};
+    const bool interior = tx.c0 >= 1 && tx.c0 + kBX <= n && tx.r0 >= 1 && tx.r0 + tx.rows <= n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    constexpr int NB = sizeof(T) == 4 ? 8 : 4;
+    {
+        cplx<T> pv[NB];
+        T kk[NB];
+        for_nodes_batched<NB>(
+            op.g, rpt,
+            [&](int v, long long p) {
+                pv[v] = fb[p];
+                kk[v] = op.k2[p];
+            },
+            [&](int v, int i, int j, long long p) {
+                const cplx<T> z = pv[v] - ax_at(i, j, kk[v], interior);
+                xb[p] = X[tx.at(i, j)];
+                z0[p] = z;
+                ZL[tz.at(i, j)] = z;
+                acc[0] += dnorm2(z);
+            });
+    }
+    if (tid < ring) ring_z(ri, rj, rk, rf);
+    for (int q = tid + nt; q < ring; q += nt) {
+        int i, j;
+        ring_node(q, i, j);
+        const long long p = op.g.at(min(max(i, 0), n), min(max(j, 0), n));
+        ring_z(i, j, op.k2[p], fb[p]);
+    }
+    __syncthreads();
+    {  // w0 = A z0 on the tile from LDS, in the thread order of the apply pass
+        T kk[NB];
+        for_nodes_batched<NB>(
+            op.g, rpt, [&](int v, long long p) { kk[v] = op.k2[p]; },
+            [&](int v, int i, int j, long long p) {
+                const int l = tz.at(i, j);
+                const cplx<T> zp = ZL[l];
+                const cplx<T> w =
+                    interior ? op.apply5k_interior(kk[v], zp, ZL[l - 1], ZL[l + 1], ZL[l - ZW], ZL[l + ZW])
+                             : op.apply5k(i, j, kk[v], zp, ZL[l - 1], ZL[l + 1], ZL[l - ZW], ZL[l + ZW]);
+                wb[p] = w;
+                acc_dot(acc[1], acc[2], zp, w);
+            });
+    }
+    block_partials<3>(acc, pout + b * kPartStride);
 }
 
 // Pass 2: beta = ||z0|| from pass 1; w0 = A z0 (unnormalised); partials <z0, w0>.
@@ -915,16 +1055,20 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_a0(Op op, Vec<T> Z, Vec<T> Wout
 // last pre-smoothing step forms its residual from it). The raw tile values
 // (w_{J-1}, z_0 .. z_{J-1}) of the first batch are loaded together with the
 // previous pass's partial sums and combined once the reduction has given the
-// coefficients.
-template <typename Op, typename T, int J, int BY, bool kOv>
+// coefficients. kInit (J = 1): the previous pass was k_gm_r_pro_a0, whose
+// partial sums start with ||z_0||^2, and this pass sets up the step's state
+// (beta, s_0, k) as k_gm_a0 does.
+template <typename Op, typename T, int J, int BY, bool kOv, bool kInit = false>
 __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win, Vec<T> Wout, GmState* st,
                                                     double breakdown, const double* pin, int nblk_in, double* pout,
                                                     const int* active, int rpt) {
+    static_assert(!kInit || J == 1, "the state set-up belongs to the first orthogonalise pass");
     const int b = blockIdx.z;
     const bool act = rhs_active(active, b);
-    const int done = st[b].arnoldi_done;
-    const double s0 = st[b].s[0], beta0 = st[b].beta;
-    constexpr int KIN = (J == 1) ? 2 : 5;  // previous pass: [||z_{J-1}||^2 (J > 1)], <z_i, w_{J-1}>
+    const int done = kInit ? 0 : st[b].arnoldi_done;
+    double s0 = kInit ? 0.0 : st[b].s[0], beta0 = kInit ? 0.0 : st[b].beta;
+    // previous pass: [||z_{J-1}||^2 (J > 1, or kInit)], <z_i, w_{J-1}>
+    constexpr int KIN = kInit ? 3 : (J == 1) ? 2 : 5;
     const cplx<T>* z[J];
 #pragma unroll
     for (int q = 0; q < J; ++q) z[q] = Z.p + (long long)(b * 4 + q) * Z.plane;
@@ -936,7 +1080,21 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
     cplx<T> c[J];
     // the block leaves after the reduction if there is nothing to do (uniform in the block)
     auto mid = [&](const double (&t)[KIN]) -> bool {
-        if (!act || done) return false;
+        if (!act) return false;
+        if constexpr (kInit) {  // as k_gm_a0: beta = ||z_0||, nothing to do for a zero residual
+            beta0 = sqrt(t[0]);
+            const bool go = beta0 > 0.0;
+            s0 = go ? 1.0 / beta0 : 0.0;
+            if (lead_thread()) {
+                GmState& S = st[b];
+                S.beta = beta0;
+                S.s[0] = s0;
+                S.k = go ? 3 : 0;
+                S.arnoldi_done = go ? 0 : 1;
+            }
+            if (!go) return false;
+        }
+        if (done) return false;
         double sv[J];  // s_0 .. s_{J-1}
         sv[0] = s0;
         double hn = 0.0;
@@ -946,7 +1104,7 @@ __global__ __launch_bounds__(kBX * BY) void k_gm_oa(Op op, Vec<T> Z, Vec<T> Win,
             broke = !(hn > breakdown * beta0);
             sv[J - 1] = broke ? 0.0 : 1.0 / hn;
         }
-        constexpr int D0 = (J > 1) ? 1 : 0;  // offset of the inner products in t
+        constexpr int D0 = (J > 1 || kInit) ? 1 : 0;  // offset of the inner products in t
         double hr[J], hi[J];
 #pragma unroll
         for (int q = 0; q < J; ++q) {
@@ -1593,6 +1751,8 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
                        Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero, RestrictOut<T>* rout,
                        DeferredUpdate<T>* defer) {
+    // partial sums: each pass reads the region its producer wrote and writes the
+    // other one (blocks of a pass still read while others write)
     double* A = region(ctx, 0);
     double* B = region(ctx, 1);
     if (defer) *defer = DeferredUpdate<T>{};
@@ -1627,20 +1787,46 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             if (du.Z.p) launch_deferred_update<T>(ctx, pro.gc, du);
             launch_prolong_add<T>(ctx, pro.gc, lop.g, pro.transfer, pro.e, u);
         }
+        bool r_a0 = false;  // the correction pass also applied A to z_0 (partials: ||z_0||^2, <z_0, w_0>)
         if (fuse_pro) {
-            with_by<Op::kHeavy>(q.by, [&](auto byc) {
-                constexpr int BY = decltype(byc)::value;
-                auto go = [&](auto kern) {
-                    hipLaunchKernelGGL(kern, q.grid, q.block, pro_bytes, ctx.stream, op, pro.gc, pro.e, u, f, pro.xt,
-                                       Z, A, HM_ACTIVE, q.rpt, du);
-                };
-                const bool d = du.Z.p != nullptr;
-                if (pro.transfer == 0 && d) go(k_gm_r_pro<Op, T, true, BY, true>);
-                else if (pro.transfer == 0) go(k_gm_r_pro<Op, T, true, BY, false>);
-                else if (d) go(k_gm_r_pro<Op, T, false, BY, true>);
-                else go(k_gm_r_pro<Op, T, false, BY, false>);
-            });
-            prereduce(A, std::integral_constant<int, 1>{});
+            const bool d = du.Z.p != nullptr;
+            if constexpr (std::is_same<Op, FineOp<T>>::value && sizeof(T) == 4) {
+                const size_t ra_bytes = ResApplyStage<T>::bytes(q.by * q.rpt);
+                if (ctx.fuse_r_a0 && !rout && ra_bytes <= kMaxTileBytes) {
+                    with_by(q.by, [&](auto byc) {
+                        constexpr int BY = decltype(byc)::value;
+                        auto go = [&](auto kern) {
+                            hipLaunchKernelGGL(kern, q.grid, q.block, ra_bytes, ctx.stream, op, pro.gc, pro.e, u, f,
+                                               pro.xt, Z, Wa, A, HM_ACTIVE, q.rpt, du);
+                        };
+                        if (pro.transfer == 0 && d) go(k_gm_r_pro_a0<T, true, BY, true>);
+                        else if (pro.transfer == 0) go(k_gm_r_pro_a0<T, true, BY, false>);
+                        else if (d) go(k_gm_r_pro_a0<T, false, BY, true>);
+                        else go(k_gm_r_pro_a0<T, false, BY, false>);
+                    });
+                    prereduce(A, std::integral_constant<int, 3>{});
+                    // region 1 may hold the pending coarse update's sums, which the
+                    // pass reads, so it wrote region 0; the step's later passes
+                    // run with the two regions swapped (its last sums, which the
+                    // update pass reads, end in region 0)
+                    std::swap(A, B);
+                    r_a0 = true;
+                }
+            }
+            if (!r_a0) {
+                with_by<Op::kHeavy>(q.by, [&](auto byc) {
+                    constexpr int BY = decltype(byc)::value;
+                    auto go = [&](auto kern) {
+                        hipLaunchKernelGGL(kern, q.grid, q.block, pro_bytes, ctx.stream, op, pro.gc, pro.e, u, f,
+                                           pro.xt, Z, A, HM_ACTIVE, q.rpt, du);
+                    };
+                    if (pro.transfer == 0 && d) go(k_gm_r_pro<Op, T, true, BY, true>);
+                    else if (pro.transfer == 0) go(k_gm_r_pro<Op, T, true, BY, false>);
+                    else if (d) go(k_gm_r_pro<Op, T, false, BY, true>);
+                    else go(k_gm_r_pro<Op, T, false, BY, false>);
+                });
+                prereduce(A, std::integral_constant<int, 1>{});
+            }
             uin = pro.xt;
         } else if (r_ready_nblk > 0) {
             // u = 0: z_0 = f and its partial norms were written by the restriction
@@ -1662,11 +1848,20 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         // handle, not the call, so a batch member runs the same code as a solo
         // solve on the same handle and matches it bit for bit.
         const bool ov = ctx.nrhs_cap == 1 && q.nblk <= kOverlapMaxBlocks;
-        if (ov) HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, true>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
-        else HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, false>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
-        prereduce(B, std::integral_constant<int, 2>{});
-        if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
-        else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE, q.rpt);
+        if (r_a0) {
+            if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
+                                 HM_ACTIVE, q.rpt);
+            else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
+                              HM_ACTIVE, q.rpt);
+        } else {
+            if (ov) HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, true>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
+            else HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, false>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
+            prereduce(B, std::integral_constant<int, 2>{});
+            if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE,
+                                 q.rpt);
+            else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false>), op, Z, Wa, Wb, st, breakdown, B, nb, A, HM_ACTIVE,
+                              q.rpt);
+        }
         prereduce(A, std::integral_constant<int, 5>{});
         // w_2 is kept (in the fourth Arnoldi plane, w_0 stays in Wa) only for a
         // residual by recurrence

@@ -174,6 +174,10 @@ struct mg_ctx {
     // the restriction folded into the last pre-smoothing pass of GMRES cycles
     // (HELMG_FUSE_RESTRICT=0: always a pass of its own)
     int fuse_restrict = 1;
+    // on level 0 of FP32 cycles the first apply pass of the post-smoothing
+    // step is folded into the correction pass before it (HELMG_FUSE_R_A0=0:
+    // a pass of its own)
+    int fuse_r_a0 = 1;
     // weighted-Jacobi sweeps two per pass where the level allows it
     // (HELMG_JACOBI_PAIRS=0: one per pass)
     int jacobi_pairs = 1;
@@ -333,6 +337,7 @@ Vec<T> vec(cplx<T>* p, const LevelBuf& lb) { return Vec<T>{p, lb.g.plane}; }
 LaunchCtx launch_ctx(mg_ctx* c, hipStream_t s, int nrhs) {
     LaunchCtx lc{s, nrhs, c->active, c->partials, c->max_batch, c->block_cap, c->fuse_correction};
     lc.fuse_restrict = c->fuse_restrict;
+    lc.fuse_r_a0 = c->fuse_r_a0;
     lc.tall_rows = c->tall_rows;
     lc.small_rows = c->small_rows;
     return lc;
@@ -1134,6 +1139,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (const char* e = std::getenv("HELMG_L1_PRODUCT")) c->product_l1 = std::atoi(e);
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_FUSE_R_A0")) c->fuse_r_a0 = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_JACOBI_PAIRS")) c->jacobi_pairs = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_DEFER_UPDATE")) c->defer_update = std::atoi(e) != 0;
     // batch handles: fewer, larger tiles per right-hand side (the launch has

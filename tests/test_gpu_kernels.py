@@ -344,6 +344,55 @@ def test_deferred_coarse_update_is_bit_identical(monkeypatch, transfer, n, env):
             assert np.array_equal(out["1", cyc, nu2, bits], out["0", cyc, nu2, bits]), (cyc, nu2, bits)
 
 
+@pytest.mark.parametrize("transfer", ["bezier", "linear"])
+@pytest.mark.parametrize("n,env,nb", [(128, {}, 1), (96, {}, 1), (256, {"HELMG_MAX_BLOCKS": "64"}, 1), (128, {}, 2),
+                                      (128, {"HELMG_DEFER_UPDATE": "0"}, 1)],
+                         ids=["n128", "n96", "n256_cap64", "n128_batch2", "n128_no_deferral"])
+def test_fused_correction_and_apply(monkeypatch, transfer, n, env, nb):
+    """Level 0 of an FP32 cycle: the first post-smoothing pass that also applies
+    A to the residual it forms (x staged with a halo of 2, z0 with a halo of 1,
+    the ring evaluated as its owning tiles evaluate it) agrees with the
+    correction pass followed by the apply pass to FP32 rounding (the same
+    expressions, contracted into fused multiply-adds differently by the two
+    kernels: within 1e-5 of the largest value at every node after a cycle), and
+    both with the oracle's FP64 cycle within 1e-4 (5e-4 on 256 intervals, where
+    the separate passes differ from it by 1.4e-4 in FP32): V and W cycles with one and
+    two post-smoothing steps, both transfers, ragged tiles (96 intervals),
+    pre-reduced partial sums (block cap 64), a batch handle, and without the
+    deferred coarse update."""
+    require_gpu()
+    import torch
+    from paper_2308_13476_amd.solver import Solver
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    k2 = W.random_k2(n, 17, 10.0, 30.0)
+    cn = 6 if n == 96 else 4
+    H = O.build_hierarchy(k2, 1.0 / n, 0.2, transfer=transfer, coarsest_n=cn)
+    u = _rand(n, nb, 180).astype(np.complex64)
+    f = _rand(n, nb, 181).astype(np.complex64)
+    runs = [("V", 1, 1), ("W", 1, 2), ("V", 2, 2)]
+    out = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("HELMG_FUSE_R_A0", fuse)
+        S = Solver(to_gpu(k2), 1.0 / n, 0.2, transfer=transfer, max_batch=nb, precision="fp32_refined",
+                   coarsest_n=cn)
+        for cyc, nu1, nu2 in runs:
+            out[fuse, cyc, nu2] = to_np(S.cycle(to_gpu(u), to_gpu(f), cycle=cyc, nu_pre=nu1, nu_post=nu2,
+                                                precision="fp32_refined"))
+        del S
+        torch.cuda.synchronize()
+    for cyc, nu1, nu2 in runs:
+        opts = O.CycleOptions(gamma=1 if cyc == "V" else 2, smoother="gmres", nu1=nu1, nu2=nu2)
+        for r in range(nb):
+            a, b = out["1", cyc, nu2][r], out["0", cyc, nu2][r]
+            d = node_rel(a, b)
+            print(f"{cyc}({nu1},{nu2}) rhs {r}: fused vs separate passes, largest node difference {d:.2e}")
+            assert d <= 1e-5, (cyc, nu2, r, d)
+            ref = O.cycle(H, 0, u[r].astype(np.complex128).ravel(), f[r].astype(np.complex128).ravel(), opts)
+            tol = 1e-4 if n <= 128 else 5e-4
+            assert rel(a, ref) <= tol and rel(b, ref) <= tol, (cyc, nu2, r, rel(a, ref), rel(b, ref))
+
+
 @pytest.mark.parametrize("n,cap", [(128, None), (96, None), (256, "64")])
 def test_paired_jacobi_sweeps(monkeypatch, n, cap):
     """Weighted-Jacobi sweeps on level 0 run two per pass (x staged for the
