@@ -58,15 +58,15 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "fc88e5ef96041f8e7e06709b0f84d9c2d1eab53e6cb3a689f6f13c8a3a6ec247",
+    "sources_sha256": "b74a61bd6346de4c12c18c35894ab56ce143b99ade59c2a2a1759b14517ef4c0",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
-    "mp2a": {"fetch_bytes": 32559505, "write_bytes": 12684816,
+    "mp2a": {"fetch_bytes": 32549787, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
     # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
-    "beyond_cache": {"fetch_bytes": 369882063, "write_bytes": 100890533,
+    "beyond_cache": {"fetch_bytes": 369931924, "write_bytes": 100890533,
                      "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
     # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
-    "batch64": {"fetch_bytes": 908529452, "write_bytes": 198098199,
+    "batch64": {"fetch_bytes": 908657600, "write_bytes": 198098193,
                 "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
 
