@@ -58,15 +58,15 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "b74a61bd6346de4c12c18c35894ab56ce143b99ade59c2a2a1759b14517ef4c0",
+    "sources_sha256": "3be1791dcdf0955efc82f2c5774ea7568feeeb0bd5b89382eb0ecb8ee94596d5",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
-    "mp2a": {"fetch_bytes": 32549787, "write_bytes": 12684816,
+    "mp2a": {"fetch_bytes": 32544203, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
     # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
-    "beyond_cache": {"fetch_bytes": 369931924, "write_bytes": 100890533,
+    "beyond_cache": {"fetch_bytes": 369834776, "write_bytes": 100890789,
                      "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
     # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
-    "batch64": {"fetch_bytes": 908657600, "write_bytes": 198098193,
+    "batch64": {"fetch_bytes": 908659597, "write_bytes": 198098217,
                 "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
 

@@ -1848,11 +1848,13 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         // handle, not the call, so a batch member runs the same code as a solo
         // solve on the same handle and matches it bit for bit.
         const bool ov = ctx.nrhs_cap == 1 && q.nblk <= kOverlapMaxBlocks;
-        if (r_a0) {
-            if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
-                                 HM_ACTIVE, q.rpt);
-            else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
-                              HM_ACTIVE, q.rpt);
+        if (r_a0) {  // only the level-0 operator of FP32 cycles takes this branch
+            if constexpr (std::is_same<Op, FineOp<T>>::value && sizeof(T) == 4) {
+                if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
+                                     HM_ACTIVE, q.rpt);
+                else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
+                                  HM_ACTIVE, q.rpt);
+            }
         } else {
             if (ov) HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, true>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
             else HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, false>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);

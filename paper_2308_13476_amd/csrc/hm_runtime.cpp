@@ -178,6 +178,9 @@ struct mg_ctx {
     // step is folded into the correction pass before it (HELMG_FUSE_R_A0=0:
     // a pass of its own)
     int fuse_r_a0 = 1;
+    // HELMG_LOG=1: one line per right-hand side and cycle on stderr (relative
+    // residual, contraction, stop decision) as the host reads the reports
+    int log = 0;
     // weighted-Jacobi sweeps two per pass where the level allows it
     // (HELMG_JACOBI_PAIRS=0: one per pass)
     int jacobi_pairs = 1;
@@ -936,6 +939,10 @@ struct SolveRun {
             rel[b] = r;
             cycles[b] = it;
             if (stats && stats->history) stats->history[(size_t)(it - 1) * nrhs + b] = r;
+            if (c->log)
+                std::fprintf(stderr, "helmg: handle %p rhs %d cycle %d relres %.6e contraction %.4f%s\n",
+                             static_cast<void*>(c), b, it, r, rel_prev[b] > 0.0 ? r / rel_prev[b] : 0.0,
+                             rep.stop == 1 ? " converged" : rep.stop == 2 ? " diverged" : "");
             if (rep.stop) {
                 state[b] = rep.stop;
                 c->h_active[b] = 0;
@@ -1140,6 +1147,7 @@ mg_status mg_setup(const double* k2, int n, double h, double shift, int levels, 
     if (const char* e = std::getenv("HELMG_FUSE_CORRECTION")) c->fuse_correction = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_RESTRICT")) c->fuse_restrict = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_FUSE_R_A0")) c->fuse_r_a0 = std::atoi(e) != 0;
+    if (const char* e = std::getenv("HELMG_LOG")) c->log = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_JACOBI_PAIRS")) c->jacobi_pairs = std::atoi(e) != 0;
     if (const char* e = std::getenv("HELMG_DEFER_UPDATE")) c->defer_update = std::atoi(e) != 0;
     // batch handles: fewer, larger tiles per right-hand side (the launch has

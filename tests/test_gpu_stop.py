@@ -72,3 +72,25 @@ def test_batch_members_stopped_before_the_first_cycle(precision):
     xs, alone = S.solve(to_gpu(f0), tol=1e-8, precision=precision)
     assert alone["status"] == 0 and alone["cycles"][0] == info["cycles"][0]
     assert torch.equal(x[0:1], xs)
+
+
+def test_per_cycle_log(monkeypatch, capfd):
+    """HELMG_LOG=1 (read at set-up) prints one line per right-hand side and
+    cycle as the host reads the stop-test reports: the relative residuals of
+    the solve's history, in order, the last one marked converged."""
+    require_gpu()
+    from paper_2308_13476_amd.solver import Solver
+    monkeypatch.setenv("HELMG_LOG", "1")
+    n, k = 64, 20.0
+    S = Solver(to_gpu(W.constant_k2(n, k)), 1.0 / n, 1.0 / k)
+    capfd.readouterr()
+    x, info = S.solve(to_gpu(W.point_source_rhs(n, [W.center_node(n)])), tol=1e-6, history=True)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("helmg: ")]
+    assert info["status"] == 0
+    assert len(lines) == info["cycles"][0], err[-2000:]
+    for c, (ln, r) in enumerate(zip(lines, info["history"][0]), start=1):
+        fields = ln.split()
+        assert fields[fields.index("cycle") + 1] == str(c)
+        assert float(fields[fields.index("relres") + 1]) == pytest.approx(r, rel=1e-6)
+    assert lines[-1].endswith("converged") and not any(ln.endswith("converged") for ln in lines[:-1])
