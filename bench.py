@@ -58,7 +58,7 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3be1791dcdf0955efc82f2c5774ea7568feeeb0bd5b89382eb0ecb8ee94596d5",
+    "sources_sha256": "cffafca8fd52040a25738401c7e81f804d080d4e79035643391c813864d10c71",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
     "mp2a": {"fetch_bytes": 32544203, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},

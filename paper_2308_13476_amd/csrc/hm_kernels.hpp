@@ -164,7 +164,9 @@ struct RestrictOut {
 // step begins with the coarse grid correction u += P e (coarse level pro.gc),
 // formed on the fly by the first pass, which keeps u + P e in pro.xt; the last
 // pass then writes the updated iterate to u (the step never changes the
-// roles of u and pro.xt). r_ready_nblk > 0
+// roles of u and pro.xt). On level 0 of FP32 cycles (ctx.fuse_r_a0) that first
+// pass also applies A to the residual it forms, taking the second pass with
+// it. r_ready_nblk > 0
 // means u = 0 and the residual pass already ran as part of the restriction
 // (z_0 = f in Z, r_ready_nblk partial sums of ||f||^2 in region 0): the step
 // starts with the second pass. u_zero: the step starts from u = 0 although u
