@@ -179,12 +179,15 @@ struct RestrictOut {
 // for the caller to hand to the next finer level's correction (ProlongIn::du);
 // the step's Z, state and partial sums must then stay untouched until that
 // pass has run. Where the step has no plain update pass, defer->Z.p is null.
+// w_ready (level 0 of FP32 cycles, with r_ready_nblk): the refinement residual
+// pass also formed w_0 = A z_0 in Wa, with ||z_0||^2 and <z_0, w_0> in region
+// 1, and the step starts with its first orthogonalise + apply pass.
 template <typename T>
 void launch_gmres_step(const LaunchCtx&, const LevelOp<T>&, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa, Vec<T> Wb,
                        GmState* st, double breakdown, const hipEvent_t* timed, Vec<T> res = Vec<T>{nullptr, 0},
                        int r_ready_nblk = 0,
                        ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false, RestrictOut<T>* rout = nullptr,
-                       DeferredUpdate<T>* defer = nullptr);
+                       DeferredUpdate<T>* defer = nullptr, bool w_ready = false);
 
 // ||f - A x||^2 per right-hand side into norms[b].r2 (level-0 operator).
 template <typename T>
@@ -197,12 +200,21 @@ template <typename T> void launch_norm(const LaunchCtx&, Grid g, Vec<T> f, RhsNo
 // cycle), r also becomes that cycle's first residual z_0 (its iterate starting
 // at zero) with the partial sums of ||z_0||^2 in region 0, and the norm's
 // partials use region 1. Returns the number of partial sums per right-hand side.
+// With w0.p set as well (and refine_apply_fits), the pass also applies the
+// cycle's FP32 operator (k^2 in k2_32) to z_0 into w0 and hands the cycle's
+// first GMRES step ||z_0||^2 and <z_0, w_0> in region 1 (three per block),
+// the norm's partials then using region 0; that step (w_ready) starts with
+// its first orthogonalise pass.
 int launch_refine_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x, Vec<double> f, Vec<float> r32,
-                           RhsNorms* norms, Vec<float> z0 = Vec<float>{nullptr, 0});
+                           RhsNorms* norms, Vec<float> z0 = Vec<float>{nullptr, 0}, const float* k2_32 = nullptr,
+                           Vec<float> w0 = Vec<float>{nullptr, 0});
 // x_out = x_in + e (e complex64), then r = f - A_s x_out as above.
 int launch_correct_residual(const LaunchCtx&, const LevelOp<double>&, Vec<double> x_in, Vec<float> e,
                             Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms,
-                            Vec<float> z0 = Vec<float>{nullptr, 0});
+                            Vec<float> z0 = Vec<float>{nullptr, 0}, const float* k2_32 = nullptr,
+                            Vec<float> w0 = Vec<float>{nullptr, 0});
+// Whether the fused refinement residual + apply pass fits its LDS stages on grid g.
+bool refine_apply_fits(const LaunchCtx&, Grid g);
 
 // Layout conversion between the caller's dense [b][n+1][n+1] arrays and the
 // padded planes. src_is_f32 / dst_is_f32 select complex64 on the caller side.

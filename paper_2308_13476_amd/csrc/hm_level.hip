@@ -1558,6 +1558,143 @@ __global__ __launch_bounds__(kBX * BY) void k_correct_residual(FineOp<double> op
     if (zb) block_partials<1>(accz, pz + b * kPartStride);
 }
 
+// The refinement residual pass (k_refine_residual, or k_correct_residual with
+// kCorrect) together with the first apply pass of the FP32 cycle that follows
+// it (k_gm_a0 on z_0 = r32): x (x_in + e with kCorrect) is staged with a halo
+// of 2, r = f - A_s x in FP64 for the tile and a halo of 1 (the ring in the
+// operator form of its owning tile), r32 = r as complex64 in LDS, then
+// w_0 = A r32 with the FP32 operator of the cycle. Partial sums: ||r||^2
+// (the stop test) to pout; ||r32||^2 and <r32, w_0> to pz, which the first
+// orthogonalise pass of the cycle (kInit) reads in place of k_gm_a0's.
+template <typename T>
+struct RefineApplyStage {
+    __host__ __device__ static size_t bytes(int rows) {
+        return size_t(Tile<2>::TW) * (rows + 4) * sizeof(cplx<double>) +
+               size_t(Tile<1>::TW) * (rows + 2) * sizeof(cplx<float>);
+    }
+};
+
+template <int BY, bool kCorrect>
+__global__ __launch_bounds__(kBX * BY) void k_residual_apply(FineOp<double> op, FineOp<float> op32, Vec<double> x_in,
+                                                             Vec<float> e, Vec<double> x_out, Vec<double> f,
+                                                             Vec<float> r32, Vec<float> Z, Vec<float> Wout,
+                                                             double* pout, double* pz, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    const cplx<double>* xb = x_in.rhs(b);
+    const cplx<float>* eb = kCorrect ? e.rhs(b) : nullptr;
+    cplx<double>* ob = kCorrect ? x_out.rhs(b) : nullptr;
+    const cplx<double>* fb = f.rhs(b);
+    cplx<float>* rb = r32.rhs(b);
+    cplx<float>* zb = Z.p + (long long)(b * 4) * Z.plane;
+    cplx<float>* wb = Wout.rhs(b);
+    const Tile<2> tx = block_tile<2>(rpt);
+    const Tile<1> tz{tx.c0, tx.r0, tx.rows};
+    cplx<double>* X = reinterpret_cast<cplx<double>*>(hm_dyn_lds);
+    cplx<float>* ZL = reinterpret_cast<cplx<float>*>(X + Tile<2>::TW * (tx.rows + 4));
+    struct XE {
+        cplx<double> x;
+        cplx<float> e;
+    };
+    fill_tile<double, 2>(
+        X, tx, op.g,
+        [&](long long q) { return XE{xb[q], kCorrect ? eb[q] : cplx<float>{0.0f, 0.0f}}; },
+        [](const XE& v) { return kCorrect ? v.x + cast<double>(v.e) : v.x; });
+    const int n = op.g.n;
+    constexpr int XW = Tile<2>::TW, ZW = Tile<1>::TW;
+    const int trows = int(blockDim.y) * rpt;
+    auto owner_interior = [&](int i, int j) {
+        const int oc = (i / kBX) * kBX, orow = (j / trows) * trows;
+        return oc >= 1 && oc + kBX <= n && orow >= 1 && orow + trows <= n;
+    };
+    auto ax_at = [&](int i, int j, double kk, bool inner) {
+        const int l = tx.at(i, j);
+        return inner ? op.apply5k_interior(kk, X[l], X[l - 1], X[l + 1], X[l - XW], X[l + XW])
+                     : op.apply5k(i, j, kk, X[l], X[l - 1], X[l + 1], X[l - XW], X[l + XW]);
+    };
+    // r32 on the halo ring (top and bottom rows, then the left and right
+    // columns); each thread's first ring node has its operands loaded with
+    // those of its tile nodes, further ones after them
+    const int ring = 2 * ZW + 2 * tx.rows;
+    auto ring_node = [&](int q, int& i, int& j) {
+        if (q < 2 * ZW) {
+            i = tx.c0 - 1 + q % ZW;
+            j = q < ZW ? tx.r0 - 1 : tx.r0 + tx.rows;
+        } else {
+            const int m = q - 2 * ZW;
+            i = (m & 1) ? tx.c0 + kBX : tx.c0 - 1;
+            j = tx.r0 + (m >> 1);
+        }
+    };
+    auto ring_r = [&](int i, int j, double kk, cplx<double> fp) {
+        cplx<float> z{0.0f, 0.0f};
+        if (i >= 0 && j >= 0 && i <= n && j <= n) z = cast<float>(fp - ax_at(i, j, kk, owner_interior(i, j)));
+        ZL[tz.at(i, j)] = z;
+    };
+    const int tid = thread_linear(), nt = int(blockDim.x * blockDim.y);
+    int ri = 0, rj = 0;
+    double rk = 0.0;
+    cplx<double> rf{0.0, 0.0};
+    if (tid < ring) {
+        ring_node(tid, ri, rj);
+        const long long p = op.g.at(min(max(ri, 0), n), min(max(rj, 0), n));
+        rk = op.k2[p];
+        rf = fb[p];
+    }
+    // the tile, in the thread order of the residual pass; each thread first
+    // zeroes its own tile positions (those off the grid stay zero)
+    for (int rr = 0; rr < rpt; ++rr)
+        ZL[tz.at(tx.c0 + int(threadIdx.x), tx.r0 + rr * int(blockDim.y) + int(threadIdx.y))] = cplx<float>{0.0f, 0.0f};
+    const bool interior = tx.c0 >= 1 && tx.c0 + kBX <= n && tx.r0 >= 1 && tx.r0 + tx.rows <= n;
+    double acc[1] = {0.0}, acz[3] = {0.0, 0.0, 0.0};
+    {
+        constexpr int NB = 4;
+        cplx<double> pv[NB];
+        double kk[NB];
+        for_nodes_batched<NB>(
+            op.g, rpt,
+            [&](int v, long long p) {
+                pv[v] = fb[p];
+                kk[v] = op.k2[p];
+            },
+            [&](int v, int i, int j, long long p) {
+                const cplx<double> r = pv[v] - ax_at(i, j, kk[v], interior);
+                if constexpr (kCorrect) ob[p] = X[tx.at(i, j)];
+                const cplx<float> r1 = cast<float>(r);
+                rb[p] = r1;
+                zb[p] = r1;
+                ZL[tz.at(i, j)] = r1;
+                acc[0] += dnorm2(r);
+                acz[0] += dnorm2(r1);
+            });
+    }
+    if (tid < ring) ring_r(ri, rj, rk, rf);
+    for (int q = tid + nt; q < ring; q += nt) {
+        int i, j;
+        ring_node(q, i, j);
+        const long long p = op.g.at(min(max(i, 0), n), min(max(j, 0), n));
+        ring_r(i, j, op.k2[p], fb[p]);
+    }
+    __syncthreads();
+    {  // w_0 = A r32 with the FP32 operator, in the thread order of the apply pass
+        constexpr int NB = 8;
+        float kk[NB];
+        for_nodes_batched<NB>(
+            op32.g, rpt, [&](int v, long long p) { kk[v] = op32.k2[p]; },
+            [&](int v, int i, int j, long long p) {
+                const int l = tz.at(i, j);
+                const cplx<float> zp = ZL[l];
+                const cplx<float> w =
+                    interior ? op32.apply5k_interior(kk[v], zp, ZL[l - 1], ZL[l + 1], ZL[l - ZW], ZL[l + ZW])
+                             : op32.apply5k(i, j, kk[v], zp, ZL[l - 1], ZL[l + 1], ZL[l - ZW], ZL[l + ZW]);
+                wb[p] = w;
+                acc_dot(acz[1], acz[2], zp, w);
+            });
+    }
+    block_partials<1>(acc, pout + b * kPartStride);
+    block_partials<3>(acz, pz + b * kPartStride);
+}
+
 // ---------------------------------------------------------------- layout
 template <typename T, typename S, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_copy_in(Grid g, const cplx<S>* src, Vec<T> dst, int scale_w,
@@ -1750,7 +1887,7 @@ template <typename T>
 void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Vec<T> f, Vec<T> Z, Vec<T> Wa,
                        Vec<T> Wb, GmState* st, double breakdown, const hipEvent_t* timed,
                        Vec<T> res, int r_ready_nblk, ProlongIn<T> pro, bool u_zero, RestrictOut<T>* rout,
-                       DeferredUpdate<T>* defer) {
+                       DeferredUpdate<T>* defer, bool w_ready) {
     // partial sums: each pass reads the region its producer wrote and writes the
     // other one (blocks of a pass still read while others write)
     double* A = region(ctx, 0);
@@ -1830,10 +1967,16 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
             uin = pro.xt;
         } else if (r_ready_nblk > 0) {
             // u = 0: z_0 = f and its partial norms were written by the restriction
+            // (or the refinement residual pass; with w_ready that pass also
+            // formed w_0 = A z_0, its sums ||z_0||^2 and <z_0, w_0> in region 1)
             nb_r = r_ready_nblk;
             if (r_ready_nblk > ctx.block_cap || (ctx.nrhs_cap > 1 && r_ready_nblk > kBatchPrereduceBlocks)) {
-                hipLaunchKernelGGL((k_prereduce<1>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, A, r_ready_nblk,
-                                   HM_ACTIVE);
+                if (w_ready)
+                    hipLaunchKernelGGL((k_prereduce<3>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, B,
+                                       r_ready_nblk, HM_ACTIVE);
+                else
+                    hipLaunchKernelGGL((k_prereduce<1>), dim3(ctx.nrhs), dim3(kBX, kBY), 0, ctx.stream, A,
+                                       r_ready_nblk, HM_ACTIVE);
                 nb_r = 1;
             }
         } else {
@@ -1848,12 +1991,14 @@ void launch_gmres_step(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> u, Ve
         // handle, not the call, so a batch member runs the same code as a solo
         // solve on the same handle and matches it bit for bit.
         const bool ov = ctx.nrhs_cap == 1 && q.nblk <= kOverlapMaxBlocks;
-        if (r_a0) {  // only the level-0 operator of FP32 cycles takes this branch
+        const bool w0_made = r_a0 || (w_ready && r_ready_nblk > 0 && !fuse_pro);
+        if (w0_made) {  // only the level-0 operator of FP32 cycles takes this branch
             if constexpr (std::is_same<Op, FineOp<T>>::value && sizeof(T) == 4) {
-                if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
-                                     HM_ACTIVE, q.rpt);
-                else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false, true>), op, Z, Wa, Wb, st, breakdown, B, nb, A,
-                                  HM_ACTIVE, q.rpt);
+                const int nb_in = r_a0 ? nb : nb_r;
+                if (ov) HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, true, true>), op, Z, Wa, Wb, st, breakdown, B, nb_in,
+                                     A, HM_ACTIVE, q.rpt);
+                else HM_LAUNCH_OP(q, (k_gm_oa<Op, T, 1, BY, false, true>), op, Z, Wa, Wb, st, breakdown, B, nb_in,
+                                  A, HM_ACTIVE, q.rpt);
             }
         } else {
             if (ov) HM_LAUNCH_OP(q, (k_gm_a0<Op, T, BY, true>), op, Z, Wa, st, A, nb_r, B, HM_ACTIVE, q.rpt);
@@ -1958,10 +2103,41 @@ void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
     launch_sum_norms(ctx, q.nblk, norms, 0);
 }
 
+bool refine_apply_fits(const LaunchCtx& ctx, Grid g) {
+    const Geom q = geom_op<FineOp<double>, double>(g, ctx);
+    return RefineApplyStage<double>::bytes(q.by * q.rpt) <= kMaxTileBytes;
+}
+
+namespace {
+// The fused refinement residual + apply pass (w0.p set): residual norms to
+// region 0, z_0's sums (||z_0||^2, <z_0, w_0>) to region 1.
+template <bool kCorrect>
+int launch_residual_apply(const LaunchCtx& ctx, const LevelOp<double>& lop, const float* k2_32, Vec<double> x_in,
+                          Vec<float> e, Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms,
+                          Vec<float> z0, Vec<float> w0) {
+    const Geom q = geom_op<FineOp<double>, double>(lop.g, ctx);
+    const FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
+    const FineOp<float> op32{lop.g, k2_32, float(1.0 / (lop.h * lop.h)), float(2.0 / lop.h)};
+    const size_t shm = RefineApplyStage<double>::bytes(q.by * q.rpt);
+    with_by(q.by, [&](auto byc) {
+        constexpr int BY = decltype(byc)::value;
+        hipLaunchKernelGGL((k_residual_apply<BY, kCorrect>), q.grid, q.block, shm, ctx.stream, op, op32, x_in, e,
+                           x_out, f, r32, z0, w0, region(ctx, 0), region(ctx, 1), HM_ACTIVE, q.rpt);
+    });
+    launch_sum_norms(ctx, q.nblk, norms, 1, 0);
+    return q.nblk;
+}
+}  // namespace
+
 // With z0.p set the residual norms use region 1 and z_0's region 0 (where the
-// first GMRES step of the next FP32 cycle reads them).
+// first GMRES step of the next FP32 cycle reads them); with w0.p set as well
+// (refine_apply_fits) the pass also forms w_0 = A z_0, the norms use region 0
+// and z_0's sums region 1 (see k_residual_apply).
 int launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x, Vec<double> f,
-                           Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
+                           Vec<float> r32, RhsNorms* norms, Vec<float> z0, const float* k2_32, Vec<float> w0) {
+    if (z0.p && w0.p)
+        return launch_residual_apply<false>(ctx, lop, k2_32, x, Vec<float>{nullptr, 0}, Vec<double>{nullptr, 0}, f,
+                                            r32, norms, z0, w0);
     using Op = FineOp<double>;
     using T = double;
     const Geom q = geom_op<Op, T>(lop.g, ctx);
@@ -1973,7 +2149,10 @@ int launch_refine_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec
 }
 
 int launch_correct_residual(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<double> x_in, Vec<float> e,
-                            Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms, Vec<float> z0) {
+                            Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms, Vec<float> z0,
+                            const float* k2_32, Vec<float> w0) {
+    if (z0.p && w0.p)
+        return launch_residual_apply<true>(ctx, lop, k2_32, x_in, e, x_out, f, r32, norms, z0, w0);
     using Op = FineOp<double>;
     using T = double;
     const Geom q = geom_op<Op, T>(lop.g, ctx);
@@ -2041,7 +2220,7 @@ void launch_grad_k2(const LaunchCtx& ctx, Grid g, double h, const double* k2, Ve
     template void launch_prolong_add<T>(const LaunchCtx&, Grid, Grid, int, Vec<T>, Vec<T>);                     \
     template void launch_gmres_step<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, Vec<T>, Vec<T>,     \
                                        Vec<T>, GmState*, double, const hipEvent_t*, Vec<T>,                     \
-                                       int, ProlongIn<T>, bool, RestrictOut<T>*, DeferredUpdate<T>*);           \
+                                       int, ProlongIn<T>, bool, RestrictOut<T>*, DeferredUpdate<T>*, bool);     \
     template void launch_resnorm<T>(const LaunchCtx&, const LevelOp<T>&, Vec<T>, Vec<T>, RhsNorms*);            \
     template void launch_norm<T>(const LaunchCtx&, Grid, Vec<T>, RhsNorms*);                                    \
     template void launch_copy_in<T>(const LaunchCtx&, Grid, const void*, bool, Vec<T>, bool, bool);             \

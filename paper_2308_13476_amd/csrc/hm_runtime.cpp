@@ -511,7 +511,8 @@ struct CycleParams {
 template <typename T>
 void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool then_residual = false,
             int r_ready_nblk = 0, ProlongIn<T> pro = ProlongIn<T>{}, bool u_zero = false,
-            RestrictOut<T>* rout = nullptr, int jsteps = 1, DeferredUpdate<T>* defer = nullptr) {
+            RestrictOut<T>* rout = nullptr, int jsteps = 1, DeferredUpdate<T>* defer = nullptr,
+            bool w_ready = false) {
     LevelBuf& lb = c->lv[l];
     const LevelOp<T> op = level_op<T>(c, l);
     const double nodes = double(lb.g.n + 1) * (lb.g.n + 1) * lc.nrhs;
@@ -547,7 +548,7 @@ void smooth(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, bool t
     const Vec<T> w = vec<T>(Prec<T>::w(lb), lb), t = vec<T>(Prec<T>::t_ref(lb), lb);
     launch_gmres_step<T>(lc, op, vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb), vec<T>(Prec<T>::V(lb), lb),
                          w, t, c->gm, Prec<T>::breakdown, tev[1] ? tev : nullptr,
-                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero, rout, defer);
+                         then_residual ? w : Vec<T>{nullptr, 0}, r_ready_nblk, pro, u_zero, rout, defer, w_ready);
     if (tev[1]) {
         c->ev_pending.push_back({tev[0], tev[1]});
         c->t_nodes += nodes;
@@ -597,10 +598,12 @@ void launch_tail_from(mg_ctx* c, const LaunchCtx& lc, int l0, const CycleParams&
 // first_visit: level l was entered by the restriction that zeroed its u.
 // defer (may be null): the update pass of the last post-smoothing step is left
 // to the caller's coarse grid correction (*defer describes it; defer->Z.p is
-// null where no update is pending and u holds the result).
+// null where no update is pending and u holds the result). w_ready (level 0
+// of FP32 cycles, with r_ready_nblk): that FP64 pass also formed the first
+// product A z_0 of the first GMRES step.
 template <typename T>
 void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_ready_nblk = 0, bool u_zero = false,
-           bool first_visit = false, DeferredUpdate<T>* defer = nullptr) {
+           bool first_visit = false, DeferredUpdate<T>* defer = nullptr, bool w_ready = false) {
     if (l == c->tail_level[sizeof(T) == 4]) {
         launch_tail_from<T>(c, lc, l, cp, first_visit);
         return;
@@ -629,7 +632,8 @@ void cycle(mg_ctx* c, const LaunchCtx& lc, int l, const CycleParams& cp, int r_r
     auto jsteps = [&](int s, int nu) { return cp.smoother == MG_JACOBI && s + 1 < nu ? 2 : 1; };
     for (int s = 0; s < cp.nu1; s += jsteps(s, cp.nu1))
         smooth<T>(c, lc, l, cp, fused && s == cp.nu1 - 1, s == 0 ? r_ready_nblk : 0, ProlongIn<T>{},
-                  s == 0 && u_zero, fused && s == cp.nu1 - 1 ? &ro : nullptr, jsteps(s, cp.nu1));
+                  s == 0 && u_zero, fused && s == cp.nu1 - 1 ? &ro : nullptr, jsteps(s, cp.nu1), nullptr,
+                  s == 0 && w_ready);
     if (!fused)
         launch_residual<T>(lc, level_op<T>(c, l), vec<T>(Prec<T>::u(lb), lb), vec<T>(Prec<T>::f(lb), lb),
                            vec<T>(Prec<T>::w(lb), lb));
@@ -810,8 +814,10 @@ struct SolveRun {
     int running = 0;
     // FP32 cycles whose first level-0 GMRES residual comes from the FP64
     // residual pass before them (u = 0 is not stored; no zeroing pass), and
-    // that pass's partial sums per right-hand side
+    // that pass's partial sums per right-hand side; w_ready: that pass also
+    // forms the step's first product A z_0 (one pass fewer per cycle)
     bool z_ready = false;
+    bool w_ready = false;
     int z_nblk = 0;
     std::vector<uintptr_t> key;
     std::chrono::steady_clock::time_point t0;
@@ -829,6 +835,10 @@ struct SolveRun {
         LevelBuf& l0 = c->lv[0];
         return z_ready ? vec<float>(Prec<float>::V(l0), l0) : Vec<float>{nullptr, 0};
     }
+    Vec<float> w_plane() const {
+        LevelBuf& l0 = c->lv[0];
+        return w_ready ? vec<float>(Prec<float>::w(l0), l0) : Vec<float>{nullptr, 0};
+    }
 
     mg_status start(hipStream_t s) {
         t0 = std::chrono::steady_clock::now();
@@ -842,8 +852,10 @@ struct SolveRun {
         launch_norm<double>(lc, l0.g, vec<double>(l0.f64, l0), c->norms);
         if (fp32) {
             z_ready = cp.smoother == MG_GMRES3 && cp.nu1 > 0 && c->L > 1 && c->tail_level[1] != 0;
+            w_ready = z_ready && c->fuse_r_a0 && refine_apply_fits(lc, l0.g);
+            key.push_back(uintptr_t(w_ready));
             z_nblk = launch_refine_residual(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0),
-                                            vec<float>(l0.f32, l0), c->norms, z_plane());
+                                            vec<float>(l0.f32, l0), c->norms, z_plane(), c->k2_32, w_plane());
         }
         else
             launch_resnorm<double>(lc, op0, vec<double>(l0.u64, l0), vec<double>(l0.f64, l0), c->norms);
@@ -899,12 +911,12 @@ struct SolveRun {
         lt.stop = StopTest{c->h_ring, c->active, c->stop_count, c->stop_limits, c->max_batch};
         if (fp32) {
             if (!z_ready) launch_zero<float>(st, l0.u32, l0.g.plane * nrhs);
-            cycle<float>(c, l2, 0, cp, z_ready ? z_nblk : 0, z_ready);
+            cycle<float>(c, l2, 0, cp, z_ready ? z_nblk : 0, z_ready, false, nullptr, w_ready);
             cplx<double>* xin = c->cur_buf == 0 ? l0.u64 : l0.t64;
             cplx<double>* xout = c->cur_buf == 0 ? l0.t64 : l0.u64;
             z_nblk = launch_correct_residual(lt, op0, vec<double>(xin, l0), vec<float>(l0.u32, l0),
                                              vec<double>(xout, l0), vec<double>(l0.f64, l0), vec<float>(l0.f32, l0),
-                                             c->norms, z_plane());
+                                             c->norms, z_plane(), c->k2_32, w_plane());
             c->cur_buf ^= 1;
         } else {
             cycle<double>(c, l2, 0, cp);

@@ -393,6 +393,57 @@ def test_fused_correction_and_apply(monkeypatch, transfer, n, env, nb):
             assert rel(a, ref) <= tol and rel(b, ref) <= tol, (cyc, nu2, r, rel(a, ref), rel(b, ref))
 
 
+@pytest.mark.parametrize("n,env,nb,x0", [(128, {}, 1, False), (96, {}, 1, True), (256, {"HELMG_MAX_BLOCKS": "64"}, 1, False),
+                                         (128, {}, 3, True), (64, {"HELMG_DEFER_UPDATE": "0"}, 1, False)],
+                         ids=["n128", "n96_x0", "n256_cap64", "n128_batch3_x0", "n64_no_deferral"])
+def test_fused_refinement_residual_and_apply(monkeypatch, n, env, nb, x0):
+    """FP32-refined solves whose FP64 residual pass before each FP32 cycle also
+    forms the first product A z_0 of the cycle's first GMRES step (x staged with
+    a halo of 2, r32 with a halo of 1 in LDS, the ring evaluated as its owning
+    tiles evaluate it) against solves with the separate apply pass: the same
+    cycle counts, residual histories within 1e-3 of each other (FP32 cycles,
+    FP64 residuals), iterates within 1e-5 of the largest value at every node, and
+    both meet the tolerance in the oracle's FP64 residual. V(1,1) (the first
+    step is also the one that restricts), W(2,2) and V(2,1); a ragged grid (96
+    intervals), pre-reduced partial sums (block cap 64), a batch handle, a
+    nonzero start and no deferred coarse update."""
+    require_gpu()
+    import torch
+    from paper_2308_13476_amd.solver import Solver
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    k2 = W.random_k2(n, 23, 10.0, 30.0)
+    cn = 6 if n == 96 else 4
+    A = O.helmholtz_matrix(k2, 1.0 / n)
+    f = _rand(n, nb, 190)
+    u0 = _rand(n, nb, 191) if x0 else None
+    runs = [("V", 1, 1), ("W", 2, 2), ("V", 2, 1)]
+    tol = 1e-7
+    out = {}
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("HELMG_FUSE_R_A0", fuse)
+        S = Solver(to_gpu(k2), 1.0 / n, 0.2, max_batch=nb, precision="fp32_refined", coarsest_n=cn)
+        for cyc, nu1, nu2 in runs:
+            x, info = S.solve(to_gpu(f), None if u0 is None else to_gpu(u0), tol=tol, cycle=cyc, nu_pre=nu1,
+                              nu_post=nu2, precision="fp32_refined", max_cycles=200, history=True)
+            out[fuse, cyc, nu1, nu2] = (to_np(x), list(info["cycles"]), info["history"])
+        del S
+        torch.cuda.synchronize()
+    for cyc, nu1, nu2 in runs:
+        (xa, ca, ha), (xb, cb, hb) = out["1", cyc, nu1, nu2], out["0", cyc, nu1, nu2]
+        assert ca == cb, (cyc, nu1, nu2, ca, cb)
+        for r in range(nb):
+            d = node_rel(xa[r], xb[r])
+            m = ca[r]  # a batch's histories run to its longest solve
+            hd = np.max(np.abs(np.array(ha[r][:m]) - np.array(hb[r][:m])) / np.array(hb[r][:m]))
+            print(f"{cyc}({nu1},{nu2}) rhs {r}: {ca[r]} cycles; fused vs separate passes, largest node "
+                  f"difference {d:.2e}, largest relative history difference {hd:.2e}")
+            assert d <= 1e-5 and hd <= 1e-3, (cyc, nu1, nu2, r, d, hd)
+            fs = O.scaled_rhs(f[r].astype(np.complex128)).ravel()
+            for xx in (xa[r], xb[r]):
+                assert np.linalg.norm(fs - A @ xx.ravel()) <= 1.01 * tol * np.linalg.norm(fs)
+
+
 @pytest.mark.parametrize("n,cap", [(128, None), (96, None), (256, "64")])
 def test_paired_jacobi_sweeps(monkeypatch, n, cap):
     """Weighted-Jacobi sweeps on level 0 run two per pass (x staged for the
