@@ -58,15 +58,15 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "cffafca8fd52040a25738401c7e81f804d080d4e79035643391c813864d10c71",
+    "sources_sha256": "3dd283bd4689eb4c80c143c649dd39f7ef8de7f9c7a5744b8c56322ef30ece0e",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
-    "mp2a": {"fetch_bytes": 32544203, "write_bytes": 12684816,
+    "mp2a": {"fetch_bytes": 32548570, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
     # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
-    "beyond_cache": {"fetch_bytes": 369834776, "write_bytes": 100890789,
+    "beyond_cache": {"fetch_bytes": 369954750, "write_bytes": 100890469,
                      "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
     # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
-    "batch64": {"fetch_bytes": 908659597, "write_bytes": 198098217,
+    "batch64": {"fetch_bytes": 908633408, "write_bytes": 198098210,
                 "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
 
