@@ -58,7 +58,7 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "3dd283bd4689eb4c80c143c649dd39f7ef8de7f9c7a5744b8c56322ef30ece0e",
+    "sources_sha256": "f6e969dd799352ca21af0d4a2a72e096151f0d6ebd03bf51e2ae1048759cbc4c",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
     "mp2a": {"fetch_bytes": 32548570, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},

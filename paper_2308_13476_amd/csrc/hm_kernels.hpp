@@ -282,11 +282,17 @@ constexpr int kMaxRestart = 64;  // longest restart cycle m
 // <V_i, w> from the incoming w, then w -= sum h_i V_i); H[b * hstride + i]
 // receives column j (i = 0..j) and the subdiagonal ||w|| (i = j + 1);
 // V_{j+1} = w / ||w||, and its complex64 copy into v32 when v32 is not null.
+// z32 (may be null; 4 planes per right-hand side): the complex64 copy is also
+// written to z32's first plane, with its partial sums of ||.||^2 in reduction
+// region 0 (as many blocks as launch_kry_first returns), the first residual
+// of an FP32 cycle from u = 0 on v32 (cycle's r_ready_nblk and u_zero).
 void launch_kry_orthogonalise(const LaunchCtx&, Grid g, cplx<double>* V, long long vstride, int j,
-                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32);
-// v = r / ||r|| with ||r||^2 from norms[b].r2 (and its complex64 copy into v32 when not null).
-void launch_kry_first(const LaunchCtx&, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
-                      const RhsNorms* norms, cplx<float>* v32);
+                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32,
+                              cplx<float>* z32 = nullptr);
+// v = r / ||r|| with ||r||^2 from norms[b].r2 (and its complex64 copy into v32,
+// and z32, as above). Returns the partial-sum count of the z32 copies.
+int launch_kry_first(const LaunchCtx&, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
+                     const RhsNorms* norms, cplx<float>* v32, cplx<float>* z32 = nullptr);
 // x += sum_{i < nz} y[b * ystride + i] Z_i.
 void launch_kry_update(const LaunchCtx&, Grid g, const cplx<double>* Z, long long zstride, int nz,
                        const cplx<double>* y, int ystride, cplx<double>* x, long long plane);

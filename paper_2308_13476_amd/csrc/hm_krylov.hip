@@ -98,12 +98,28 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_cgs_update(Grid g, const cplx
     block_partials<2>(acc, pout + b * kPartStride);
 }
 
+// The complex64 copy of a new basis vector is also the right-hand side of the
+// FP32 cycle that preconditions it; with z32 set it is written a second time,
+// as the first Arnoldi vector of that cycle's first GMRES step (z32 holds 4
+// planes per right-hand side), with its block partial sums of ||v32||^2 at
+// pz + b * kPartStride, so that step starts from u = 0 without a residual pass.
+__device__ __forceinline__ void kry_out32(cplx<float>* fb, cplx<float>* zb, long long p, cplx<double> v,
+                                          double& acc) {
+    const cplx<float> v1 = cast<float>(v);
+    if (fb) fb[p] = v1;
+    if (zb) {
+        zb[p] = v1;
+        acc += double(v1.re) * double(v1.re) + double(v1.im) * double(v1.im);
+    }
+}
+
 // ||w|| from the previous pass; H[b][0] = ||w|| (entry j+1 of the column);
 // v_out = w / ||w|| (zero when ||w|| = 0).
 __global__ __launch_bounds__(kBX * kBY) void k_kry_normalize(Grid g, const cplx<double>* w, cplx<double>* vout,
                                                             long long plane, cplx<double>* Hsub, int hstride,
                                                             const double* pin, int nblk_in, cplx<float>* v32,
-                                                            const int* active, int rpt) {
+                                                            cplx<float>* z32, double* pz, const int* active,
+                                                            int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     double t[2];
@@ -114,17 +130,20 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_normalize(Grid g, const cplx<
     const cplx<double>* wb = w + b * plane;
     cplx<double>* ob = vout + b * plane;
     cplx<float>* fb = v32 ? v32 + b * plane : nullptr;
+    cplx<float>* zb = z32 ? z32 + b * 4 * plane : nullptr;
+    double acc[1] = {0.0};
     for_nodes(g, rpt, [&](int, int, long long p) {
         const cplx<double> v = s * wb[p];
         ob[p] = v;
-        if (fb) fb[p] = cast<float>(v);
+        kry_out32(fb, zb, p, v, acc[0]);
     });
+    if (zb) block_partials<1>(acc, pz + b * kPartStride);
 }
 
 // v = r / ||r|| with ||r||^2 from norms[b].r2
 __global__ __launch_bounds__(kBX * kBY) void k_kry_first(Grid g, const cplx<double>* r, cplx<double>* v,
                                                         long long plane, const RhsNorms* norms, cplx<float>* v32,
-                                                        const int* active, int rpt) {
+                                                        cplx<float>* z32, double* pz, const int* active, int rpt) {
     const int b = blockIdx.z;
     if (!rhs_active(active, b)) return;
     const double nr = sqrt(norms[b].r2);
@@ -132,11 +151,14 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_first(Grid g, const cplx<doub
     const cplx<double>* rb = r + b * plane;
     cplx<double>* vb = v + b * plane;
     cplx<float>* fb = v32 ? v32 + b * plane : nullptr;
+    cplx<float>* zb = z32 ? z32 + b * 4 * plane : nullptr;
+    double acc[1] = {0.0};
     for_nodes(g, rpt, [&](int, int, long long p) {
         const cplx<double> x = s * rb[p];
         vb[p] = x;
-        if (fb) fb[p] = cast<float>(x);
+        kry_out32(fb, zb, p, x, acc[0]);
     });
+    if (zb) block_partials<1>(acc, pz + b * kPartStride);
 }
 
 // x += sum_i y[b][i] z_i for i < nz (y complex, [b][ystride])
@@ -185,13 +207,19 @@ KGeom kgeom(const LaunchCtx& ctx, const Grid& g, long long cap_limit = 1LL << 30
 
 double* kregion(const LaunchCtx& ctx, int r) { return ctx.partials + (long long)r * ctx.nrhs_cap * kPartStride; }
 
+// the inner-product pass keeps the partials of every chunk in one reduction
+// region; the passes that write a basis vector use the same block grid, so
+// that the z_0 partial sums of k_kry_first and k_kry_normalize always count
+// the same number of blocks
+constexpr int kKryChunks = (kMaxRestart + kCgsChunk - 1) / kCgsChunk;
+KGeom kry_geom(const LaunchCtx& ctx, const Grid& g) { return kgeom(ctx, g, kPartStride / (2 * kCgsChunk * kKryChunks)); }
+
 }  // namespace
 
 void launch_kry_orthogonalise(const LaunchCtx& ctx, Grid g, cplx<double>* V, long long vstride, int j,
-                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32) {
-    // the partials of every chunk fit one reduction region
-    constexpr int kChunks = (kMaxRestart + kCgsChunk - 1) / kCgsChunk;
-    const KGeom q = kgeom(ctx, g, kPartStride / (2 * kCgsChunk * kChunks));
+                              cplx<double>* w, cplx<double>* H, int hstride, long long plane, cplx<float>* v32,
+                              cplx<float>* z32) {
+    const KGeom q = kry_geom(ctx, g);
     double* A = kregion(ctx, 0);
     double* B = kregion(ctx, 1);
     for (int i0 = 0; i0 <= j; i0 += kCgsChunk)
@@ -203,13 +231,15 @@ void launch_kry_orthogonalise(const LaunchCtx& ctx, Grid g, cplx<double>* V, lon
     hipLaunchKernelGGL(k_kry_cgs_update, q.grid, q.block, 0, ctx.stream, g, V, vstride, j, w, plane, H, hstride, B,
                        ctx.active, q.rpt);
     hipLaunchKernelGGL(k_kry_normalize, q.grid, q.block, 0, ctx.stream, g, w, V + (j + 1) * vstride, plane,
-                       H + j + 1, hstride, B, q.nblk, v32, ctx.active, q.rpt);
+                       H + j + 1, hstride, B, q.nblk, v32, z32, A, ctx.active, q.rpt);
 }
 
-void launch_kry_first(const LaunchCtx& ctx, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
-                      const RhsNorms* norms, cplx<float>* v32) {
-    const KGeom q = kgeom(ctx, g);
-    hipLaunchKernelGGL(k_kry_first, q.grid, q.block, 0, ctx.stream, g, r, v, plane, norms, v32, ctx.active, q.rpt);
+int launch_kry_first(const LaunchCtx& ctx, Grid g, const cplx<double>* r, cplx<double>* v, long long plane,
+                     const RhsNorms* norms, cplx<float>* v32, cplx<float>* z32) {
+    const KGeom q = kry_geom(ctx, g);
+    hipLaunchKernelGGL(k_kry_first, q.grid, q.block, 0, ctx.stream, g, r, v, plane, norms, v32, z32,
+                       kregion(ctx, 0), ctx.active, q.rpt);
+    return q.nblk;
 }
 
 void launch_kry_update(const LaunchCtx& ctx, Grid g, const cplx<double>* Z, long long zstride, int nz,

@@ -1550,15 +1550,22 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
     for (int b = 0; b < nrhs; ++b) nf[b] = std::sqrt(c->h_norms[b].f2);
     uint64_t omega_bits;
     std::memcpy(&omega_bits, &o.omega, sizeof(omega_bits));
+    // FP32 preconditioner cycles whose first level-0 GMRES residual is the
+    // complex64 basis vector itself (u = 0): the pass that writes v_j also
+    // writes it as the first Arnoldi vector with its partial norms (z_nblk
+    // blocks), so the cycle has no zeroing pass and no level-0 residual pass
+    const bool z_ready = fp32 && cp.smoother == MG_GMRES3 && cp.nu1 > 0 && c->L > 1 && c->tail_level[1] != 0;
+    cplx<float>* z32 = z_ready ? Prec<float>::V(l0) : nullptr;
+    int z_nblk = 0;
     const std::vector<uintptr_t> key{0xF6E5u, uintptr_t(fp32), uintptr_t(cyc), uintptr_t(smoother),
                                      uintptr_t(o.nu_pre), uintptr_t(o.nu_post), uintptr_t(omega_bits),
-                                     uintptr_t(nrhs)};
+                                     uintptr_t(nrhs), uintptr_t(z_ready)};
     auto precond_body = [&](hipStream_t st) {
         LaunchCtx l2 = lc;
         l2.stream = st;
         if (fp32) {
-            launch_zero<float>(st, l0.u32, pl * nrhs);
-            cycle<float>(c, l2, 0, cp);
+            if (!z_ready) launch_zero<float>(st, l0.u32, pl * nrhs);
+            cycle<float>(c, l2, 0, cp, z_ready ? z_nblk : 0, z_ready);
         } else {
             launch_zero<double>(st, l0.u64, pl * nrhs);
             cycle<double>(c, l2, 0, cp);
@@ -1610,7 +1617,7 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
         // v_0, and each v_{j+1} below, is also written in complex64 to the
         // FP32 cycle's right-hand side plane when the preconditioner is the
         // FP32 cycle
-        launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms, fp32 ? l0.f32 : nullptr);
+        z_nblk = launch_kry_first(lc, g0, K.Wv, K.V, pl, c->norms, fp32 ? l0.f32 : nullptr, z32);
         std::vector<int> in_cycle = act;  // right-hand sides updated at the end of this cycle
         std::vector<int> stopped(nrhs, 0);
         // iteration j on the stream: z_j = M(v_j), one cycle from zero on
@@ -1624,7 +1631,8 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
             if (fp32) launch_kry_cast_up(lc, g0, l0.u32, zj, pl);
             else HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
             launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
-            launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl, fp32 ? l0.f32 : nullptr);
+            launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl, fp32 ? l0.f32 : nullptr,
+                                     z32);
             if (mg_status st = check_launch(c)) return st;
             HM_HIP(hipMemcpyAsync(c->h_hcol + size_t(j & 1) * nrhs * (m + 1), K.H,
                                   sizeof(cplx<double>) * nrhs * (m + 1), hipMemcpyDeviceToHost, s));

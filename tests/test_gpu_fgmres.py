@@ -88,3 +88,31 @@ def test_fgmres_batch_members_stop_at_their_own_iteration():
         assert abs(info["cycles"][b] - ref.iterations) <= 1
         same = O.fgmres(H.A[0], fs, pre, m=3, tol=1e-30, max_iter=info["cycles"][b])
         assert rel(to_np(x)[b], same.x) <= 1e-10, (b, rel(to_np(x)[b], same.x))
+
+
+@pytest.mark.parametrize("m,nb", [(20, 1), (5, 2)])
+def test_fgmres_fp32_cycles_follow_the_oracle(m, nb):
+    """FP32 cycles as the preconditioner (each starts from u = 0 with the
+    complex64 basis vector as its first GMRES residual, written by the pass
+    that forms the vector) against the oracle's FGMRES with FP64 cycles: per
+    source the iteration count within one, the residual estimates of the
+    common iterations within 1e-3 of each other (the preconditioners differ by
+    FP32 rounding), and the true FP64 residual at the tolerance; with restarts
+    (m = 5) and two sources."""
+    n, k = 128, 40.0
+    nodes = [W.center_node(n), (30, 90)][:nb]
+    S, H, f = _setup(n, k, 1.0 / k, nodes=nodes, precision="fp32_refined", max_batch=nb)
+    x, info = S.solve_fgmres(to_gpu(f), tol=1e-9, m=m, precision="fp32_refined", max_iter=300, history=True)
+    assert info["status"] == 0
+    pre = O.mg_preconditioner(H, O.CycleOptions(smoother="gmres"))
+    for b in range(nb):
+        fs = O.scaled_rhs(f[b]).ravel()
+        ref = O.fgmres(H.A[0], fs, pre, m=m, tol=1e-9, max_iter=300)
+        it = min(info["cycles"][b], ref.iterations)
+        d = np.max(np.abs(np.array(info["history"][b][:it]) - np.array(ref.history[:it])) / np.array(ref.history[:it]))
+        print(f"source {b}: {info['cycles'][b]} iterations (oracle {ref.iterations}), residual estimates "
+              f"within {d:.2e}")
+        assert abs(info["cycles"][b] - ref.iterations) <= 1
+        assert d <= 1e-3
+        r = np.linalg.norm(fs - H.A[0] @ to_np(x)[b].ravel()) / np.linalg.norm(fs)
+        assert r <= 1e-9 * 1.01, (b, r)
