@@ -58,15 +58,15 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "f6e969dd799352ca21af0d4a2a72e096151f0d6ebd03bf51e2ae1048759cbc4c",
+    "sources_sha256": "aff03796165d1326d1f8f4adff1e29fefea9abf261aa08c7238715e1b5d1c18d",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
-    "mp2a": {"fetch_bytes": 32548570, "write_bytes": 12684816,
+    "mp2a": {"fetch_bytes": 32512431, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
     # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
-    "beyond_cache": {"fetch_bytes": 369954750, "write_bytes": 100890469,
+    "beyond_cache": {"fetch_bytes": 369718158, "write_bytes": 100890373,
                      "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
     # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
-    "batch64": {"fetch_bytes": 908633408, "write_bytes": 198098210,
+    "batch64": {"fetch_bytes": 908594866, "write_bytes": 198098197,
                 "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
 

@@ -90,6 +90,8 @@ struct Vec {
 };
 
 template <typename T> void launch_apply(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> y);
+// Level 0 (lop.level == 0): x = xs widened to FP64, and y = A_s x, in one pass.
+void launch_apply_widened(const LaunchCtx&, const LevelOp<double>& lop, Vec<float> xs, Vec<double> x, Vec<double> y);
 template <typename T> void launch_residual(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> r);
 template <typename T>
 void launch_jacobi(const LaunchCtx&, const LevelOp<T>&, Vec<T> x, Vec<T> f, Vec<T> y, double inv_omega);
@@ -296,7 +298,6 @@ int launch_kry_first(const LaunchCtx&, Grid g, const cplx<double>* r, cplx<doubl
 // x += sum_{i < nz} y[b * ystride + i] Z_i.
 void launch_kry_update(const LaunchCtx&, Grid g, const cplx<double>* Z, long long zstride, int nz,
                        const cplx<double>* y, int ystride, cplx<double>* x, long long plane);
-void launch_kry_cast_up(const LaunchCtx&, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane);
 
 // ---- setup ----
 // Validity of the caller's dense k^2 array (n+1)^2: flags[0] |= 1 (non-finite),

@@ -1,9 +1,10 @@
 // Level-0 vector kernels of the outer flexible GMRES(m) (§1: multigrid on the
 // CSL as a preconditioner for GMRES): classical Gram-Schmidt in two sweeps
 // (all inner products <v_i, w> in one pass over w, then w -= sum h_i v_i),
-// normalisation, the update x += Z y, precision casts of whole planes and
-// the first basis vector r / ||r||. FP64 data, [b][plane] per vector, the
-// Krylov vectors [j][b][plane].
+// normalisation, the update x += Z y and the first basis vector r / ||r||
+// (the complex64 copies of the basis vectors for FP32 preconditioner cycles
+// included). FP64 data, [b][plane] per vector, the Krylov vectors
+// [j][b][plane].
 #include "hm_ops.hpp"
 
 namespace hm {
@@ -176,16 +177,6 @@ __global__ __launch_bounds__(kBX * kBY) void k_kry_update(Grid g, const cplx<dou
     });
 }
 
-template <typename S, typename D>
-__global__ __launch_bounds__(kBX * kBY) void k_kry_cast(Grid g, const cplx<S>* src, cplx<D>* dst, long long plane,
-                                                       const int* active, int rpt) {
-    const int b = blockIdx.z;
-    if (!rhs_active(active, b)) return;
-    const cplx<S>* sb = src + b * plane;
-    cplx<D>* db = dst + b * plane;
-    for_nodes(g, rpt, [&](int, int, long long p) { db[p] = cast<D>(sb[p]); });
-}
-
 struct KGeom {
     dim3 grid, block;
     int rpt, nblk;
@@ -247,12 +238,6 @@ void launch_kry_update(const LaunchCtx& ctx, Grid g, const cplx<double>* Z, long
     const KGeom q = kgeom(ctx, g);
     hipLaunchKernelGGL(k_kry_update, q.grid, q.block, 0, ctx.stream, g, Z, zstride, nz, y, ystride, x, plane,
                        ctx.active, q.rpt);
-}
-
-void launch_kry_cast_up(const LaunchCtx& ctx, Grid g, const cplx<float>* src, cplx<double>* dst, long long plane) {
-    const KGeom q = kgeom(ctx, g);
-    hipLaunchKernelGGL((k_kry_cast<float, double>), q.grid, q.block, 0, ctx.stream, g, src, dst, plane, ctx.active,
-                       q.rpt);
 }
 
 }  // namespace hm

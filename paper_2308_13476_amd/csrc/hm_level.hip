@@ -398,6 +398,26 @@ __global__ __launch_bounds__(kBX * BY) void k_apply(Op op, Vec<T> x, Vec<T> y, c
                              });
 }
 
+// y = A_s x on level 0 with x the complex64 plane xs widened to FP64, which is
+// written to x as well (the outer FGMRES keeps the FP32 cycle's result as its
+// FP64 vector z_j and applies the operator to it: one pass instead of two).
+template <int BY>
+__global__ __launch_bounds__(kBX * BY) void k_apply_widened(FineOp<double> op, Vec<float> xs, Vec<double> x,
+                                                            Vec<double> y, const int* active, int rpt) {
+    const int b = blockIdx.z;
+    if (!rhs_active(active, b)) return;
+    const cplx<float>* sb = xs.rhs(b);
+    cplx<double>* xb = x.rhs(b);
+    cplx<double>* yb = y.rhs(b);
+    for_nodes_applied_pre<FineOp<double>, double>(
+        op, rpt, [sb](long long q) { return sb[q]; }, [](cplx<float> v) { return cast<double>(v); },
+        [](long long) { return NoVals{}; },
+        [&](int, int, long long p, NoVals, cplx<double> xv, cplx<double> ax) {
+            xb[p] = xv;
+            yb[p] = ax;
+        });
+}
+
 template <typename Op, typename T, int BY>
 __global__ __launch_bounds__(kBX * BY) void k_residual(Op op, Vec<T> x, Vec<T> f, Vec<T> r, const int* active,
                                                        int rpt) {
@@ -1786,6 +1806,15 @@ void launch_apply(const LaunchCtx& ctx, const LevelOp<T>& lop, Vec<T> x, Vec<T> 
         const Geom q = geom_op<Op, T>(lop.g, ctx);
         HM_LAUNCH_OP(q, (k_apply<Op, T, BY>), op, x, y, HM_ACTIVE, q.rpt);
     });
+}
+
+void launch_apply_widened(const LaunchCtx& ctx, const LevelOp<double>& lop, Vec<float> xs, Vec<double> x,
+                          Vec<double> y) {
+    using Op = FineOp<double>;
+    using T = double;
+    const Op op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
+    const Geom q = geom_op<Op, T>(lop.g, ctx);
+    HM_LAUNCH_OP(q, (k_apply_widened<BY>), op, xs, x, y, HM_ACTIVE, q.rpt);
 }
 
 template <typename T>

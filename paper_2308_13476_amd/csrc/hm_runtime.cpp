@@ -1628,9 +1628,12 @@ mg_status mg_solve_fgmres(mg_handle c, const void* rhs, void* x, int nrhs, doubl
             cplx<double>* zj = K.Z + j * K.vstride;
             if (!fp32) HM_HIP(hipMemcpyAsync(l0.f64, vj, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
             if (mg_status st = run_cycle_graph(c, s, key, precond_body)) return st;
-            if (fp32) launch_kry_cast_up(lc, g0, l0.u32, zj, pl);
-            else HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
-            launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
+            if (fp32) {
+                launch_apply_widened(lc, op0, vec<float>(l0.u32, l0), vec<double>(zj, l0), vec<double>(K.Wv, l0));
+            } else {
+                HM_HIP(hipMemcpyAsync(zj, l0.u64, size_t(pl) * nrhs * 16, hipMemcpyDeviceToDevice, s));
+                launch_apply<double>(lc, op0, vec<double>(zj, l0), vec<double>(K.Wv, l0));
+            }
             launch_kry_orthogonalise(lc, g0, K.V, K.vstride, j, K.Wv, K.H, m + 1, pl, fp32 ? l0.f32 : nullptr,
                                      z32);
             if (mg_status st = check_launch(c)) return st;
