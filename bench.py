@@ -58,15 +58,15 @@ CLASS1_FP32_K2_BYTES = 4.0
 TRAFFIC_SOURCES = ["paper_2308_13476_amd/csrc/hm_level.hip", "paper_2308_13476_amd/csrc/hm_ops.hpp",
                    "paper_2308_13476_amd/csrc/hm_common.hpp", "paper_2308_13476_amd/csrc/hm_kernels.hpp"]
 MEASURED_TRAFFIC = {
-    "sources_sha256": "aff03796165d1326d1f8f4adff1e29fefea9abf261aa08c7238715e1b5d1c18d",
+    "sources_sha256": "732caa4287a4d51b95c76c1481e5ed21ab1a24977b0e2e55076b26ecf54778bf",
     # k_gm_oa<FineOp<float>, float, 2, 4> at n = 1024 (headline workload)
-    "mp2a": {"fetch_bytes": 32512431, "write_bytes": 12684816,
+    "mp2a": {"fetch_bytes": 32481573, "write_bytes": 12684816,
              "profile": "profiles/fp32_cycle_level0_n1024_hbm_traffic.md"},
     # k_gm_oa<FineOp<double>, double, 2, 4> at n = 2048 (working set beyond the Infinity Cache)
-    "beyond_cache": {"fetch_bytes": 369718158, "write_bytes": 100890373,
+    "beyond_cache": {"fetch_bytes": 369740140, "write_bytes": 100889850,
                      "profile": "profiles/fp64_level0_n2048_hbm_traffic.md"},
     # k_gm_oa<FineOp<float>, float, 2, 4>, 64 right-hand sides on n = 512
-    "batch64": {"fetch_bytes": 908594866, "write_bytes": 198098197,
+    "batch64": {"fetch_bytes": 908578802, "write_bytes": 198098200,
                 "profile": "profiles/batch64_n512_hbm_traffic.md"},
 }
 

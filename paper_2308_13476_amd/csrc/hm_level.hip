@@ -2132,9 +2132,25 @@ void launch_norm(const LaunchCtx& ctx, Grid g, Vec<T> f, RhsNorms* norms) {
     launch_sum_norms(ctx, q.nblk, norms, 0);
 }
 
+namespace {
+// The fused refinement residual + apply pass takes the level's operator
+// geometry with the rows per thread lowered until its two LDS stages fit (the
+// taller tiles of batch handles do not): it hands its partial sums to the
+// next pass with their own block count.
+Geom refine_apply_geom(const LaunchCtx& ctx, Grid g) {
+    Geom q = geom_op<FineOp<double>, double>(g, ctx);
+    if (RefineApplyStage<double>::bytes(q.by * q.rpt) > kMaxTileBytes) {
+        while (q.rpt > 1 && RefineApplyStage<double>::bytes(q.by * q.rpt) > kMaxTileBytes) --q.rpt;
+        q.grid = level_grid(g, q.rpt, ctx.nrhs, q.by, ctx.nrhs_cap > 1);
+        q.nblk = int(q.grid.x * q.grid.y);
+    }
+    return q;
+}
+}  // namespace
+
 bool refine_apply_fits(const LaunchCtx& ctx, Grid g) {
-    const Geom q = geom_op<FineOp<double>, double>(g, ctx);
-    return RefineApplyStage<double>::bytes(q.by * q.rpt) <= kMaxTileBytes;
+    const Geom q = refine_apply_geom(ctx, g);
+    return RefineApplyStage<double>::bytes(q.by * q.rpt) <= kMaxTileBytes && q.nblk <= kMaxPartialBlocks;
 }
 
 namespace {
@@ -2144,7 +2160,7 @@ template <bool kCorrect>
 int launch_residual_apply(const LaunchCtx& ctx, const LevelOp<double>& lop, const float* k2_32, Vec<double> x_in,
                           Vec<float> e, Vec<double> x_out, Vec<double> f, Vec<float> r32, RhsNorms* norms,
                           Vec<float> z0, Vec<float> w0) {
-    const Geom q = geom_op<FineOp<double>, double>(lop.g, ctx);
+    const Geom q = refine_apply_geom(ctx, lop.g);
     const FineOp<double> op{lop.g, lop.k2, 1.0 / (lop.h * lop.h), 2.0 / lop.h};
     const FineOp<float> op32{lop.g, k2_32, float(1.0 / (lop.h * lop.h)), float(2.0 / lop.h)};
     const size_t shm = RefineApplyStage<double>::bytes(q.by * q.rpt);

@@ -394,8 +394,11 @@ def test_fused_correction_and_apply(monkeypatch, transfer, n, env, nb):
 
 
 @pytest.mark.parametrize("n,env,nb,x0", [(128, {}, 1, False), (96, {}, 1, True), (256, {"HELMG_MAX_BLOCKS": "64"}, 1, False),
-                                         (128, {}, 3, True), (64, {"HELMG_DEFER_UPDATE": "0"}, 1, False)],
-                         ids=["n128", "n96_x0", "n256_cap64", "n128_batch3_x0", "n64_no_deferral"])
+                                         (128, {}, 3, True), (64, {"HELMG_DEFER_UPDATE": "0"}, 1, False),
+                                         (512, {"HELMG_MAX_BLOCKS": "64"}, 1, False),
+                                         (512, {"HELMG_MAX_BLOCKS": "64"}, 2, True)],
+                         ids=["n128", "n96_x0", "n256_cap64", "n128_batch3_x0", "n64_no_deferral",
+                              "n512_cap64_lowered_rows", "n512_cap64_batch2_lowered_rows"])
 def test_fused_refinement_residual_and_apply(monkeypatch, n, env, nb, x0):
     """FP32-refined solves whose FP64 residual pass before each FP32 cycle also
     forms the first product A z_0 of the cycle's first GMRES step (x staged with
@@ -406,7 +409,9 @@ def test_fused_refinement_residual_and_apply(monkeypatch, n, env, nb, x0):
     both meet the tolerance in the oracle's FP64 residual. V(1,1) (the first
     step is also the one that restricts), W(2,2) and V(2,1); a ragged grid (96
     intervals), pre-reduced partial sums (block cap 64), a batch handle, a
-    nonzero start and no deferred coarse update."""
+    nonzero start and no deferred coarse update; on 512 intervals with block
+    cap 64 the level's tiles are too tall for the pass's LDS stages, which
+    then runs with fewer rows per block than the level's other passes."""
     require_gpu()
     import torch
     from paper_2308_13476_amd.solver import Solver
